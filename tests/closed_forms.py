@@ -1,0 +1,39 @@
+"""Closed-form references used to pin the oracle (scipy / mpmath as black boxes).
+
+Mie series for a penetrable circular cylinder (Sec. 7.1, eq. (2dom_anal)).
+The paper leaves a_n, b_n to the transmission conditions (2.2)-(2.3); with
+c_n = i^n e^{-i n theta_inc} the incident coefficients, x0 = k0 R, x1 = k1 R and
+tau = k1 / (eps k0) = k0 / k1 for eps = (k1/k0)^2:
+    a_n = -c_n [J_n'(x0) J_n(x1) - tau J_n(x0) J_n'(x1)]
+              / [H_n'(x0) J_n(x1) - tau H_n(x0) J_n'(x1)],
+and the far field of the scattered part with u_sc ~ e^{i k0 r}/sqrt(r) F:
+    F(theta) = sqrt(2/(pi k0)) e^{-i pi/4} sum_n a_n (-i)^n e^{i n theta}.
+"""
+import numpy as np
+import scipy.special as sp
+
+
+def mie_coefficients(k0, k1, R, theta_inc, nmax=30):
+    x0, x1 = k0 * R, k1 * R
+    tau = k0 / k1
+    ns = np.arange(-nmax, nmax + 1)
+    c = (1j ** ns) * np.exp(-1j * ns * theta_inc)
+    J0, J0p = sp.jv(ns, x0), sp.jvp(ns, x0)
+    H0, H0p = sp.hankel1(ns, x0), sp.h1vp(ns, x0)
+    J1, J1p = sp.jv(ns, x1), sp.jvp(ns, x1)
+    a = -c * (J0p * J1 - tau * J0 * J1p) / (H0p * J1 - tau * H0 * J1p)
+    b = (c * J0 + a * H0) / J1
+    return ns, a, b
+
+
+def mie_farfield(k0, k1, R, theta_inc, dirs, nmax=30):
+    ns, a, _ = mie_coefficients(k0, k1, R, theta_inc, nmax)
+    dirs = np.asarray(dirs, dtype=np.float64)
+    F = (a[None, :] * ((-1j) ** ns)[None, :] * np.exp(1j * np.outer(dirs, ns))).sum(axis=1)
+    return np.sqrt(2.0 / (np.pi * k0)) * np.exp(-1j * np.pi / 4) * F
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))

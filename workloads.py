@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs for the collocation BEM of arXiv 2312.12787.
+
+This module only produces INPUTS: boundary polylines, wavenumbers, incident
+angles, solver settings and request streams.  It holds none of the method's
+arithmetic (no element geometry, kernels, quadrature or solves), so the CPU
+oracle and the HIP path can both take their inputs from here without sharing
+any of the computation.
+
+Orientation convention used by every generator: an interface's normal is the
+LEFT normal of its direction of travel.  It points INTO ``dom_left`` and OUT
+of ``dom_right``.  The host medium is domain 0 and must be a ``dom_right``
+(Sec. 2: the normal is directed from the host medium; Sec. 6: for the
+multi-material sketch the normals point into Omega_2).  A counter-clockwise
+outer boundary therefore has ``dom_left`` = scatterer, ``dom_right`` = 0.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+CALDERON = 0          # eq. (calderon_bieb) beta=-alpha / eq. (3dom_calderon_bie)
+CALDERON_BETA1 = 1    # eq. (calderon_bie1)
+CONVENTIONAL = 2      # eq. (naive_bie) / eq. (3dom_conv_bie)
+CALDERON_ORIG = 3     # eq. (3dom_calderon_bie0)
+
+
+@dataclass
+class Interface:
+    xy: np.ndarray            # (n_nodes, 2) float64 node coordinates
+    closed: bool              # closed curve: last element joins node n-1 to node 0
+    dom_left: int             # domain the normal points into
+    dom_right: int            # domain the normal leaves
+
+
+@dataclass
+class ProblemSpec:
+    k: List[complex]                      # wavenumber of each domain; k[0] real > 0
+    interfaces: List[Interface]
+    quad: int = 8                         # Gauss-Legendre points per element
+    form: int = CALDERON
+    alpha: Optional[complex] = None       # None: -i/k0
+    beta: Optional[complex] = None        # None: -alpha (Calderon forms) or 1
+    bm_coef: Optional[List[complex]] = None  # None: alpha/eps_d per domain
+    name: str = ""
+
+    @property
+    def n_elements(self) -> int:
+        return sum(len(f.xy) if f.closed else len(f.xy) - 1 for f in self.interfaces)
+
+    @property
+    def order(self) -> int:
+        return 2 * self.n_elements
+
+    # flat arrays in the layout both C interfaces take
+    def flat(self):
+        k = np.array([[complex(v).real, complex(v).imag] for v in self.k], dtype=np.float64).ravel()
+        n_nodes = np.array([len(f.xy) for f in self.interfaces], dtype=np.int32)
+        closed = np.array([1 if f.closed else 0 for f in self.interfaces], dtype=np.int32)
+        xy = np.ascontiguousarray(np.concatenate([np.asarray(f.xy, np.float64) for f in self.interfaces]).ravel())
+        dl = np.array([f.dom_left for f in self.interfaces], dtype=np.int32)
+        dr = np.array([f.dom_right for f in self.interfaces], dtype=np.int32)
+        return k, n_nodes, closed, xy, dl, dr
+
+
+# --------------------------------------------------------------------------
+# boundary curves
+# --------------------------------------------------------------------------
+def circle_nodes(n: int, radius: float = 1.0, clockwise: bool = False, center=(0.0, 0.0)) -> np.ndarray:
+    """Inscribed regular n-gon, vertex 0 at angle 0 (Sec. 7: the unit circle is
+    approximated by its inscribed polygon)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    if clockwise:
+        t = -t
+    return np.stack([center[0] + radius * np.cos(t), center[1] + radius * np.sin(t)], axis=1)
+
+
+def kite_nodes(n: int) -> np.ndarray:
+    """Kite x(t) = (cos t + 0.65 cos 2t - 0.65, 1.5 sin t) at t_j = 2 pi j / n (CCW)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    return np.stack([np.cos(t) + 0.65 * np.cos(2 * t) - 0.65, 1.5 * np.sin(t)], axis=1)
+
+
+def perturbed_circle_nodes(n: int, amps: Sequence[float], phases: Sequence[float]) -> np.ndarray:
+    """r(t) = 1 + sum_{m=2..6} a_m cos(m t + phi_m) at t_j = 2 pi j / n (CCW)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    r = np.ones_like(t)
+    for m, (a, p) in enumerate(zip(amps, phases), start=2):
+        r += a * np.cos(m * t + p)
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+def square_nodes(per_side: int, side: float = 1.0) -> np.ndarray:
+    """Square of the given side, centred at 0, ``per_side`` equal elements per
+    side, CCW starting at the lower-left corner (Sec. 4 check)."""
+    h = side / per_side
+    s = side / 2.0
+    pts = []
+    for i in range(per_side):
+        pts.append((-s + i * h, -s))
+    for i in range(per_side):
+        pts.append((s, -s + i * h))
+    for i in range(per_side):
+        pts.append((s - i * h, s))
+    for i in range(per_side):
+        pts.append((-s, s - i * h))
+    return np.array(pts, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# problems
+# --------------------------------------------------------------------------
+def single_material(nodes: np.ndarray, k0: float, k1: complex, quad: int = 8, form: int = CALDERON,
+                    name: str = "", **kw) -> ProblemSpec:
+    """A scatterer (domain 1) bounded by the CCW closed curve ``nodes`` in the
+    host medium (domain 0)."""
+    return ProblemSpec(k=[complex(k0), complex(k1)],
+                       interfaces=[Interface(np.asarray(nodes, np.float64), True, 1, 0)],
+                       quad=quad, form=form, name=name, **kw)
+
+
+def disk(n: int, k0: float, k1: complex, radius: float = 1.0, **kw) -> ProblemSpec:
+    return single_material(circle_nodes(n, radius), k0, k1, name=f"disk{n}", **kw)
+
+
+def kite(n: int, k0: float, k1: complex, **kw) -> ProblemSpec:
+    return single_material(kite_nodes(n), k0, k1, name=f"kite{n}", **kw)
+
+
+def concentric(n_outer: int, n_inner: int, k: Sequence[complex], r_outer: float = 2.0,
+               r_inner: float = 1.0, quad: int = 8, form: int = CALDERON) -> ProblemSpec:
+    """Concentric disks (Sec. 7.2): Omega_2 = annulus (domain 1), Omega_3 =
+    inner disk (domain 2).  Normals point into Omega_2 on both circles, so the
+    inner circle is traversed clockwise."""
+    outer = Interface(circle_nodes(n_outer, r_outer), True, 1, 0)
+    inner = Interface(circle_nodes(n_inner, r_inner, clockwise=True), True, 1, 2)
+    return ProblemSpec(k=[complex(v) for v in k], interfaces=[outer, inner], quad=quad, form=form,
+                       name=f"concentric{n_outer}+{n_inner}")
+
+
+def equispaced_angles(n: int) -> np.ndarray:
+    return 2.0 * np.pi * np.arange(n) / n
+
+
+# --------------------------------------------------------------------------
+# the benchmark workloads
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    problems: List[ProblemSpec]
+    angles: np.ndarray
+    restart: int
+    tol: float
+    far_dirs: np.ndarray = field(default_factory=lambda: equispaced_angles(360))
+
+
+def workload_disk256() -> Workload:
+    """Unit disk as a 256-gon, k0 = 1, k1 = 2, 8-point Gauss, angle 0, GMRES(50), 1e-10."""
+    return Workload("disk256_k1-2", [disk(256, 1.0, 2.0)], np.array([0.0]), 50, 1e-10)
+
+
+def workload_kite4096(n: int = 4096) -> Workload:
+    """Kite with N = 4096 elements (8192 x 8192 complex128), k0 = 20 with
+    k1 = 30 and with lossy k1 = 30 + 0.3i, 16 equispaced incident angles,
+    GMRES(100) to 1e-10."""
+    return Workload(f"kite{n}_k20-30_x16", [kite(n, 20.0, 30.0), kite(n, 20.0, 30.0 + 0.3j)],
+                    equispaced_angles(16), 100, 1e-10)
+
+
+def workload_kite16384_fp32(n: int = 16384) -> Workload:
+    return Workload(f"kite{n}_k20-30_x64", [kite(n, 20.0, 30.0)], equispaced_angles(64), 100, 1e-6)
+
+
+def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0):
+    """Served-path request stream: Poisson arrivals, Fourier-perturbed circles,
+    N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32 angles."""
+    ss = np.random.SeedSequence(seed)
+    rng_t = np.random.default_rng(ss.spawn(1)[0])
+    gaps = rng_t.exponential(1.0 / rate, size=n_requests)
+    t = np.cumsum(gaps)
+    out = []
+    for i, child in enumerate(ss.spawn(n_requests)):
+        rng = np.random.default_rng(child)
+        amps = rng.uniform(0.0, 0.08, size=5)
+        phases = rng.uniform(0.0, 2 * np.pi, size=5)
+        n = int(round(math.exp(rng.uniform(math.log(512), math.log(8192)))))
+        k0 = float(rng.uniform(1.0, 50.0))
+        ratio = float(rng.uniform(1.2, 3.0))
+        nrhs = int(rng.integers(1, 33))
+        angles = rng.uniform(0.0, 2 * np.pi, size=nrhs)
+        spec = single_material(perturbed_circle_nodes(n, amps, phases), k0, k0 * ratio,
+                               name=f"req{i}")
+        out.append(dict(arrival=float(t[i]), spec=spec, angles=angles))
+    return out
