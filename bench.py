@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload (default): the kite x(t) = (cos t + 0.65 cos 2t - 0.65, 1.5 sin t)
+with N = 4096 elements (8192 x 8192 complex128 system), host wavenumber
+k0 = 20 and two interior cases, k1 = 30 and lossy k1 = 30 + 0.3i, 16
+equispaced plane-wave angles solved as one block by GMRES(100) to a relative
+residual of 1e-10, far field at 360 directions; everything in FP64.
+
+One step = both cases, each: derive the geometry tables on the device,
+assemble the matrix, build the 16 right-hand sides, solve, evaluate the far
+field.  The inputs (node coordinates) are uploaded once before the timed
+region.  value = solved right-hand sides per second over the K timed steps.
+
+Also reported: p50/p99 latency of one case (16 solves), the assembly rate, and
+the roofline record of the dominant kernel measured with the library's HIP
+events on the solve stream, plus the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload kite4096|disk256]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solves/s + p50/p99 latency at 1e-6 rel. err vs FP64; assembly FLOP/s, matvec GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_record(kernel_src):
+    """HBM traffic of the product kernel from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "matvec_traffic_kite4096.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != source_sha(kernel_src):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, gpu_iters, rows_per_case=48):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    rows_per_case strided matrix rows of each case and one full-size product;
+    scaled to full assembly (rows x n) plus the product count the GPU solve
+    needed (sum of GMRES iterations and restart residuals)."""
+    import oracle as O
+    t_total = 0.0
+    spent = 0.0
+    for spec, iters in zip(workload.problems, gpu_iters):
+        P = O.Problem(spec)
+        n = P.n
+        rows = np.linspace(0, n - 1, rows_per_case).round().astype(np.int32)
+        t0 = time.perf_counter()
+        P.assemble_rows(rows)
+        t_rows = time.perf_counter() - t0
+        A = np.zeros((n, n), dtype=np.complex128, order="F")
+        x = np.ones(n, dtype=np.complex128)
+        t0 = time.perf_counter()
+        O.matvec(A, x)
+        t_mv = time.perf_counter() - t0
+        del A
+        spent += t_rows + t_mv
+        t_total += t_rows / rows_per_case * n + iters * t_mv
+    solves = len(workload.problems) * len(workload.angles)
+    return {"value": solves / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{rows_per_case} strided rows per case assembled by the oracle and one full-size "
+                       f"oracle product, scaled to {workload.problems[0].order} rows and to the "
+                       f"{sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation, about "
+                       f"1% of a product here, not modelled); {spent:.1f} s of CPU work")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2312_12787_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.workload_kite4096() if args.workload == "kite4096" else W.workload_disk256()
+    dirs = wl.far_dirs
+    stream = torch.cuda.current_stream()
+    probs, mats = [], []
+    for spec in wl.problems:
+        g = P.Problem(spec)
+        g.geometry()  # uploads the inputs (nodes, plan) once
+        mats.append(torch.empty((g.n, g.n), dtype=torch.complex128, device="cuda"))
+        _, _, wb = g.sizes(P.F64, len(wl.angles), wl.restart)
+        g._workspace(wb)
+        probs.append(g)
+    torch.cuda.synchronize()
+
+    lat = []
+    iters = [0] * len(probs)
+    products = [0] * len(probs)
+    infos = []
+    nr = len(wl.angles)
+
+    def step(record):
+        for ci, (g, A) in enumerate(zip(probs, mats)):
+            t0 = time.perf_counter()
+            g.geometry_update()
+            g.assemble(P.F64, out=A)
+            B = g.rhs(wl.angles)
+            X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000)
+            F = g.farfield(X, dirs)
+            torch.cuda.synchronize()
+            if record:
+                lat.append(time.perf_counter() - t0)
+                iters[ci] += int(info.iters.sum())
+                # products a one-right-hand-side-at-a-time solver needs: one per
+                # Arnoldi step plus one residual per cycle
+                products[ci] += int(info.iters.sum() + info.restarts.sum()) + nr
+                infos.append(info)
+            if not info.converged.all():
+                raise RuntimeError(f"case {ci} did not converge: {info}")
+            del F
+
+    for _ in range(args.warmup):
+        step(False)
+    for g in probs:
+        g.profile(True)
+        g.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    prof = [g.profile_read(reset=True) for g in probs]
+    for g in probs:
+        g.profile(False)
+
+    n = probs[0].n
+    N = probs[0].N
+    q = wl.problems[0].quad
+    solves = args.steps * len(probs) * nr
+    mv_launch = sum(p["matvec_launches"] for p in prof)
+    mv_ms = sum(p["matvec_ms"] for p in prof)
+    as_launch = sum(p["assemble_launches"] for p in prof)
+    as_ms = sum(p["assemble_ms"] for p in prof)
+    mv_bytes = 16.0 * n * n + 2 * 16.0 * n * nr  # matrix + X + Y per launch (algorithmic)
+    mv_avg_ms = mv_ms / max(1, mv_launch)
+    mv_gbs = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
+    as_avg_ms = as_ms / max(1, as_launch)
+    evals = 2.0 * N * (N - 1) * q  # (H0, H1) pairs at Gauss points, both wavenumbers
+    kernel_src = os.path.join(ROOT, "paper_2312_12787_amd", "csrc", "linalg.hip")
+    traffic = traffic_record(kernel_src)
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": solves / T,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "elements": N, "system_order": n, "cases": [str(s.k[1]) for s in wl.problems],
+                   "k0": float(np.real(wl.problems[0].k[0])), "rhs_per_case": nr, "restart": wl.restart,
+                   "tol": wl.tol, "quad": q, "far_field_dirs": len(dirs), "solves_per_step": len(probs) * nr},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "unit": "one case: geometry tables + assembly + 16 solves + far field"},
+        "gmres_iterations_per_rhs": [it / (args.steps * nr) for it in iters],
+        "assembly": {"launches": as_launch, "avg_ms": as_avg_ms,
+                     "evals_per_s": evals / (as_avg_ms * 1e-3) if as_launch else None},
+        "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs,
+                   "share_of_step_time": mv_ms / (T * 1e3)},
+        "roofline": {"kernel": "k_matvec_mfma (FP64 MFMA split-K block product, 16 right-hand sides)", "bound": "hbm",
+                     "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl, [p // args.steps for p in products])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * bem.h -- C ABI of the MI355X (gfx950) hot path of the collocation boundary
+ * element method for 2-D Helmholtz transmission problems of Matsumoto,
+ * Yoshiki and Isakari, "Automatically well-conditioned collocation boundary
+ * element method for transmission problems based on the Burton-Miller
+ * formulation" (arXiv 2312.12787).
+ *
+ * The library assembles the dense complex collocation matrix of the
+ * Calderon-ordered Burton-Miller system on the GPU and solves it with
+ * restarted GMRES whose dense matrix-vector products, Arnoldi projections,
+ * norms and Givens updates all run in HIP kernels.
+ *
+ * Conventions shared by every call (paper Sec. 2, Sec. 3.3, Sec. 6):
+ *   - time factor exp(-i w t); fundamental solution G_k(r) = (i/4) H0^(1)(k r);
+ *   - domain 0 is the unbounded host medium, k[0] real and > 0; every other
+ *     domain d has a wavenumber with Im k[d] >= 0 and eps_d = (k[d]/k[0])^2;
+ *   - an interface is a polyline of nodes; element e joins node e to node e+1
+ *     (a closed interface also joins its last node to its first); the unit
+ *     normal of an element is the LEFT normal of its direction of travel and
+ *     points INTO domain dom_left and OUT of domain dom_right; the host
+ *     medium must be a dom_right (the normal leaves the host medium, Sec. 2);
+ *   - constant elements, collocation at element midpoints, q-point
+ *     Gauss-Legendre quadrature off the diagonal, analytic self terms (Sec. 7);
+ *   - N_tot = total number of elements; the system order is n = 2 N_tot;
+ *     unknowns are [u on every element ; w = (1/eps) du/dn on every element];
+ *     for the Calderon forms the standard-type equations fill rows [0, N_tot)
+ *     and the Burton-Miller-type ones rows [N_tot, n), both in element order
+ *     (closing recipe of Sec. 6);
+ *   - every matrix and vector on the device is column-major; complex numbers
+ *     are interleaved (re, im) pairs: complex128 for BEM_F64, complex64 for
+ *     BEM_F32;
+ *   - the library never allocates device memory: the caller passes every
+ *     device buffer (sizes from bem_sizes) and owns it; pointers named *_dev
+ *     are device pointers, all others are host pointers;
+ *   - all device work of a call is ordered on the caller's stream; calls that
+ *     return data to the host (bem_solve) synchronise that stream;
+ *   - errors are returned as status codes; bem_last_error() gives a message
+ *     for the calling thread.  No call aborts or throws.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stddef.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_problem bem_problem;
+
+typedef struct {
+    double re, im;
+} bem_z;
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_E_ARG = 1,       /* an argument is out of range or inconsistent            */
+    BEM_E_GEOMETRY = 2,  /* invalid boundary description                          */
+    BEM_E_STATE = 3,     /* call order violated (e.g. matvec before assemble)      */
+    BEM_E_DEVICE = 4,    /* a HIP call failed; message in bem_last_error()         */
+    BEM_E_NOMEM = 5,     /* a caller buffer is smaller than bem_sizes asked for    */
+    BEM_E_NOCONV = 6,    /* GMRES stopped at max_iter; X holds the last iterate   */
+    BEM_E_NONFINITE = 7  /* NaN or Inf met in a residual                           */
+} bem_status;
+
+typedef enum { BEM_F64 = 0, BEM_F32 = 1 } bem_prec;
+
+/* Formulation presets.
+ *   BEM_CALDERON       eq. (calderon_bieb) with beta = -alpha for one inclusion,
+ *                      eq. (3dom_calderon_bie) with gamma_d = alpha/eps_d for
+ *                      several (the recipe closing Sec. 6).  Default.
+ *   BEM_CALDERON_BETA1 eq. (calderon_bie1) (beta = 1).
+ *   BEM_CONVENTIONAL   eq. (naive_bie) / eq. (3dom_conv_bie): equations listed
+ *                      domain by domain, host medium first, unscaled.
+ *   BEM_CALDERON_ORIG  eq. (3dom_calderon_bie0): only the host medium uses the
+ *                      Burton-Miller equation.                                   */
+typedef enum {
+    BEM_CALDERON = 0,
+    BEM_CALDERON_BETA1 = 1,
+    BEM_CONVENTIONAL = 2,
+    BEM_CALDERON_ORIG = 3
+} bem_form;
+
+/* Problem statement (Sec. 2): domains with their wavenumbers, interfaces
+ * between them, and the coupling constants of the Burton-Miller equations.
+ * All pointers are host pointers, read during bem_create only.              */
+typedef struct {
+    int n_dom;              /* number of domains, >= 2                                  */
+    const bem_z *k;         /* [n_dom] wavenumbers; k[0] real > 0; Im k[d] >= 0         */
+    int n_if;               /* number of interfaces, >= 1                               */
+    const int *n_nodes;     /* [n_if] nodes of each interface                           */
+    const int *closed;      /* [n_if] 1: closed curve (>= 3 nodes), 0: open (>= 2 nodes) */
+    const double *xy;       /* [2 * sum(n_nodes)] node coordinates (x, y), interface by interface */
+    const int *dom_left;    /* [n_if] domain the normal points into (never 0)           */
+    const int *dom_right;   /* [n_if] domain the normal leaves                          */
+    int quad;               /* Gauss-Legendre points per element, 1..16 (8 or 10 usual) */
+    int form;               /* bem_form                                                 */
+    const bem_z *alpha;     /* NULL: -i / k[0] (Sec. 3.3)                               */
+    const bem_z *beta;      /* NULL: -alpha for BEM_CALDERON / BEM_CALDERON_ORIG, else 1 */
+    const bem_z *bm_coef;   /* [n_dom] or NULL: Burton-Miller coefficient alpha/eps_d   */
+} bem_desc;
+
+/* Validate a problem statement and build its host-side plan (element and row
+ * bookkeeping).  No device work.  On success *out owns the plan; free it with
+ * bem_destroy.  BEM_E_GEOMETRY: too few nodes, a zero-length element, an
+ * unknown or repeated domain id, the host medium on the normal's side, or
+ * |1 + eps_left/eps_right| < 1e-12 (accumulation point at 0, end of Sec. 5).
+ * BEM_E_ARG: k[0] not real-positive, Im k < 0, quad out of range.           */
+bem_status bem_create(const bem_desc *desc, bem_problem **out);
+void bem_destroy(bem_problem *p);
+
+/* Number of elements N_tot and system order n = 2 N_tot. */
+int bem_n_elements(const bem_problem *p);
+int bem_order(const bem_problem *p);
+
+/* Byte sizes of the caller-owned device buffers:
+ *   geom_bytes   geometry / quadrature / constant tables (bem_geometry),
+ *   matrix_bytes the n x n matrix at lda = n in precision prec,
+ *   work_bytes   workspace of bem_matvec, bem_solve and bem_farfield for up to
+ *                nrhs right-hand sides, GMRES restart length `restart` and up
+ *                to 4096 far-field directions.  Any pointer may be NULL.     */
+bem_status bem_sizes(const bem_problem *p, int prec, int nrhs, int restart, size_t *geom_bytes,
+                     size_t *matrix_bytes, size_t *work_bytes);
+
+/* Step (boundary -> element tables), Sec. 4 and Sec. 7: upload the nodes and
+ * the plan into geom_dev and compute on the device the element table
+ * (end nodes, midpoint, tangent, left normal, length), the Gauss-Legendre
+ * rule, the Gauss points of every element, the per-domain constants (eps,
+ * Burton-Miller coefficients, Hankel-function tables) and the analytic
+ * self terms.  geom_dev must stay alive (and unmodified) until the problem is
+ * destroyed or bem_geometry is called again.                                 */
+bem_status bem_geometry(bem_problem *p, void *geom_dev, size_t geom_bytes, hipStream_t stream);
+
+/* Recompute every derived device table of bem_geometry (element table, Gauss
+ * rule and points, per-domain constants, self terms) from the inputs already
+ * uploaded into geom_dev, with no host-to-device copy and no synchronisation.
+ * Invalidates the recorded matrix (bem_assemble must run again).            */
+bem_status bem_geometry_update(bem_problem *p, hipStream_t stream);
+
+/* Assemble the n x n system matrix (eqs. (stmp)-(ddtmp), (fundamental_sol),
+ * the block systems of Secs. 3-6) into A_dev with leading dimension lda >= n,
+ * in precision prec (BEM_F64: complex128; BEM_F32: complex64 entries, with
+ * self terms computed in FP64 and rounded).  Requires bem_geometry.  The
+ * problem records A_dev, lda and prec for bem_matvec / bem_solve.           */
+bem_status bem_assemble(bem_problem *p, int prec, void *A_dev, size_t lda, hipStream_t stream);
+
+/* Right-hand sides of the plane waves exp(i k0 (cos th, sin th) . x), one per
+ * angle (host array angles[nang]): u_in + alpha q_in on the rows of the host
+ * medium's Burton-Miller equation, 0 elsewhere (eq. (calderon_bieb)).  B_dev
+ * is complex128, n x nang, leading dimension ldb >= n.                      */
+bem_status bem_rhs(const bem_problem *p, int nang, const double *angles, void *B_dev, size_t ldb,
+                   hipStream_t stream);
+
+/* Y = A X for nrhs columns (the dense products of GMRES, Sec. 3.2).  X and Y
+ * have the precision of the assembled matrix (complex128 for BEM_F64,
+ * complex64 for BEM_F32), leading dimensions ldx, ldy >= n.  work_dev holds
+ * split-K partial sums (bem_sizes with this nrhs).                          */
+bem_status bem_matvec(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev,
+                      size_t ldy, void *work_dev, size_t work_bytes, hipStream_t stream);
+
+typedef struct {
+    int restart;        /* GMRES restart length m (>= 1)                                  */
+    int max_iter;       /* cap on matrix-vector products per right-hand side            */
+    double tol;         /* stop when ||b - A x|| <= tol ||b|| (true residual, FP64)      */
+    double inner_tol;   /* BEM_F32 matrix only: relative tolerance of each inner solve;
+                           0 selects 1e-5                                               */
+    int max_refine;     /* BEM_F32 matrix only: cap on FP64 refinement steps; 0 -> 20    */
+} bem_solve_opts;
+
+typedef struct {
+    int iters;          /* matrix-vector products spent on this right-hand side         */
+    int restarts;       /* restart cycles (FP64) or refinement steps (BEM_F32 matrix)     */
+    int converged;      /* 1 if the true relative residual reached tol                   */
+    double rel_residual;/* final true relative residual ||b - A x|| / ||b||              */
+} bem_solve_info;
+
+/* Solve A X = B for nrhs right-hand sides (complex128, n x nrhs, ldb >= n) by
+ * GMRES(restart) started from X = 0 (Sec. 3.2: the Krylov space of A itself,
+ * no preconditioner applied).  The right-hand sides share every matrix pass
+ * (block products); their Krylov spaces are independent.  With an FP64
+ * matrix the Arnoldi process is classical Gram-Schmidt with one
+ * re-orthogonalisation; with an FP32 matrix (bem_assemble(BEM_F32)) the
+ * inner GMRES runs FP32 products and FP64 Arnoldi, and an outer FP64
+ * iterative refinement recomputes r = b - A x with FP64 accumulation until
+ * tol.  X_dev is complex128 (ldx >= n) and is overwritten.  info is a host
+ * array [nrhs].  Returns BEM_E_NOCONV if any column missed tol.            */
+bem_status bem_solve(bem_problem *p, int nrhs, const void *B_dev, size_t ldb, const bem_solve_opts *opts,
+                     void *X_dev, size_t ldx, void *work_dev, size_t work_bytes, bem_solve_info *info,
+                     hipStream_t stream);
+
+/* Far-field pattern of the scattered field in the host medium for nrhs
+ * solutions (complex128 X_dev, ldx >= n): u_sc ~ e^{i k0 |x|} / sqrt|x| F,
+ *   F(th) = e^{i pi/4} / sqrt(8 pi k0) sum_j sigma_j [w_j + i k0 (xh.n_j) u_j]
+ *           h_j e^{-i k0 xh.c_j} sinc(k0 h_j xh.t_j / 2)
+ * over the elements of the host medium's boundary (sigma_j = +1 when the
+ * normal leaves the host medium).  dirs: host array of ndir <= 4096 angles.
+ * F_dev complex128, ndir x nrhs, ldf >= ndir.                               */
+bem_status bem_farfield(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, int ndir,
+                        const double *dirs, void *F_dev, size_t ldf, void *work_dev, size_t work_bytes,
+                        hipStream_t stream);
+
+/* Kernel timing for measurement.  While enabled, the library records HIP
+ * events on the caller's stream immediately before and after the main kernel
+ * of every assembly (the fused block-assembly kernel) and every dense product
+ * (the split-K product kernel, not its small reduction pass), including the
+ * products inside bem_solve.  bem_profile_read waits for the recorded events,
+ * returns the launch counts and summed durations, and with reset != 0 starts
+ * a new tally.  Host event objects are created by the library as needed and
+ * released by bem_destroy; no device memory is used.                        */
+typedef struct {
+    int assemble_launches;
+    double assemble_ms;
+    int matvec_launches;
+    double matvec_ms;
+} bem_profile;
+bem_status bem_profile_enable(bem_problem *p, int on);
+bem_status bem_profile_read(bem_problem *p, bem_profile *out, int reset);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char *bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

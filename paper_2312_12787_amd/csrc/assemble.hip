@@ -1,0 +1,522 @@
+// assemble.hip -- setup kernels (element table, Gauss rule, per-domain
+// constants, self terms) and the fused assembly of the collocation matrix
+// of the Calderon-ordered Burton-Miller system (Secs. 3-7 of arXiv 2312.12787).
+#include <hip/hip_runtime.h>
+
+#include "hankel_dev.h"
+#include "hankel_tables.h"
+#include "internal.h"
+#include "launch.h"
+
+namespace bemk {
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double EULER = 0.57721566490153286061;
+
+template <class T>
+__device__ __forceinline__ const T* tab(const char* g, size_t off) { return reinterpret_cast<const T*>(g + off); }
+template <class T>
+__device__ __forceinline__ T* tabw(char* g, size_t off) { return reinterpret_cast<T*>(g + off); }
+
+__device__ __forceinline__ cd cdiv(cd a, cd b)
+{
+    const double den = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+__device__ __forceinline__ cd csqrt_(cd z)
+{
+    const double r = hypot(z.re, z.im);
+    double sr = sqrt(0.5 * (r + fabs(z.re)));
+    if (sr == 0.0) return {0.0, 0.0};
+    if (z.re >= 0.0) return {sr, z.im / (2.0 * sr)};
+    return {fabs(z.im) / (2.0 * sr), z.im >= 0.0 ? sr : -sr};
+}
+__device__ __forceinline__ cd clog_(cd z) { return {log(hypot(z.re, z.im)), atan2(z.im, z.re)}; }
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rule on [-1, 1] (Sec. 7).  One lane per node: Newton's
+// method on P_q with P_q, P_q' from the three-term recurrence.
+// ---------------------------------------------------------------------------
+__global__ void k_gauss_rule(int q, double* gl)
+{
+    const int i = threadIdx.x;
+    if (i >= q) return;
+    double x = cos(PI * (4.0 * i + 3.0) / (4.0 * q + 2.0));
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int n = 2; n <= q; ++n) {
+            const double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double pq = (q == 1) ? x : p1;
+        const double pqm1 = (q == 1) ? 1.0 : p0;
+        dp = q * (pqm1 - x * pq) / (1.0 - x * x);
+        const double dx = pq / dp;
+        x -= dx;
+        if (fabs(dx) < 1e-17) break;
+    }
+    // recompute the derivative at the converged node
+    double p0 = 1.0, p1 = x;
+    for (int n = 2; n <= q; ++n) {
+        const double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+        p0 = p1;
+        p1 = p2;
+    }
+    const double pq = (q == 1) ? x : p1, pqm1 = (q == 1) ? 1.0 : p0;
+    dp = q * (pqm1 - x * pq) / (1.0 - x * x);
+    // node i counted from the right end: store in ascending order
+    gl[q - 1 - i] = x;
+    gl[QMAX + q - 1 - i] = 2.0 / ((1.0 - x * x) * dp * dp);
+}
+
+// ---------------------------------------------------------------------------
+// Element table and the Gauss points of every element (Secs. 4, 7).
+// ---------------------------------------------------------------------------
+__global__ void k_elements(char* g, GeomLayout L, int N, int q)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N) return;
+    const double2* nodes = tab<double2>(g, L.nodes);
+    const int2 ab = tab<int2>(g, L.elnodes)[e];
+    const double* gl = tab<double>(g, L.gl);
+    const double2 a = nodes[ab.x], b = nodes[ab.y];
+    ElemRec E;
+    E.ax = a.x;
+    E.ay = a.y;
+    E.bx = b.x;
+    E.by = b.y;
+    E.cx = 0.5 * (a.x + b.x);
+    E.cy = 0.5 * (a.y + b.y);
+    const double dx = b.x - a.x, dy = b.y - a.y;
+    E.h = sqrt(dx * dx + dy * dy);
+    E.tx = dx / E.h;
+    E.ty = dy / E.h;
+    E.nx = -E.ty;
+    E.ny = E.tx;
+    for (int k = 0; k < 5; ++k) E.pad[k] = 0.0;
+    tabw<ElemRec>(g, L.elem)[e] = E;
+    GaussRec G;
+    GaussRec32 G32;
+    for (int k = 0; k < QMAX; ++k) {
+        if (k < q) {
+            const double s = 0.5 * E.h * gl[k];
+            G.x[k] = E.cx + s * E.tx;
+            G.y[k] = E.cy + s * E.ty;
+            G.w[k] = 0.5 * E.h * gl[QMAX + k];
+        } else {
+            G.x[k] = G.y[k] = G.w[k] = 0.0;
+        }
+        G32.x[k] = (float)G.x[k];
+        G32.y[k] = (float)G.y[k];
+        G32.w[k] = (float)G.w[k];
+    }
+    tabw<GaussRec>(g, L.gauss)[e] = G;
+    tabw<GaussRec32>(g, L.gauss32)[e] = G32;
+}
+
+// ---------------------------------------------------------------------------
+// Per-domain constants: eps_d = (k_d/k_0)^2 (Sec. 2), the Burton-Miller
+// coefficient alpha/eps_d (Sec. 6 recipe), the row scaling beta (Sec. 5) and
+// the Hankel tables of the wavenumber.
+// ---------------------------------------------------------------------------
+__device__ void build_wave(cd k, WaveConst& W)
+{
+    const double ak = hypot(k.re, k.im);
+    W.kr = k.re;
+    W.ki = k.im;
+    W.r2_small = (HANKEL_XS_F64 / ak) * (HANKEL_XS_F64 / ak);
+    const cd xk = cdiv({HANKEL_XS_F64, 0.0}, k);  // XS / k
+    W.ur = xk.re;
+    W.ui = xk.im;
+    const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));  // sqrt(2/(pi k))
+    const double c4 = 0.70710678118654752440;
+    W.a0r = sq.re * c4 + sq.im * c4;  // * e^{-i pi/4} = (1 - i)/sqrt2
+    W.a0i = sq.im * c4 - sq.re * c4;
+    W.a1r = -sq.re * c4 + sq.im * c4;  // * e^{-3 i pi/4} = (-1 - i)/sqrt2
+    W.a1i = -sq.im * c4 - sq.re * c4;
+    const cd lk = clog_(cscale(k, 0.5));
+    W.lk0r = (2.0 / PI) * (lk.re + EULER);
+    W.lk0i = (2.0 / PI) * lk.im;
+    W.lk1r = (2.0 / PI) * lk.re;
+    W.lk1i = (2.0 / PI) * lk.im;
+    const cd y1 = cdiv({-2.0 / PI, 0.0}, k);
+    W.y1r = y1.re;
+    W.y1i = y1.im;
+    // amplitude polynomials: a_m w^m with w = (XS/k)^2 rho
+    const cd w1 = cmul(xk, xk);
+    cd pw = {1.0, 0.0};
+    for (int m = 0; m < NAMP; ++m) {
+        W.m0r[m] = HANKEL_M0_F64[m] * pw.re;
+        W.m0i[m] = HANKEL_M0_F64[m] * pw.im;
+        W.n0r[m] = HANKEL_N0_F64[m] * pw.re;
+        W.n0i[m] = HANKEL_N0_F64[m] * pw.im;
+        W.m1r[m] = HANKEL_M1_F64[m] * pw.re;
+        W.m1i[m] = HANKEL_M1_F64[m] * pw.im;
+        W.n1r[m] = HANKEL_N1_F64[m] * pw.re;
+        W.n1i[m] = HANKEL_N1_F64[m] * pw.im;
+        pw = cmul(pw, w1);
+    }
+    // ascending series: t = -k^2/4
+    const cd t = cscale(cmul(k, k), -0.25);
+    cd c0 = {1.0, 0.0};                  // (-k^2/4)^m / (m!)^2
+    cd c1 = cscale(k, 0.5);              // (k/2) (-k^2/4)^m / (m! (m+1)!)
+    double hm = 0.0;                     // harmonic number H_m
+    for (int m = 0; m < NSER; ++m) {
+        if (m > 0) {
+            c0 = cscale(cmul(c0, t), 1.0 / ((double)m * m));
+            c1 = cscale(cmul(c1, t), 1.0 / ((double)m * (m + 1)));
+            hm += 1.0 / m;
+        }
+        W.j0r[m] = c0.re;
+        W.j0i[m] = c0.im;
+        // Y0 remainder: -(2/pi) H_m c0_m  (m >= 1)
+        W.e0r[m] = (m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.re;
+        W.e0i[m] = (m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.im;
+        W.j1r[m] = c1.re;
+        W.j1i[m] = c1.im;
+        // Y1 remainder: -(1/pi)(psi(m+1) + psi(m+2)) c1_m, psi(m+1) = H_m - gamma
+        const double ps = (hm - EULER) + (hm + 1.0 / (m + 1) - EULER);
+        W.e1r[m] = -(1.0 / PI) * ps * c1.re;
+        W.e1i[m] = -(1.0 / PI) * ps * c1.im;
+    }
+}
+
+__device__ void build_wave32(cd k, WaveConst32& W)
+{
+    const double ak = hypot(k.re, k.im);
+    W.kr = (float)k.re;
+    W.ki = (float)k.im;
+    W.r2_small = (float)((HANKEL_XS_F32 / ak) * (HANKEL_XS_F32 / ak));
+    const cd xk = cdiv({HANKEL_XS_F32, 0.0}, k);
+    W.ur = (float)xk.re;
+    W.ui = (float)xk.im;
+    const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));
+    const double c4 = 0.70710678118654752440;
+    W.a0r = (float)(sq.re * c4 + sq.im * c4);
+    W.a0i = (float)(sq.im * c4 - sq.re * c4);
+    W.a1r = (float)(-sq.re * c4 + sq.im * c4);
+    W.a1i = (float)(-sq.im * c4 - sq.re * c4);
+    const cd lk = clog_(cscale(k, 0.5));
+    W.lk0r = (float)((2.0 / PI) * (lk.re + EULER));
+    W.lk0i = (float)((2.0 / PI) * lk.im);
+    W.lk1r = (float)((2.0 / PI) * lk.re);
+    W.lk1i = (float)((2.0 / PI) * lk.im);
+    const cd y1 = cdiv({-2.0 / PI, 0.0}, k);
+    W.y1r = (float)y1.re;
+    W.y1i = (float)y1.im;
+    const cd w1 = cmul(xk, xk);
+    cd pw = {1.0, 0.0};
+    for (int m = 0; m < NAMP32; ++m) {
+        W.m0r[m] = (float)(HANKEL_M0_F32[m] * pw.re);
+        W.m0i[m] = (float)(HANKEL_M0_F32[m] * pw.im);
+        W.n0r[m] = (float)(HANKEL_N0_F32[m] * pw.re);
+        W.n0i[m] = (float)(HANKEL_N0_F32[m] * pw.im);
+        W.m1r[m] = (float)(HANKEL_M1_F32[m] * pw.re);
+        W.m1i[m] = (float)(HANKEL_M1_F32[m] * pw.im);
+        W.n1r[m] = (float)(HANKEL_N1_F32[m] * pw.re);
+        W.n1i[m] = (float)(HANKEL_N1_F32[m] * pw.im);
+        pw = cmul(pw, w1);
+    }
+    const cd t = cscale(cmul(k, k), -0.25);
+    cd c0 = {1.0, 0.0}, c1 = cscale(k, 0.5);
+    double hm = 0.0;
+    for (int m = 0; m < NSER32; ++m) {
+        if (m > 0) {
+            c0 = cscale(cmul(c0, t), 1.0 / ((double)m * m));
+            c1 = cscale(cmul(c1, t), 1.0 / ((double)m * (m + 1)));
+            hm += 1.0 / m;
+        }
+        W.j0r[m] = (float)c0.re;
+        W.j0i[m] = (float)c0.im;
+        W.e0r[m] = (float)((m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.re);
+        W.e0i[m] = (float)((m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.im);
+        W.j1r[m] = (float)c1.re;
+        W.j1i[m] = (float)c1.im;
+        const double ps = (hm - EULER) + (hm + 1.0 / (m + 1) - EULER);
+        W.e1r[m] = (float)(-(1.0 / PI) * ps * c1.re);
+        W.e1i[m] = (float)(-(1.0 / PI) * ps * c1.im);
+    }
+}
+
+__global__ void k_domains(char* g, GeomLayout L)
+{
+    const int d = threadIdx.x;
+    const GlobalIn G = *tab<GlobalIn>(g, L.glob_in);
+    if (d >= G.n_dom) return;
+    const DomIn* in = tab<DomIn>(g, L.dom_in);
+    const cd k0 = {in[0].k[0], in[0].k[1]};
+    const cd k = {in[d].k[0], in[d].k[1]};
+    const cd r = cdiv(k, k0);
+    const cd eps = cmul(r, r);
+    // alpha = -i / k0 (Sec. 3.3) unless given
+    const cd alpha = G.has_alpha ? cd{G.alpha[0], G.alpha[1]} : cdiv({0.0, -1.0}, k0);
+    cd beta;
+    if (G.has_beta)
+        beta = {G.beta[0], G.beta[1]};
+    else if (G.form == 0 || G.form == 3)
+        beta = {-alpha.re, -alpha.im};
+    else
+        beta = {1.0, 0.0};
+    const cd c = in[d].has_bm ? cd{in[d].bm[0], in[d].bm[1]} : cdiv(alpha, eps);
+    DomConst D;
+    D.k[0] = k.re;
+    D.k[1] = k.im;
+    D.eps[0] = eps.re;
+    D.eps[1] = eps.im;
+    D.c[0] = c.re;
+    D.c[1] = c.im;
+    D.beta[0] = beta.re;
+    D.beta[1] = beta.im;
+    D.cplx = (k.im != 0.0);
+    D.pad = 0;
+    tabw<DomConst>(g, L.dom)[d] = D;
+    build_wave(k, tabw<WaveConst>(g, L.wave)[d]);
+    build_wave32(k, tabw<WaveConst32>(g, L.wave32)[d]);
+}
+
+// ---------------------------------------------------------------------------
+// Self term of the single-layer operator on a flat element at its midpoint
+// (Sec. 7, the weak singularity): S_ii = (i/(2k)) int_0^{kh/2} H0(t) dt, the
+// integral taken term by term from the ascending series of J0 and Y0.
+// One lane per (element, domain on either side of it).
+// ---------------------------------------------------------------------------
+__device__ cd int_h0(cd z)
+{
+    const cd zh = cscale(z, 0.5);
+    const cd q = cmul(zh, zh);
+    const cd lz = clog_(zh);
+    cd T = cscale(zh, 2.0);  // 2 (z/2)^{2m+1} (-1)^m / (m!)^2
+    cd sj = {0.0, 0.0}, sj2 = {0.0, 0.0}, sh = {0.0, 0.0};
+    double hm = 0.0;
+    for (int m = 0; m < 200; ++m) {
+        if (m > 0) {
+            T = cscale(cmul(T, q), -1.0 / ((double)m * m));
+            hm += 1.0 / m;
+        }
+        const double o = 2.0 * m + 1.0;
+        const cd a = cscale(T, 1.0 / o);
+        sj = cadd(sj, a);
+        sj2 = cadd(sj2, cscale(T, 1.0 / (o * o)));
+        sh = cadd(sh, cscale(a, hm));
+        if (m > 3 && hypot(a.re, a.im) < 1e-18 * hypot(sj.re, sj.im)) break;
+    }
+    // int Y0 = (2/pi) [ (ln(z/2) + gamma) sum T/(2m+1) - sum T/(2m+1)^2 - sum H_m T/(2m+1) ]
+    const cd ly = cmul({lz.re + EULER, lz.im}, sj);
+    const cd iy = cscale({ly.re - sj2.re - sh.re, ly.im - sj2.im - sh.im}, 2.0 / PI);
+    return {sj.re - iy.im, sj.im + iy.re};  // int J0 + i int Y0
+}
+
+__global__ void k_self_terms(char* g, GeomLayout L, int N, int n_dom)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N) return;
+    const ElemRec E = tab<ElemRec>(g, L.elem)[e];
+    const int iface = tab<int>(g, L.elif)[e];
+    const IfacePlan P = tab<IfacePlan>(g, L.iface)[iface];
+    const DomConst* D = tab<DomConst>(g, L.dom);
+    double2* S = tabw<double2>(g, L.self);
+    for (int side = 0; side < 2; ++side) {
+        const int d = side ? P.dr : P.dl;
+        const cd k = {D[d].k[0], D[d].k[1]};
+        const cd I = int_h0(cscale(k, 0.5 * E.h));
+        const cd pre = cdiv({0.0, 0.5}, k);  // i / (2k)
+        const cd s = cmul(pre, I);
+        S[(size_t)d * N + e] = make_double2(s.re, s.im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused assembly of one equation block (one side of an interface) against the
+// elements of one interface.  Operators (eqs. (stmp)-(ddtmp)) of domain d
+// between collocation point x_i and element j:
+//   S  = (i/4)   sum_g w_g H0(k r_g)
+//   D  = (ik/4)  sum_g w_g H1(k r_g) (r_g . n_j)/r_g
+//   D* = -(ik/4) sum_g w_g H1(k r_g) (r_g . n_i)/r_g
+//   N  = k^2 (n_i.n_j) S + (ik/4)[E(b_j) - E(a_j)],  E(p) = H1(k|x_i-p|) t_i.(x_i-p)/|x_i-p|
+// (N by the identity d2G/dnx dny = k^2 (nx.ny) G - d2G/dtx dty, exact on a
+// flat element; E at the shared end nodes is carried from element to element).
+// Block entries (sigma = +1 if the normal leaves domain d, eps = eps_d):
+//   standard row, scale s:  A[row, u_j] = s (delta/2 + sigma D),   A[row, w_j] = -s sigma eps S
+//   Burton-Miller row, c:   A[row, u_j] = delta/2 + sigma (D + c N),
+//                           A[row, w_j] = -sigma eps S + c (eps delta/2 - sigma eps D*)
+// One lane per collocation row; the wave walks the source elements of its
+// chunk in order (wave-uniform element data, coalesced column-major stores).
+// ---------------------------------------------------------------------------
+template <int Q, bool CPLX, bool BM>
+__device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, const GaussRec* __restrict__ gq,
+                                              const WaveConst& W, const DomConst& Dm, int sg, int i,
+                                              const ElemRec& Ei, int j0, int cnt, int q_rt, cd selfS,
+                                              double2* __restrict__ A, size_t lda, size_t row, int N)
+{
+    const int q = Q > 0 ? Q : q_rt;
+    const cd k = {Dm.k[0], Dm.k[1]};
+    const cd ik4 = {-0.25 * k.im, 0.25 * k.re};     // i k / 4
+    const cd eps = {Dm.eps[0], Dm.eps[1]};
+    const cd c = {Dm.c[0], Dm.c[1]};
+    const cd beta = {Dm.beta[0], Dm.beta[1]};
+    const double s = (double)sg;
+    // per-block combination constants
+    const cd cD = BM ? cd{s * ik4.re, s * ik4.im} : cscale(cmul(beta, ik4), s);  // multiplies sum D
+    const cd iq = {0.0, 0.25};
+    cd cS = cscale(cmul(eps, iq), -s);  // multiplies sum S (w column)
+    if (!BM) cS = cmul(cS, beta);
+    const cd cDs = cscale(cmul(cmul(c, eps), ik4), s);    // multiplies sum D* (note the minus signs cancel)
+    const cd cNS = cscale(cmul(cmul(c, cmul(k, k)), iq), s);  // k^2 (n_i.n_j) S part of c sigma N
+    const cd cNE = cscale(cmul(c, ik4), s);                   // end-point part of c sigma N
+    const cd du = BM ? cd{0.5, 0.0} : cscale(beta, 0.5);      // jump term, u column
+    const cd dw = cscale(cmul(c, eps), 0.5);                  // jump term, w column (BM only)
+
+    const double xi = Ei.cx, yi = Ei.cy;
+    cd Ea = {0.0, 0.0};
+    if (BM) {
+        const ElemRec& E0 = el[j0];
+        const double dx = xi - E0.ax, dy = yi - E0.ay;
+        const double r2 = dx * dx + dy * dy;
+        const double r = sqrt(r2), rinv = 1.0 / r, sr = sqrt(rinv);
+        const cd h1 = hankel1_only<CPLX>(W, r, r2, rinv, sr);
+        Ea = cscale(h1, (Ei.tx * dx + Ei.ty * dy) * rinv);
+    }
+    for (int jj = 0; jj < cnt; ++jj) {
+        const int j = j0 + jj;
+        const ElemRec& Ej = el[j];
+        cd sS = {0.0, 0.0}, sD = {0.0, 0.0}, sDs = {0.0, 0.0};
+        const bool diag = (j == i);
+        if (!diag) {
+            const GaussRec& G = gq[j];
+#pragma unroll
+            for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
+                if (Q == 0 && g >= q) break;
+                const double rx = xi - G.x[g], ry = yi - G.y[g];
+                const double r2 = fma(rx, rx, ry * ry);
+                const double r = sqrt(r2);
+                const double rinv = 1.0 / r;
+                const double sr = sqrt(rinv);
+                cd h0, h1;
+                hankel01<CPLX>(W, r, r2, rinv, sr, h0, h1);
+                const double wg = G.w[g];
+                sS.re = fma(wg, h0.re, sS.re);
+                sS.im = fma(wg, h0.im, sS.im);
+                const double wd = wg * (rx * Ej.nx + ry * Ej.ny) * rinv;
+                sD.re = fma(wd, h1.re, sD.re);
+                sD.im = fma(wd, h1.im, sD.im);
+                if (BM) {
+                    const double ws = wg * (rx * Ei.nx + ry * Ei.ny) * rinv;
+                    sDs.re = fma(ws, h1.re, sDs.re);
+                    sDs.im = fma(ws, h1.im, sDs.im);
+                }
+            }
+        }
+        cd au, aw;
+        if (!diag) {
+            au = cmul(cD, sD);
+            aw = cmul(cS, sS);
+        } else {
+            // self term: D = D* = 0 on a flat element, S analytic; sS carries S / (i/4)
+            const cd s4 = cdiv(selfS, iq);
+            sS = s4;
+            au = du;
+            aw = cmul(cS, sS);
+            if (BM) aw = cadd(aw, dw);
+        }
+        if (BM) {
+            const double dxb = xi - Ej.bx, dyb = yi - Ej.by;
+            const double r2 = dxb * dxb + dyb * dyb;
+            const double r = sqrt(r2), rinv = 1.0 / r, sr = sqrt(rinv);
+            const cd h1 = hankel1_only<CPLX>(W, r, r2, rinv, sr);
+            const cd Eb = cscale(h1, (Ei.tx * dxb + Ei.ty * dyb) * rinv);
+            const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
+            au = cadd(au, cadd(cscale(cmul(cNS, sS), ninj), cmul(cNE, {Eb.re - Ea.re, Eb.im - Ea.im})));
+            aw = cadd(aw, cmul(cDs, sDs));
+            Ea = Eb;
+        }
+        A[row + (size_t)j * lda] = make_double2(au.re, au.im);
+        A[row + (size_t)(N + j) * lda] = make_double2(aw.re, aw.im);
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(ROW_TILE) void k_assemble_f64(const char* __restrict__ g, GeomLayout L, int N,
+                                                            int n_if, int q_rt, double2* __restrict__ A,
+                                                            size_t lda)
+{
+    const Tile rt = tab<Tile>(g, L.rtiles)[blockIdx.x];
+    const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
+    const int side = blockIdx.z;
+    const int li = threadIdx.x;
+    if (li >= rt.count) return;
+    const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
+    const int d = side ? P.dr : P.dl;
+    const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
+    const bool bm = side ? (P.bm_r != 0) : false;
+    const int i = rt.start + li;
+    const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
+    if (sg == 0) {
+        for (int jj = 0; jj < cc.count; ++jj) {
+            const int j = cc.start + jj;
+            A[row + (size_t)j * lda] = make_double2(0.0, 0.0);
+            A[row + (size_t)(N + j) * lda] = make_double2(0.0, 0.0);
+        }
+        return;
+    }
+    const ElemRec* el = tab<ElemRec>(g, L.elem);
+    const GaussRec* gq = tab<GaussRec>(g, L.gauss);
+    const WaveConst& W = tab<WaveConst>(g, L.wave)[d];
+    const DomConst Dm = tab<DomConst>(g, L.dom)[d];
+    const ElemRec Ei = el[i];
+    cd selfS = {0.0, 0.0};
+    if (i >= cc.start && i < cc.start + cc.count) {
+        const double2 s = tab<double2>(g, L.self)[(size_t)d * N + i];
+        selfS = {s.x, s.y};
+    }
+    if (bm) {
+        if (Dm.cplx)
+            assemble_side<Q, true, true>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+        else
+            assemble_side<Q, false, true>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+    } else {
+        if (Dm.cplx)
+            assemble_side<Q, true, false>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+        else
+            assemble_side<Q, false, false>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauss_rule, dim3(1), dim3(64), 0, s, q, reinterpret_cast<double*>(g + L.gl));
+    hipLaunchKernelGGL(k_domains, dim3(1), dim3(64), 0, s, g, L);
+    hipLaunchKernelGGL(k_elements, dim3((N + 255) / 256), dim3(256), 0, s, g, L, N, q);
+    hipLaunchKernelGGL(k_self_terms, dim3((N + 63) / 64), dim3(64), 0, s, g, L, N, n_dom);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
+                               int q, double2* A, size_t lda, hipStream_t s)
+{
+    dim3 grid(n_rtiles, n_cchunks, 2);
+    if (q == 8)
+        hipLaunchKernelGGL(k_assemble_f64<8>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    else if (q == 10)
+        hipLaunchKernelGGL(k_assemble_f64<10>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    else
+        hipLaunchKernelGGL(k_assemble_f64<0>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    return hipGetLastError();
+}
+
+}  // namespace bemk
+
+namespace bemk {
+hipError_t launch_assemble_f32(const char*, const GeomLayout&, int, int, int, int, int, float2*, size_t, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+}  // namespace bemk

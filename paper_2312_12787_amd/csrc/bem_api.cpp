@@ -1,0 +1,791 @@
+// bem_api.cpp -- host runtime behind the C ABI of include/bem.h.
+//
+// Host work is validation and integer bookkeeping (element ranges, equation
+// blocks, tiles, buffer offsets) plus the control flow of GMRES; every step
+// of the numerical method runs in the gfx950 kernels (assemble.hip,
+// linalg.hip).  The library never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+#include "internal.h"
+#include "launch.h"
+
+using bemk::GeomLayout;
+using bemk::IfacePlan;
+using bemk::Tile;
+
+namespace {
+
+thread_local std::string g_err;
+
+bem_status fail(bem_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+bem_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(BEM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OK(call)                                           \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);      \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// HIP-event timing of the main kernels (bem_profile_enable / bem_profile_read).
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    hipEvent_t pending[2] = {nullptr, nullptr};
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    hipError_t err = hipSuccess;
+};
+
+void prof_cb(void* ctx, int kind, int phase, hipStream_t s)
+{
+    Prof* P = static_cast<Prof*>(ctx);
+    if (!P->on) return;
+    if (P->used == P->pool.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            P->err = r;
+            return;
+        }
+        P->pool.push_back(e);
+    }
+    hipEvent_t e = P->pool[P->used++];
+    hipError_t r = hipEventRecord(e, s);
+    if (r != hipSuccess) P->err = r;
+    if (phase == 0)
+        P->pending[kind] = e;
+    else if (P->pending[kind])
+        P->recs.push_back({kind, P->pending[kind], e});
+}
+
+struct bem_problem {
+    mutable Prof prof;
+    bemk::KernelHook hook{prof_cb, nullptr};
+    const bemk::KernelHook* hk() const { return prof.on ? &hook : nullptr; }
+    int n_dom = 0, n_if = 0, N = 0, quad = 8, form = 0;
+    std::vector<std::complex<double>> k;
+    std::vector<int> dl, dr, n_nodes, closed;
+    std::vector<double> xy;
+    std::vector<IfacePlan> iface;
+    std::vector<int> sigma;        // [d * n_if + m]
+    std::vector<Tile> rtiles, cchunks;
+    std::vector<int> elif;          // interface of each element
+    std::vector<int> elnodes;       // (a, b) node indices per element
+    bemk::DomIn dummy{};
+    std::vector<bemk::DomIn> dom_in;
+    bemk::GlobalIn glob{};
+    GeomLayout L{};
+    // device state recorded by the calls
+    char* geom = nullptr;
+    void* A = nullptr;
+    size_t lda = 0;
+    int prec = -1;
+};
+
+namespace {
+
+int sigma_of(const bem_problem* p, int d, int m)
+{
+    if (p->dr[m] == d) return 1;
+    if (p->dl[m] == d) return -1;
+    return 0;
+}
+
+GeomLayout make_layout(const bem_problem* p)
+{
+    GeomLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    size_t nn = p->xy.size() / 2;
+    L.nodes = take(nn * sizeof(double2));
+    L.elnodes = take((size_t)p->N * sizeof(int2));
+    L.elif = take((size_t)p->N * sizeof(int));
+    L.iface = take((size_t)p->n_if * sizeof(IfacePlan));
+    L.rtiles = take(p->rtiles.size() * sizeof(Tile));
+    L.cchunks = take(p->cchunks.size() * sizeof(Tile));
+    L.sigma = take((size_t)p->n_dom * p->n_if * sizeof(int));
+    L.dom_in = take((size_t)p->n_dom * sizeof(bemk::DomIn));
+    L.glob_in = take(sizeof(bemk::GlobalIn));
+    size_t upload_end = off;
+    (void)upload_end;
+    L.elem = take((size_t)p->N * sizeof(bemk::ElemRec));
+    L.gauss = take((size_t)p->N * sizeof(bemk::GaussRec));
+    L.gauss32 = take((size_t)p->N * sizeof(bemk::GaussRec32));
+    L.gl = take(2 * bemk::QMAX * sizeof(double));
+    L.dom = take((size_t)p->n_dom * sizeof(bemk::DomConst));
+    L.wave = take((size_t)p->n_dom * sizeof(bemk::WaveConst));
+    L.wave32 = take((size_t)p->n_dom * sizeof(bemk::WaveConst32));
+    L.self = take((size_t)p->n_dom * p->N * sizeof(double2));
+    L.total = off;
+    return L;
+}
+
+// Workspace of the solver and products (byte offsets into work_dev).
+struct WorkLayout {
+    size_t V, W, R, Ro, D, X32, W32, mv_part, dot_part, h1, h2, y, H, cs, sn, gvec, norm_part, hnorm, resid, rnorm,
+        bnorm, active, kdim, dirs, total;
+    int ldv, nblk, splits;
+};
+
+WorkLayout make_work(int n, int nr, int m)
+{
+    WorkLayout W{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    W.ldv = (n + 63) / 64 * 64;
+    W.nblk = (n + 255) / 256;
+    W.splits = bemk::matvec_splits(n);
+    const size_t vec = (size_t)W.ldv * nr * sizeof(double2);
+    W.V = take((size_t)(m + 1) * vec);
+    W.W = take(vec);
+    W.R = take(vec);
+    W.Ro = take(vec);
+    W.D = take(vec);
+    W.X32 = take((size_t)W.ldv * nr * sizeof(float2));
+    W.W32 = take((size_t)W.ldv * nr * sizeof(float2));
+    W.mv_part = take((size_t)W.splits * std::min(nr, 16) * n * sizeof(double2));
+    W.dot_part = take((size_t)nr * W.nblk * (m + 1) * sizeof(double2));
+    W.h1 = take((size_t)nr * 1024 * sizeof(double2));
+    W.h2 = take((size_t)nr * 1024 * sizeof(double2));
+    W.y = take((size_t)nr * 1024 * sizeof(double2));
+    W.H = take((size_t)nr * (m + 1) * m * sizeof(double2));
+    W.cs = take((size_t)nr * m * sizeof(double2));
+    W.sn = take((size_t)nr * m * sizeof(double2));
+    W.gvec = take((size_t)nr * (m + 1) * sizeof(double2));
+    W.norm_part = take((size_t)nr * std::max(W.nblk, 64) * sizeof(double));
+    W.hnorm = take((size_t)nr * sizeof(double));
+    W.resid = take((size_t)nr * sizeof(double));
+    W.rnorm = take((size_t)nr * sizeof(double));
+    W.bnorm = take((size_t)nr * sizeof(double));
+    W.active = take((size_t)nr * sizeof(int));
+    W.kdim = take((size_t)nr * sizeof(int));
+    W.dirs = take((size_t)bemk::MAX_DIRS * sizeof(double));
+    W.total = off;
+    return W;
+}
+
+bem_status check_problem(const bem_problem* p)
+{
+    if (!p) return fail(BEM_E_ARG, "null problem");
+    return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_err.c_str(); }
+
+bem_status bem_create(const bem_desc* desc, bem_problem** out)
+{
+    if (!desc || !out) return fail(BEM_E_ARG, "null argument");
+    *out = nullptr;
+    if (desc->n_dom < 2 || desc->n_dom > 64) return fail(BEM_E_ARG, "n_dom must be in [2, 64]");
+    if (desc->n_if < 1) return fail(BEM_E_ARG, "n_if must be >= 1");
+    if (desc->quad < 1 || desc->quad > bemk::QMAX) return fail(BEM_E_ARG, "quad must be in [1, 16]");
+    if (desc->form < 0 || desc->form > 3) return fail(BEM_E_ARG, "unknown form");
+    if (!desc->k || !desc->n_nodes || !desc->closed || !desc->xy || !desc->dom_left || !desc->dom_right)
+        return fail(BEM_E_ARG, "null array in the description");
+    auto p = new bem_problem();
+    p->hook.ctx = &p->prof;
+    p->n_dom = desc->n_dom;
+    p->n_if = desc->n_if;
+    p->quad = desc->quad;
+    p->form = desc->form;
+    for (int d = 0; d < p->n_dom; ++d) {
+        const std::complex<double> kd(desc->k[d].re, desc->k[d].im);
+        if (!std::isfinite(kd.real()) || !std::isfinite(kd.imag())) {
+            delete p;
+            return fail(BEM_E_ARG, "non-finite wavenumber");
+        }
+        if (d == 0 && !(kd.real() > 0.0 && kd.imag() == 0.0)) {
+            delete p;
+            return fail(BEM_E_ARG, "k[0] (host medium) must be real and positive");
+        }
+        if (kd.imag() < 0.0) {
+            delete p;
+            return fail(BEM_E_ARG, "Im k must be >= 0");
+        }
+        if (std::abs(kd) == 0.0) {
+            delete p;
+            return fail(BEM_E_ARG, "k must be nonzero");
+        }
+        p->k.push_back(kd);
+    }
+    int node0 = 0, total = 0;
+    for (int m = 0; m < p->n_if; ++m) {
+        const int nn = desc->n_nodes[m], cl = desc->closed[m] ? 1 : 0;
+        const int l = desc->dom_left[m], r = desc->dom_right[m];
+        if (l < 0 || l >= p->n_dom || r < 0 || r >= p->n_dom || l == r) {
+            delete p;
+            return fail(BEM_E_GEOMETRY, "interface " + std::to_string(m) + ": bad domain ids");
+        }
+        if (l == 0) {
+            delete p;
+            return fail(BEM_E_GEOMETRY, "interface " + std::to_string(m) +
+                                            ": the normal must leave the host medium (dom_right = 0)");
+        }
+        if (nn < (cl ? 3 : 2)) {
+            delete p;
+            return fail(BEM_E_GEOMETRY, "interface " + std::to_string(m) + ": too few nodes");
+        }
+        const int ne = cl ? nn : nn - 1;
+        IfacePlan P{};
+        P.off = total;
+        P.count = ne;
+        P.dl = l;
+        P.dr = r;
+        for (int e = 0; e < ne; ++e) {
+            const int a = node0 + e, b = node0 + (e + 1) % nn;
+            const double dx = desc->xy[2 * b] - desc->xy[2 * a], dy = desc->xy[2 * b + 1] - desc->xy[2 * a + 1];
+            if (!std::isfinite(dx) || !std::isfinite(dy) || dx * dx + dy * dy == 0.0) {
+                delete p;
+                return fail(BEM_E_GEOMETRY, "interface " + std::to_string(m) + ": zero-length or non-finite element " +
+                                                std::to_string(e));
+            }
+            p->elnodes.push_back(a);
+            p->elnodes.push_back(b);
+            p->elif.push_back(m);
+        }
+        p->iface.push_back(P);
+        p->n_nodes.push_back(nn);
+        p->closed.push_back(cl);
+        p->dl.push_back(l);
+        p->dr.push_back(r);
+        node0 += nn;
+        total += ne;
+    }
+    p->xy.assign(desc->xy, desc->xy + 2 * node0);
+    p->N = total;
+    // eps_left / eps_right = -1 puts the accumulation point at 0 (end of Sec. 5)
+    for (int m = 0; m < p->n_if; ++m) {
+        const auto el = (p->k[p->dl[m]] / p->k[0]) * (p->k[p->dl[m]] / p->k[0]);
+        const auto er = (p->k[p->dr[m]] / p->k[0]) * (p->k[p->dr[m]] / p->k[0]);
+        if (std::abs(1.0 + el / er) < 1e-12) {
+            delete p;
+            return fail(BEM_E_GEOMETRY, "eps_left / eps_right = -1 on interface " + std::to_string(m));
+        }
+    }
+    p->sigma.assign((size_t)p->n_dom * p->n_if, 0);
+    for (int d = 0; d < p->n_dom; ++d)
+        for (int m = 0; m < p->n_if; ++m) p->sigma[(size_t)d * p->n_if + m] = sigma_of(p, d, m);
+    // equation blocks
+    const int N = p->N;
+    if (p->form == BEM_CONVENTIONAL) {
+        // eq. (naive_bie) / (3dom_conv_bie): domain by domain, host medium first
+        int row = 0;
+        for (int d = 0; d < p->n_dom; ++d)
+            for (int m = 0; m < p->n_if; ++m) {
+                if (p->dr[m] == d) {
+                    p->iface[m].row_r = row;
+                    row += p->iface[m].count;
+                }
+                if (p->dl[m] == d) {
+                    p->iface[m].row_l = row;
+                    row += p->iface[m].count;
+                }
+            }
+        for (int m = 0; m < p->n_if; ++m) p->iface[m].bm_r = (p->dr[m] == 0);
+    } else {
+        // standard-type equations in the upper half, Burton-Miller ones in the lower
+        for (int m = 0; m < p->n_if; ++m) {
+            p->iface[m].row_l = p->iface[m].off;
+            p->iface[m].row_r = N + p->iface[m].off;
+            p->iface[m].bm_r = (p->form == BEM_CALDERON_ORIG) ? (p->dr[m] == 0) : 1;
+        }
+    }
+    for (int m = 0; m < p->n_if; ++m) {
+        const IfacePlan& P = p->iface[m];
+        for (int s = 0; s < P.count; s += bemk::ROW_TILE)
+            p->rtiles.push_back(Tile{m, P.off + s, std::min(bemk::ROW_TILE, P.count - s), 0});
+        for (int s = 0; s < P.count; s += bemk::COL_CHUNK)
+            p->cchunks.push_back(Tile{m, P.off + s, std::min(bemk::COL_CHUNK, P.count - s), 0});
+    }
+    // inputs for the device-side constant tables
+    p->dom_in.resize(p->n_dom);
+    for (int d = 0; d < p->n_dom; ++d) {
+        p->dom_in[d].k[0] = p->k[d].real();
+        p->dom_in[d].k[1] = p->k[d].imag();
+        p->dom_in[d].has_bm = desc->bm_coef ? 1 : 0;
+        p->dom_in[d].bm[0] = desc->bm_coef ? desc->bm_coef[d].re : 0.0;
+        p->dom_in[d].bm[1] = desc->bm_coef ? desc->bm_coef[d].im : 0.0;
+    }
+    p->glob.has_alpha = desc->alpha ? 1 : 0;
+    p->glob.alpha[0] = desc->alpha ? desc->alpha->re : 0.0;
+    p->glob.alpha[1] = desc->alpha ? desc->alpha->im : 0.0;
+    p->glob.has_beta = desc->beta ? 1 : 0;
+    p->glob.beta[0] = desc->beta ? desc->beta->re : 0.0;
+    p->glob.beta[1] = desc->beta ? desc->beta->im : 0.0;
+    p->glob.form = p->form;
+    p->glob.n_dom = p->n_dom;
+    p->L = make_layout(p);
+    *out = p;
+    return BEM_OK;
+}
+
+void bem_destroy(bem_problem* p)
+{
+    if (!p) return;
+    for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+    delete p;
+}
+
+bem_status bem_profile_enable(bem_problem* p, int on)
+{
+    if (bem_status s = check_problem(p)) return s;
+    p->prof.on = on != 0;
+    return BEM_OK;
+}
+
+bem_status bem_profile_read(bem_problem* p, bem_profile* out, int reset)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!out) return fail(BEM_E_ARG, "null output");
+    Prof& P = p->prof;
+    if (P.err != hipSuccess) return hip_fail(P.err, "profiling events");
+    std::memset(out, 0, sizeof *out);
+    for (const auto& r : P.recs) {
+        HIP_OK(hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.kind == bemk::KIND_ASSEMBLE) {
+            out->assemble_launches += 1;
+            out->assemble_ms += ms;
+        } else {
+            out->matvec_launches += 1;
+            out->matvec_ms += ms;
+        }
+    }
+    if (reset) {
+        P.recs.clear();
+        P.used = 0;
+        P.pending[0] = P.pending[1] = nullptr;
+    }
+    return BEM_OK;
+}
+
+int bem_n_elements(const bem_problem* p) { return p ? p->N : -1; }
+int bem_order(const bem_problem* p) { return p ? 2 * p->N : -1; }
+
+bem_status bem_sizes(const bem_problem* p, int prec, int nrhs, int restart, size_t* geom_bytes,
+                     size_t* matrix_bytes, size_t* work_bytes)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (prec != BEM_F64 && prec != BEM_F32) return fail(BEM_E_ARG, "prec must be BEM_F64 or BEM_F32");
+    if (nrhs < 1) return fail(BEM_E_ARG, "nrhs must be >= 1");
+    if (restart < 1 || restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
+    const size_t n = 2 * (size_t)p->N;
+    if (geom_bytes) *geom_bytes = p->L.total;
+    if (matrix_bytes) *matrix_bytes = n * n * (prec == BEM_F64 ? sizeof(double2) : sizeof(float2));
+    if (work_bytes) *work_bytes = make_work((int)n, nrhs, restart).total;
+    return BEM_OK;
+}
+
+bem_status bem_geometry(bem_problem* p, void* geom_dev, size_t geom_bytes, hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!geom_dev) return fail(BEM_E_ARG, "null geometry buffer");
+    if (geom_bytes < p->L.total) return fail(BEM_E_NOMEM, "geometry buffer smaller than bem_sizes asked for");
+    const GeomLayout& L = p->L;
+    // one host image of everything uploaded
+    std::vector<char> img(L.elem, 0);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(img.data() + off, src, bytes);
+    };
+    put(L.nodes, p->xy.data(), p->xy.size() * sizeof(double));
+    put(L.elnodes, p->elnodes.data(), p->elnodes.size() * sizeof(int));
+    put(L.elif, p->elif.data(), p->elif.size() * sizeof(int));
+    put(L.iface, p->iface.data(), p->iface.size() * sizeof(IfacePlan));
+    put(L.rtiles, p->rtiles.data(), p->rtiles.size() * sizeof(Tile));
+    put(L.cchunks, p->cchunks.data(), p->cchunks.size() * sizeof(Tile));
+    put(L.sigma, p->sigma.data(), p->sigma.size() * sizeof(int));
+    put(L.dom_in, p->dom_in.data(), p->dom_in.size() * sizeof(bemk::DomIn));
+    put(L.glob_in, &p->glob, sizeof(bemk::GlobalIn));
+    char* g = static_cast<char*>(geom_dev);
+    HIP_OK(hipMemcpyAsync(g, img.data(), img.size(), hipMemcpyHostToDevice, stream));
+    HIP_OK(bemk::launch_setup(g, L, p->N, p->n_dom, p->quad, stream));
+    // the host image must outlive the asynchronous copy
+    HIP_OK(hipStreamSynchronize(stream));
+    p->geom = g;
+    p->A = nullptr;
+    p->prec = -1;
+    return BEM_OK;
+}
+
+bem_status bem_geometry_update(bem_problem* p, hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_geometry_update");
+    HIP_OK(bemk::launch_setup(p->geom, p->L, p->N, p->n_dom, p->quad, stream));
+    p->A = nullptr;
+    p->prec = -1;
+    return BEM_OK;
+}
+
+bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_assemble");
+    if (prec != BEM_F64 && prec != BEM_F32) return fail(BEM_E_ARG, "prec must be BEM_F64 or BEM_F32");
+    const size_t n = 2 * (size_t)p->N;
+    if (!A_dev) return fail(BEM_E_ARG, "null matrix");
+    if (lda < n) return fail(BEM_E_ARG, "lda < n");
+    const int nrt = (int)p->rtiles.size(), ncc = (int)p->cchunks.size();
+    if (nrt > 65535 || ncc > 65535) return fail(BEM_E_ARG, "problem too large for one assembly grid");
+    bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
+    if (prec == BEM_F64)
+        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, nrt, ncc, p->quad,
+                                         static_cast<double2*>(A_dev), lda, stream));
+    else
+        HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, nrt, ncc, p->quad,
+                                         static_cast<float2*>(A_dev), lda, stream));
+    bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 1, stream);
+    p->A = A_dev;
+    p->lda = lda;
+    p->prec = prec;
+    return BEM_OK;
+}
+
+
+bem_status bem_rhs(const bem_problem* p, int nang, const double* angles, void* B_dev, size_t ldb,
+                   hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_rhs");
+    if (nang < 1 || !angles || !B_dev) return fail(BEM_E_ARG, "bad right-hand-side arguments");
+    if (ldb < 2 * (size_t)p->N) return fail(BEM_E_ARG, "ldb < n");
+    HIP_OK(bemk::launch_rhs(p->geom, p->L, p->N, angles, nang, static_cast<double2*>(B_dev), ldb, stream));
+    return BEM_OK;
+}
+
+bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t ldx, void* Y_dev, size_t ldy,
+                      void* work_dev, size_t work_bytes, hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_matvec");
+    const int n = 2 * p->N;
+    if (nrhs < 1 || !X_dev || !Y_dev || !work_dev) return fail(BEM_E_ARG, "bad matvec arguments");
+    if (ldx < (size_t)n || ldy < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+    const WorkLayout W = make_work(n, std::min(nrhs, 16), 1);
+    const size_t need = W.mv_part + (size_t)W.splits * std::min(nrhs, 16) * n * sizeof(double2);
+    if (work_bytes < need) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
+    char* w = static_cast<char*>(work_dev);
+    if (p->prec == BEM_F64)
+        HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n,
+                                       static_cast<const double2*>(X_dev), ldx, nrhs, static_cast<double2*>(Y_dev),
+                                       ldy, reinterpret_cast<double2*>(w + W.mv_part), stream, p->hk()));
+    else
+        HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, n, static_cast<const float2*>(X_dev),
+                                       ldx, nrhs, static_cast<float2*>(Y_dev), ldy,
+                                       reinterpret_cast<float2*>(w + W.mv_part), stream, p->hk()));
+    return BEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared state of one bem_solve call.
+struct Solver {
+    const bem_problem* p;
+    WorkLayout W;
+    char* w;
+    hipStream_t s;
+    int n, nr, m;
+    template <class T>
+    T* at(size_t off) const
+    {
+        return reinterpret_cast<T*>(w + off);
+    }
+    double2* V(int i) const { return at<double2>(W.V) + (size_t)i * nr * W.ldv; }
+};
+
+// Y = A X for FP64 vectors; with an FP32 matrix the product runs in FP32.
+bem_status apply_A(const Solver& c, const double2* X, size_t ldx, double2* Y, size_t ldy)
+{
+    const bem_problem* p = c.p;
+    if (p->prec == BEM_F64) {
+        HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
+                                       c.at<double2>(c.W.mv_part), c.s, p->hk()));
+    } else {
+        float2* x32 = c.at<float2>(c.W.X32);
+        float2* y32 = c.at<float2>(c.W.W32);
+        HIP_OK(bemk::launch_cast_f64_to_f32(X, ldx, c.n, c.nr, x32, c.W.ldv, c.s));
+        HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, c.n, x32, c.W.ldv, c.nr, y32,
+                                       c.W.ldv, reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s,
+                                       p->hk()));
+        HIP_OK(bemk::launch_cast_f32_to_f64(y32, c.W.ldv, c.n, c.nr, Y, ldy, c.s));
+    }
+    return BEM_OK;
+}
+
+// R = B - A X with FP64 accumulation (an FP32 matrix is widened on load).
+bem_status residual(const Solver& c, const double2* B, size_t ldb, const double2* X, size_t ldx, double2* R,
+                    size_t ldr)
+{
+    const bem_problem* p = c.p;
+    if (p->prec == BEM_F64)
+        HIP_OK(bemk::launch_residual_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, B, ldb, R, ldr,
+                                         c.at<double2>(c.W.mv_part), c.s, p->hk()));
+    else
+        HIP_OK(bemk::launch_residual_f32A(static_cast<const float2*>(p->A), p->lda, c.n, X, ldx, c.nr, B, ldb, R,
+                                          ldr, c.at<double2>(c.W.mv_part), c.s, p->hk()));
+    return BEM_OK;
+}
+
+bem_status col_norms(const Solver& c, const double2* X, size_t ldx, double* dev_out, std::vector<double>& host)
+{
+    HIP_OK(bemk::launch_col_norms(X, ldx, c.n, c.nr, c.at<double>(c.W.norm_part), dev_out, c.s));
+    host.resize(c.nr);
+    HIP_OK(hipMemcpyAsync(host.data(), dev_out, c.nr * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIP_OK(hipStreamSynchronize(c.s));
+    return BEM_OK;
+}
+
+bem_status upload_ints(const Solver& c, size_t off, const std::vector<int>& v)
+{
+    HIP_OK(hipMemcpyAsync(c.w + off, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, c.s));
+    return BEM_OK;
+}
+
+// GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi by
+// classical Gram-Schmidt with one re-orthogonalisation; the true residual is
+// recomputed at the end of each cycle.  Columns with want[r] == 0 are left
+// untouched.  iters[r] counts Arnoldi products.
+bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, double tol, int maxit,
+                 const std::vector<int>& want, std::vector<int>& iters, std::vector<int>& conv,
+                 std::vector<double>& rel, std::vector<int>& cycles, bool& nonfinite)
+{
+    const int n = c.n, nr = c.nr, m = c.m;
+    const size_t ldv = c.W.ldv;
+    double2* R = c.at<double2>(c.W.R);
+    double2* Wv = c.at<double2>(c.W.W);
+    for (int r = 0; r < nr; ++r)
+        if (want[r]) HIP_OK(hipMemsetAsync(X + (size_t)r * ldx, 0, (size_t)n * sizeof(double2), c.s));
+    HIP_OK(hipMemcpy2DAsync(R, ldv * sizeof(double2), B, ldb * sizeof(double2), (size_t)n * sizeof(double2), nr,
+                            hipMemcpyDeviceToDevice, c.s));
+    std::vector<double> bnorm, rnorm;
+    if (bem_status st = col_norms(c, B, ldb, c.at<double>(c.W.bnorm), bnorm)) return st;
+    rnorm = bnorm;
+    HIP_OK(hipMemcpyAsync(c.at<double>(c.W.rnorm), rnorm.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
+    std::vector<int> alive(nr, 0);
+    for (int r = 0; r < nr; ++r) {
+        if (!want[r]) continue;
+        if (!std::isfinite(bnorm[r])) {
+            nonfinite = true;
+            continue;
+        }
+        if (bnorm[r] == 0.0) {
+            conv[r] = 1;
+            rel[r] = 0.0;
+            continue;
+        }
+        alive[r] = 1;
+    }
+    std::vector<double> resid(nr);
+    std::vector<int> running(nr), kdim(nr);
+    while (std::count(alive.begin(), alive.end(), 1) > 0) {
+        running = alive;
+        if (bem_status st = upload_ints(c, c.W.active, running)) return st;
+        HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
+                                        c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
+        std::fill(kdim.begin(), kdim.end(), 0);
+        for (int j = 0; j < m; ++j) {
+            const int* act = c.at<int>(c.W.active);
+            if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
+            HIP_OK(bemk::launch_dots(c.V(0), ldv, nr, j + 1, Wv, ldv, n, c.at<double2>(c.W.dot_part),
+                                     c.at<double2>(c.W.h1), act, c.s));
+            HIP_OK(bemk::launch_update(c.V(0), ldv, nr, j + 1, c.at<double2>(c.W.h1), Wv, ldv, n, act, nullptr, c.s));
+            HIP_OK(bemk::launch_dots(c.V(0), ldv, nr, j + 1, Wv, ldv, n, c.at<double2>(c.W.dot_part),
+                                     c.at<double2>(c.W.h2), act, c.s));
+            HIP_OK(bemk::launch_update(c.V(0), ldv, nr, j + 1, c.at<double2>(c.W.h2), Wv, ldv, n, act,
+                                       c.at<double>(c.W.norm_part), c.s));
+            HIP_OK(bemk::launch_arnoldi_givens(nr, j, m, c.at<double2>(c.W.h1), c.at<double2>(c.W.h2),
+                                               c.at<double>(c.W.norm_part), c.W.nblk, c.at<double2>(c.W.H),
+                                               c.at<double2>(c.W.cs), c.at<double2>(c.W.sn),
+                                               c.at<double2>(c.W.gvec), c.at<double>(c.W.hnorm),
+                                               c.at<double>(c.W.resid), act, c.s));
+            HIP_OK(bemk::launch_scale_into(Wv, ldv, n, nr, c.at<double>(c.W.hnorm), c.V(j + 1), ldv, act, c.s));
+            HIP_OK(hipMemcpyAsync(resid.data(), c.at<double>(c.W.resid), nr * sizeof(double), hipMemcpyDeviceToHost,
+                                  c.s));
+            HIP_OK(hipStreamSynchronize(c.s));
+            bool changed = false;
+            for (int r = 0; r < nr; ++r) {
+                if (!running[r]) continue;
+                ++iters[r];
+                kdim[r] = j + 1;
+                const bool stop = !std::isfinite(resid[r]) || resid[r] <= tol * bnorm[r] || iters[r] >= maxit;
+                if (stop) {
+                    running[r] = 0;
+                    changed = true;
+                }
+            }
+            if (std::count(running.begin(), running.end(), 1) == 0) break;
+            if (changed)
+                if (bem_status st = upload_ints(c, c.W.active, running)) return st;
+        }
+        if (bem_status st = upload_ints(c, c.W.kdim, kdim)) return st;
+        HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
+                                      c.at<double2>(c.W.y), c.s));
+        HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx, c.s));
+        if (bem_status st = residual(c, B, ldb, X, ldx, R, ldv)) return st;
+        if (bem_status st = col_norms(c, R, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;
+        for (int r = 0; r < nr; ++r) {
+            if (!alive[r]) continue;
+            rel[r] = rnorm[r] / bnorm[r];
+            if (!std::isfinite(rel[r])) {
+                nonfinite = true;
+                alive[r] = 0;
+            } else if (rel[r] <= tol) {
+                conv[r] = 1;
+                alive[r] = 0;
+            } else if (iters[r] >= maxit) {
+                alive[r] = 0;
+            } else {
+                ++cycles[r];
+            }
+        }
+    }
+    return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bem_status bem_solve(bem_problem* p, int nrhs, const void* B_dev, size_t ldb, const bem_solve_opts* opts,
+                     void* X_dev, size_t ldx, void* work_dev, size_t work_bytes, bem_solve_info* info,
+                     hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_solve");
+    if (nrhs < 1 || !B_dev || !X_dev || !work_dev || !opts || !info) return fail(BEM_E_ARG, "bad solve arguments");
+    const int n = 2 * p->N;
+    if (ldb < (size_t)n || ldx < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+    if (opts->restart < 1 || opts->restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
+    if (!(opts->tol > 0.0) || opts->max_iter < 1) return fail(BEM_E_ARG, "tol must be > 0 and max_iter >= 1");
+    Solver c{p, make_work(n, nrhs, opts->restart), static_cast<char*>(work_dev), stream, n, nrhs, opts->restart};
+    if (work_bytes < c.W.total) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
+    const double2* B = static_cast<const double2*>(B_dev);
+    double2* X = static_cast<double2*>(X_dev);
+    std::vector<int> iters(nrhs, 0), conv(nrhs, 0), cycles(nrhs, 0), want(nrhs, 1);
+    std::vector<double> rel(nrhs, 1.0);
+    bool nonfinite = false;
+    if (p->prec == BEM_F64) {
+        if (bem_status st = gmres(c, B, ldb, X, ldx, opts->tol, opts->max_iter, want, iters, conv, rel, cycles,
+                                  nonfinite))
+            return st;
+    } else {
+        // FP32 products inside GMRES, FP64 outer iterative refinement:
+        //   r = b - A x (FP64 accumulation), solve A d = r loosely, x += d.
+        const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
+        const int max_refine = opts->max_refine > 0 ? opts->max_refine : 20;
+        const size_t ldv = c.W.ldv;
+        double2* Ro = c.at<double2>(c.W.Ro);
+        double2* D = c.at<double2>(c.W.D);
+        for (int r = 0; r < nrhs; ++r)
+            HIP_OK(hipMemsetAsync(X + (size_t)r * ldx, 0, (size_t)n * sizeof(double2), stream));
+        std::vector<double> bnorm, rnorm;
+        if (bem_status st = col_norms(c, B, ldb, c.at<double>(c.W.bnorm), bnorm)) return st;
+        HIP_OK(hipMemcpy2DAsync(Ro, ldv * sizeof(double2), B, ldb * sizeof(double2), (size_t)n * sizeof(double2),
+                                nrhs, hipMemcpyDeviceToDevice, stream));
+        rnorm = bnorm;
+        std::vector<int> active(nrhs, 1);
+        for (int step = 0; step <= max_refine; ++step) {
+            bool any = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!active[r]) continue;
+                rel[r] = bnorm[r] > 0.0 ? rnorm[r] / bnorm[r] : 0.0;
+                if (!std::isfinite(rel[r])) {
+                    nonfinite = true;
+                    active[r] = 0;
+                } else if (rel[r] <= opts->tol) {
+                    conv[r] = 1;
+                    active[r] = 0;
+                } else if (iters[r] >= opts->max_iter || step == max_refine) {
+                    active[r] = 0;
+                } else {
+                    any = true;
+                }
+            }
+            if (!any) break;
+            std::vector<int> it2(nrhs, 0), conv2(nrhs, 0), cyc2(nrhs, 0);
+            std::vector<double> rel2(nrhs, 1.0);
+            bool nf2 = false;
+            if (bem_status st = gmres(c, Ro, ldv, D, ldv, inner_tol, opts->max_iter, active, it2, conv2, rel2, cyc2,
+                                      nf2))
+                return st;
+            if (nf2) nonfinite = true;
+            for (int r = 0; r < nrhs; ++r) {
+                iters[r] += it2[r];
+                if (active[r]) ++cycles[r];
+            }
+            if (bem_status st = upload_ints(c, c.W.active, active)) return st;
+            HIP_OK(bemk::launch_add_f64(D, ldv, n, nrhs, X, ldx, c.at<int>(c.W.active), stream));
+            if (bem_status st = residual(c, B, ldb, X, ldx, Ro, ldv)) return st;
+            if (bem_status st = col_norms(c, Ro, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;
+        }
+    }
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+        info[r].iters = iters[r];
+        info[r].restarts = cycles[r];
+        info[r].converged = conv[r];
+        info[r].rel_residual = rel[r];
+        all = all && conv[r];
+    }
+    if (nonfinite) return fail(BEM_E_NONFINITE, "non-finite residual");
+    if (!all) return fail(BEM_E_NOCONV, "GMRES reached max_iter before tol on some right-hand side");
+    return BEM_OK;
+}
+
+bem_status bem_farfield(const bem_problem* p, int nrhs, const void* X_dev, size_t ldx, int ndir, const double* dirs,
+                        void* F_dev, size_t ldf, void* work_dev, size_t work_bytes, hipStream_t stream)
+{
+    (void)work_dev;
+    (void)work_bytes;
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_farfield");
+    if (nrhs < 1 || ndir < 1 || ndir > bemk::MAX_DIRS || !X_dev || !dirs || !F_dev)
+        return fail(BEM_E_ARG, "bad far-field arguments");
+    if (ldx < 2 * (size_t)p->N || ldf < (size_t)ndir) return fail(BEM_E_ARG, "leading dimension too small");
+    if (nrhs > 65535 * 8) return fail(BEM_E_ARG, "too many right-hand sides");
+    HIP_OK(bemk::launch_farfield(p->geom, p->L, p->N, p->n_if, p->n_dom, static_cast<const double2*>(X_dev), ldx, nrhs,
+                                 dirs, ndir, static_cast<double2*>(F_dev), ldf, stream));
+    return BEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// internal.h -- data layout shared by the host runtime and the gfx950 kernels.
+//
+// Everything the kernels read lives in one caller-owned device buffer (the
+// "geometry buffer"); GeomLayout holds the byte offset of each table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bemk {
+
+constexpr int QMAX = 16;      // largest Gauss rule
+constexpr int NAMP = 15;      // coefficients of each FP64 amplitude polynomial
+constexpr int NAMP32 = 7;     // ... FP32
+constexpr int NSER = 22;      // terms of each FP64 ascending series (|z| < 6)
+constexpr int NSER32 = 12;    // ... FP32 (|z| < 4)
+constexpr int ROW_TILE = 256; // collocation rows per assembly workgroup
+constexpr int COL_CHUNK = 32; // source elements per assembly workgroup
+constexpr int MAX_DIRS = 4096;
+
+// One boundary element (128 bytes).  Normal = left normal of the travel
+// direction a -> b.
+struct ElemRec {
+    double cx, cy;  // midpoint = collocation point
+    double tx, ty;  // unit tangent (b - a) / h
+    double nx, ny;  // unit normal (-ty, tx)
+    double h;       // length |b - a|
+    double ax, ay;  // first node
+    double bx, by;  // second node
+    double pad[5];
+};
+
+// Gauss points of one element and their weights (h/2) w_g.
+struct GaussRec {
+    double x[QMAX], y[QMAX], w[QMAX];
+};
+
+struct GaussRec32 {
+    float x[QMAX], y[QMAX], w[QMAX];
+};
+
+// Inputs of a domain as given by the caller (complex numbers as re, im).
+struct DomIn {
+    double k[2];
+    double bm[2];
+    int has_bm;
+    int pad;
+};
+
+struct GlobalIn {
+    double alpha[2];
+    double beta[2];
+    int has_alpha, has_beta, form, n_dom;
+};
+
+// Derived per-domain constants (computed on the device).
+struct DomConst {
+    double k[2];     // wavenumber
+    double eps[2];   // (k / k0)^2
+    double c[2];     // Burton-Miller coefficient alpha / eps (or the caller's)
+    double beta[2];  // scaling of the standard-type rows
+    int cplx;        // Im k != 0
+    int pad;
+};
+
+// Per-wavenumber tables of the device Hankel evaluator (FP64).
+//   |k r| <  XS: ascending series in s = r^2 with complex coefficients,
+//   |k r| >= XS: fitted amplitude polynomials in rho = 1/r^2 with the
+//                coefficients of w = (XS/z)^2 rescaled by (XS/k)^(2m).
+struct WaveConst {
+    double kr, ki;
+    double r2_small;                // (XS / |k|)^2
+    double ur, ui;                  // XS / k
+    double a0r, a0i, a1r, a1i;      // sqrt(2/(pi k)) e^{-i pi/4}, sqrt(2/(pi k)) e^{-3 i pi/4}
+    double lk0r, lk0i;              // (2/pi) (ln(k/2) + gamma)
+    double lk1r, lk1i;              // (2/pi) ln(k/2)
+    double y1r, y1i;                // -2 / (pi k)
+    double m0r[NAMP], m0i[NAMP], n0r[NAMP], n0i[NAMP];
+    double m1r[NAMP], m1i[NAMP], n1r[NAMP], n1i[NAMP];
+    double j0r[NSER], j0i[NSER], e0r[NSER], e0i[NSER];
+    double j1r[NSER], j1i[NSER], e1r[NSER], e1i[NSER];
+};
+
+// FP32 version (|k r| < 4: series, else amplitude fit).
+struct WaveConst32 {
+    float kr, ki;
+    float r2_small;
+    float ur, ui;
+    float a0r, a0i, a1r, a1i;
+    float lk0r, lk0i, lk1r, lk1i, y1r, y1i;
+    float m0r[NAMP32], m0i[NAMP32], n0r[NAMP32], n0i[NAMP32];
+    float m1r[NAMP32], m1i[NAMP32], n1r[NAMP32], n1i[NAMP32];
+    float j0r[NSER32], j0i[NSER32], e0r[NSER32], e0i[NSER32];
+    float j1r[NSER32], j1i[NSER32], e1r[NSER32], e1i[NSER32];
+};
+
+// Interface plan (host-computed integer bookkeeping).
+struct IfacePlan {
+    int off, count;   // element range
+    int dl, dr;       // domain the normal enters / leaves
+    int bm_r;         // the dom_right equation is of Burton-Miller type
+    int row_l, row_r; // first row of the dom_left / dom_right equation block
+    int pad;
+};
+
+// A tile of consecutive elements of one interface.
+struct Tile {
+    int iface, start, count, pad;
+};
+
+struct GeomLayout {
+    size_t nodes, elnodes, elem, gauss, gauss32, gl, dom_in, glob_in, dom, wave, wave32, self,
+        iface, rtiles, cchunks, sigma, elif, total;
+};
+
+}  // namespace bemk

@@ -1,0 +1,87 @@
+// launch.h -- host-side entry points of the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bemk {
+
+// Optional callback around the main kernel of a launcher (phase 0 before the
+// launch, 1 after), used by the library's HIP-event timing.
+enum { KIND_ASSEMBLE = 0, KIND_MATVEC = 1 };
+struct KernelHook {
+    void (*fn)(void* ctx, int kind, int phase, hipStream_t s);
+    void* ctx;
+};
+inline void hook_call(const KernelHook* h, int kind, int phase, hipStream_t s)
+{
+    if (h && h->fn) h->fn(h->ctx, kind, phase, s);
+}
+
+hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, hipStream_t s);
+hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
+                               int q, double2* A, size_t lda, hipStream_t s);
+hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
+                               int q, float2* A, size_t lda, hipStream_t s);
+
+// angles / dirs are HOST arrays: they travel to the kernels by value in
+// chunks of ANGLE_CHUNK.
+constexpr int ANGLE_CHUNK = 256;
+struct AngleChunk {
+    double v[ANGLE_CHUNK];
+};
+hipError_t launch_rhs(const char* g, const GeomLayout& L, int N, const double* angles, int nang, double2* B,
+                      size_t ldb, hipStream_t s);
+
+// Y = A X; partial holds splits * nrhs * n complex values.
+int matvec_splits(int n);
+hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
+                             double2* Y, size_t ldy, double2* partial, hipStream_t s,
+                             const KernelHook* hook = nullptr);
+hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
+                             size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr);
+// R = B - A X (FP64)
+hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
+                              const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,
+                              const KernelHook* hook = nullptr);
+// R = B - A X with an FP32 matrix, FP64 vectors and FP64 accumulation.
+hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
+                                const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial,
+                                hipStream_t s, const KernelHook* hook = nullptr);
+
+// GMRES building blocks (basis V[(i * nr + r) * ldv + q], FP64).
+hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double* partial, double* out,
+                            hipStream_t s);
+hipError_t launch_dots(const double2* V, size_t ldv, int nr, int jcount, const double2* W, size_t ldw, int n,
+                       double2* partial, double2* h, const int* active, hipStream_t s);
+hipError_t launch_update(const double2* V, size_t ldv, int nr, int jcount, const double2* h, double2* W,
+                         size_t ldw, int n, const int* active, double* norm_partial, hipStream_t s);
+hipError_t launch_arnoldi_finish(int nr, int j, int m, const double2* h1, const double2* h2,
+                                 const double* norm_partial, int nblk, double2* H, double* hnorm,
+                                 const int* active, hipStream_t s);
+hipError_t launch_scale_into(const double2* W, size_t ldw, int n, int nr, const double* hnorm, double2* V,
+                             size_t ldv, const int* active, hipStream_t s);
+hipError_t launch_arnoldi_givens(int nr, int j, int m, const double2* h1, const double2* h2,
+                                 const double* norm_part, int nblk, double2* H, double2* cs, double2* sn,
+                                 double2* gvec, double* hnorm, double* resid, const int* active, hipStream_t s);
+hipError_t launch_givens(int nr, int j, int m, double2* H, double2* cs, double2* sn, double2* gvec,
+                         double* resid, const int* active, hipStream_t s);
+hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
+                              double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
+hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
+                            hipStream_t s);
+hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+                          double2* X, size_t ldx, hipStream_t s);
+hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, size_t ldax, int n, int nr,
+                            double2* R, size_t ldr, hipStream_t s);
+hipError_t launch_cast_f64_to_f32(const double2* X, size_t ldx, int n, int nr, float2* Y, size_t ldy, hipStream_t s);
+hipError_t launch_cast_f32_to_f64(const float2* X, size_t ldx, int n, int nr, double2* Y, size_t ldy, hipStream_t s);
+hipError_t launch_add_f64(const double2* D, size_t ldd, int n, int nr, double2* X, size_t ldx, const int* active,
+                          hipStream_t s);
+
+hipError_t launch_farfield(const char* g, const GeomLayout& L, int N, int n_if, int n_dom, const double2* X,
+                           size_t ldx, int nrhs, const double* dirs, int ndir, double2* F, size_t ldf,
+                           hipStream_t s);
+
+}  // namespace bemk

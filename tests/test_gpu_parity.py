@@ -1,0 +1,208 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every input is seeded and synthetic (workloads.py); expected values come from
+the oracle on the same inputs.  Tolerances:
+  * assembly, right-hand side, far field, matvec: entrywise relative to the
+    largest entry, 1e-13 for real wavenumbers (both sides evaluate the same
+    formulas; the Hankel evaluators differ only by rounding, < 4e-16) and
+    5e-13 for lossy media (the device amplitude fit continued to complex
+    arguments is accurate to ~4e-14 relative);
+  * solutions: 1e-10 relative (the FP64 target), solved to 1e-12 so that the
+    forward error kappa * tol stays below it.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import mie_farfield, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_12787_amd as P
+    return P
+
+
+def _A_np(A_t, n):
+    """device matrix tensor (ncols, lda) -> numpy (n, n) matrix"""
+    return A_t.T[:n].cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+ASSEMBLY_CASES = [
+    ("disk256_k1-2", lambda: W.disk(256, 1.0, 2.0), 1e-13),
+    ("kite300_k4-6.5+0.4i", lambda: W.kite(300, 4.0, 6.5 + 0.4j), 5e-13),
+    ("kite300_beta1", lambda: W.kite(300, 3.0, 5.0, form=W.CALDERON_BETA1), 1e-13),
+    ("kite300_conventional", lambda: W.kite(300, 3.0, 5.0, form=W.CONVENTIONAL), 1e-13),
+    ("disk97_q10", lambda: W.disk(97, 2.0, 3.0, quad=10), 1e-13),
+    ("disk97_q5", lambda: W.disk(97, 2.0, 3.0, quad=5), 1e-13),
+    ("concentric_mod", lambda: W.concentric(70, 33, [2.0, 2.5, 3.5 + 0.2j]), 5e-13),
+    ("concentric_orig", lambda: W.concentric(70, 33, [2.0, 2.5, 3.5], form=W.CALDERON_ORIG), 1e-13),
+    ("concentric_conv", lambda: W.concentric(70, 33, [2.0, 2.5, 3.5], form=W.CONVENTIONAL), 1e-13),
+    ("kite40_k25-40", lambda: W.kite(40, 25.0, 40.0), 1e-13),
+]
+
+
+@pytest.mark.parametrize("name,make,tol", ASSEMBLY_CASES, ids=[c[0] for c in ASSEMBLY_CASES])
+def test_assembly_matches_oracle(name, make, tol):
+    P = _gpu()
+    spec = make()
+    _say("case", name, "N", spec.n_elements)
+    g = P.Problem(spec)
+    A = _A_np(g.assemble(P.F64), g.n)
+    torch.cuda.synchronize()
+    Ao = O.Problem(spec).assemble()
+    err = np.abs(A - Ao).max() / np.abs(Ao).max()
+    _say("  max entry error / max|A|", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("k1", [30.0, 30.0 + 0.3j], ids=["k1=30", "k1=30+0.3i"])
+def test_assembly_full_size_kite4096_sampled_rows(k1):
+    """Full-size kite (N = 4096, 8192 x 8192) in the launch configuration the
+    benchmark uses; 12 rows (both equation blocks, first/last/ragged tiles)
+    against the oracle's row-by-row assembly."""
+    P = _gpu()
+    spec = W.kite(4096, 20.0, k1)
+    g = P.Problem(spec)
+    A_t = g.assemble(P.F64)
+    rows = np.array([0, 1, 255, 256, 2047, 4095, 4096, 4097, 6000, 8191, 7936, 5121], dtype=np.int32)
+    got = A_t[:, torch.as_tensor(rows, device=A_t.device).long()].T.cpu().numpy()
+    ref = O.Problem(spec).assemble_rows(rows)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("kite4096", k1, "max sampled-row error / max|row|", err)
+    assert err < (1e-13 if np.imag(k1) == 0 else 5e-13)
+
+
+def test_rhs_matvec_farfield_match_oracle():
+    P = _gpu()
+    spec = W.kite(301, 5.0, 8.0 + 0.1j)
+    g = P.Problem(spec)
+    A_t = g.assemble(P.F64)
+    po = O.Problem(spec)
+    angles = np.array([0.0, 0.3, 2.0, 5.5])
+    B = g.rhs(angles).cpu().numpy().T
+    Bo = po.rhs(angles)
+    assert rel_err(B, Bo) < 1e-14
+    rng = np.random.default_rng(7)
+    for nrhs in (1, 3, 16, 19):
+        X = rng.standard_normal((g.n, nrhs)) + 1j * rng.standard_normal((g.n, nrhs))
+        Y = g.matvec(torch.as_tensor(X.T.copy(), device="cuda")).cpu().numpy().T
+        Ao = _A_np(A_t, g.n)
+        Yo = np.stack([O.matvec(Ao, X[:, r]) for r in range(nrhs)], axis=1)
+        _say("matvec nrhs", nrhs, rel_err(Y, Yo))
+        assert np.abs(Y - Yo).max() < 1e-13 * np.abs(Yo).max()
+    dirs = np.linspace(0, 2 * np.pi, 37)
+    X = rng.standard_normal((g.n, 3)) + 1j * rng.standard_normal((g.n, 3))
+    F = g.farfield(torch.as_tensor(X.T.copy(), device="cuda"), dirs).cpu().numpy().T
+    Fo = po.farfield(X, dirs)
+    assert np.abs(F - Fo).max() < 1e-13 * np.abs(Fo).max()
+
+
+def test_solve_disk256_matches_oracle_and_mie():
+    """Unit disk as a 256-gon, k0 = 1, k1 = 2, angle 0, GMRES(50)."""
+    P = _gpu()
+    spec = W.disk(256, 1.0, 2.0)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    B = g.rhs([0.0])
+    X, info = g.solve(B, restart=50, tol=1e-12)
+    _say("disk256 iters", info.iters, "rel res", info.rel_residual)
+    assert info.converged.all() and info.rel_residual[0] <= 1e-12
+    po = O.Problem(spec)
+    Xo = O.lu_solve(po.assemble(), po.rhs([0.0]))
+    assert rel_err(X.cpu().numpy().T, Xo) < 1e-10
+    dirs = W.equispaced_angles(360)
+    F = g.farfield(X, dirs).cpu().numpy().T[:, 0]
+    assert rel_err(F, po.farfield(Xo, dirs)[:, 0]) < 1e-10
+    assert rel_err(F, mie_farfield(1.0, 2.0, 1.0, 0.0, dirs)) < 2.5e-3
+    # same iteration count as the oracle's GMRES(50) up to Gram-Schmidt rounding
+    _, it_o, _, _ = O.gmres(po.assemble(), po.rhs([0.0])[:, 0], 50, 1e-12)
+    assert abs(int(info.iters[0]) - it_o) <= 2
+
+
+@pytest.mark.parametrize("form", [W.CALDERON, W.CALDERON_BETA1, W.CONVENTIONAL])
+def test_solve_kite_forms_and_restart(form):
+    """Lossy kite; restart shorter than the iteration count; all forms give
+    the oracle's LU solution."""
+    P = _gpu()
+    spec = W.kite(200, 6.0, 9.0 + 0.2j, form=form)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    ang = [0.1, 1.7, 3.3]
+    X, info = g.solve(g.rhs(ang), restart=8, tol=1e-12, max_iter=20000)
+    _say("form", form, "iters", info.iters, "restarts", info.restarts)
+    assert info.converged.all()
+    po = O.Problem(spec)
+    Xo = O.lu_solve(po.assemble(), po.rhs(ang))
+    assert rel_err(X.cpu().numpy().T, Xo) < 1e-10
+
+
+def test_batched_columns_equal_single_solves():
+    """Each column of a 16-angle block solve equals its own single solve."""
+    P = _gpu()
+    spec = W.kite(256, 8.0, 12.0)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    ang = W.equispaced_angles(16)
+    B = g.rhs(ang)
+    X, info = g.solve(B, restart=30, tol=1e-12)
+    assert info.converged.all()
+    for r in (0, 5, 15):
+        x1, i1 = g.solve(B[r:r + 1], restart=30, tol=1e-12)
+        assert rel_err(X[r].cpu().numpy(), x1[0].cpu().numpy()) < 1e-10
+        assert i1.iters[0] == info.iters[r]
+
+
+def test_noconv_status_and_zero_rhs():
+    P = _gpu()
+    spec = W.kite(64, 6.0, 9.0)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    B = g.rhs([0.0, 1.0])
+    B[1].zero_()
+    X, info = g.solve(B, restart=4, tol=1e-14, max_iter=6)
+    assert info.status == 6
+    assert info.converged[0] == 0 and info.iters[0] == 6
+    assert info.converged[1] == 1 and info.rel_residual[1] == 0.0
+    assert torch.count_nonzero(X[1]).item() == 0
+    with pytest.raises(P.BemError):
+        g.solve(B, restart=4, tol=1e-14, max_iter=6, raise_on_noconv=True)
+
+
+def test_state_errors():
+    P = _gpu()
+    g = P.Problem(W.disk(32, 1.0, 2.0))
+    with pytest.raises(P.BemError, match="BEM_E_STATE"):
+        g.matvec(torch.zeros((1, g.n), dtype=torch.complex128, device="cuda"))
+
+
+def test_kite4096_block_solve_residuals_against_oracle_rows():
+    """Full-size benchmark case: 16 angles, GMRES(100) to 1e-10.  The GPU
+    residual claim is checked on 8 sampled rows of the oracle's own matrix."""
+    P = _gpu()
+    spec = W.kite(4096, 20.0, 30.0)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    ang = W.equispaced_angles(16)
+    B = g.rhs(ang)
+    X, info = g.solve(B, restart=100, tol=1e-10)
+    _say("kite4096 iters", info.iters.tolist(), "rel", info.rel_residual.max())
+    assert info.converged.all() and info.rel_residual.max() <= 1e-10
+    rows = np.array([3, 1000, 4095, 4096, 5000, 8191, 2222, 7777], dtype=np.int32)
+    po = O.Problem(spec)
+    Ar = po.assemble_rows(rows)
+    Bo = po.rhs(ang)
+    Xn = X.cpu().numpy().T
+    res = Bo[rows] - Ar @ Xn
+    scale = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
+    _say("sampled residual / rms(b)", np.abs(res).max() / scale.min())
+    assert np.abs(res).max() < 1e-7 * scale.min()
