@@ -85,6 +85,37 @@ def cpu_baseline(workload, gpu_iters, rows_per_case=48):
                        f"1% of a product here, not modelled); {spent:.1f} s of CPU work")}
 
 
+def matvec_mode(args, wl, P, torch):
+    """Assemble the first case, then time --steps block products with all the
+    workload's right-hand sides, then one plain device copy of 1 GiB (a
+    kernel of known traffic for scaling hardware counters)."""
+    g = P.Problem(wl.problems[0])
+    g.assemble(P.F64)
+    X = g.rhs(wl.angles)
+    for _ in range(max(1, args.warmup)):
+        g.matvec(X)
+    torch.cuda.synchronize()
+    g.profile(True)
+    g.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Y = g.matvec(X)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    pr = g.profile_read(reset=True)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    n, nr = g.n, len(wl.angles)
+    mv_bytes = 16.0 * n * n + 2 * 16.0 * n * nr
+    avg = pr["matvec_ms"] / max(1, pr["matvec_launches"])
+    print(json.dumps({"mode": "matvec", "workload": wl.name, "launches": pr["matvec_launches"], "avg_ms": avg,
+                      "algorithmic_bytes_per_launch": mv_bytes, "GB_per_s": mv_bytes / (avg * 1e-3) / 1e9,
+                      "wall_ms_per_product": T / args.steps * 1e3, "copy_bytes": 1 << 30}), flush=True)
+    del Y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +123,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="full", choices=["full", "matvec"],
+                    help="matvec: assemble case 1 and run only --steps 16-right-hand-side products, then one plain "
+                         "1 GiB device copy (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1 "
@@ -105,6 +139,8 @@ def main():
 
     torch.cuda.set_device(0)
     wl = W.workload_kite4096() if args.workload == "kite4096" else W.workload_disk256()
+    if args.mode == "matvec":
+        return matvec_mode(args, wl, P, torch)
     dirs = wl.far_dirs
     stream = torch.cuda.current_stream()
     probs, mats = [], []
@@ -171,7 +207,7 @@ def main():
     mv_gbs = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
     as_avg_ms = as_ms / max(1, as_launch)
     evals = 2.0 * N * (N - 1) * q  # (H0, H1) pairs at Gauss points, both wavenumbers
-    kernel_src = os.path.join(ROOT, "paper_2312_12787_amd", "csrc", "linalg.hip")
+    kernel_src = os.path.join(ROOT, "paper_2312_12787_amd", "csrc", "matvec.hip")
     traffic = traffic_record(kernel_src)
     lat_ms = np.array(lat) * 1e3
     out = {
