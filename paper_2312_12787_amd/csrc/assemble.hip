@@ -485,6 +485,234 @@ __global__ __launch_bounds__(ROW_TILE) void k_assemble_f64(const char* __restric
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// FP32 assembly (precision path).  Entries are stored as complex64.  What
+// decides the accuracy stays in FP64: the distance r and the phase k r (FP32
+// would put an error of |k r| 6e-8 into every far entry), the ascending
+// series for |k r| < 4, the self terms.  The amplitude polynomials of
+// |k r| >= 4 (degree 6 in w), sin/cos of the phase reduced to [-pi, pi] and
+// the quadrature sums run in FP32.
+// ---------------------------------------------------------------------------
+struct cf {
+    float re, im;
+};
+__device__ __forceinline__ cf cmulf(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+template <int N>
+__device__ __forceinline__ float hornerf(const float* __restrict__ c, float x)
+{
+    float acc = c[N - 1];
+#pragma unroll
+    for (int m = N - 2; m >= 0; --m) acc = fmaf(acc, x, c[m]);
+    return acc;
+}
+template <int N>
+__device__ __forceinline__ cf hornerf_c(const float* __restrict__ cr, const float* __restrict__ ci, float x)
+{
+    float ar = cr[N - 1], ai = ci[N - 1];
+#pragma unroll
+    for (int m = N - 2; m >= 0; --m) {
+        ar = fmaf(ar, x, cr[m]);
+        ai = fmaf(ai, x, ci[m]);
+    }
+    return {ar, ai};
+}
+
+// H0, H1 at k r with r given in FP64; result in FP32.
+template <bool CPLX>
+__device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveConst32& W, double r, cf& h0, cf& h1)
+{
+    if (r * r < (double)W.r2_small) {
+        const double r2 = r * r, rinv = 1.0 / r, sr = sqrt(rinv);
+        cd a0, a1;
+        hankel01<CPLX>(W64, r, r2, rinv, sr, a0, a1);
+        h0 = {(float)a0.re, (float)a0.im};
+        h1 = {(float)a1.re, (float)a1.im};
+        return;
+    }
+    constexpr double TWO_PI = 6.283185307179586476925;
+    constexpr double INV_TWO_PI = 0.159154943091895335769;
+    const double ph = W64.kr * r;
+    const double red = fma(-rint(ph * INV_TWO_PI), TWO_PI, ph);  // |red| <= pi (+ rounding)
+    float sn, cs;
+    sincosf((float)red, &sn, &cs);
+    const float rf = (float)r;
+    const float rinv = 1.0f / rf;
+    const float rho = rinv * rinv;
+    const float srinv = sqrtf(rinv);
+    if (!CPLX) {
+        const float m0 = hornerf<NAMP32>(W.m0r, rho), n0 = hornerf<NAMP32>(W.n0r, rho);
+        const float m1 = hornerf<NAMP32>(W.m1r, rho), n1 = hornerf<NAMP32>(W.n1r, rho);
+        const float u = W.ur * rinv;
+        const cf e = {cs * srinv, sn * srinv};
+        h0 = cmulf(cmulf(e, {W.a0r, W.a0i}), {m0, u * n0});
+        h1 = cmulf(cmulf(e, {W.a1r, W.a1i}), {m1, u * n1});
+    } else {
+        const cf m0 = hornerf_c<NAMP32>(W.m0r, W.m0i, rho), n0 = hornerf_c<NAMP32>(W.n0r, W.n0i, rho);
+        const cf m1 = hornerf_c<NAMP32>(W.m1r, W.m1i, rho), n1 = hornerf_c<NAMP32>(W.n1r, W.n1i, rho);
+        const cf u = {W.ur * rinv, W.ui * rinv};
+        const cf un0 = cmulf(u, n0), un1 = cmulf(u, n1);
+        const float damp = (float)exp(-W64.ki * r) * srinv;
+        const cf e = {cs * damp, sn * damp};
+        h0 = cmulf(cmulf(e, {W.a0r, W.a0i}), {m0.re - un0.im, m0.im + un0.re});
+        h1 = cmulf(cmulf(e, {W.a1r, W.a1i}), {m1.re - un1.im, m1.im + un1.re});
+    }
+}
+
+template <int Q, bool CPLX, bool BM>
+__device__ __forceinline__ void assemble_side_f32(const ElemRec* __restrict__ el, const GaussRec* __restrict__ gq,
+                                                  const WaveConst& W64, const WaveConst32& W, const DomConst& Dm,
+                                                  int sg, int i, const ElemRec& Ei, int j0, int cnt, int q_rt,
+                                                  cd selfS, float2* __restrict__ A, size_t lda, size_t row, int N)
+{
+    const int q = Q > 0 ? Q : q_rt;
+    const cd k = {Dm.k[0], Dm.k[1]};
+    const cd ik4 = {-0.25 * k.im, 0.25 * k.re};
+    const cd eps = {Dm.eps[0], Dm.eps[1]};
+    const cd c = {Dm.c[0], Dm.c[1]};
+    const cd beta = {Dm.beta[0], Dm.beta[1]};
+    const double s = (double)sg;
+    const cd iq = {0.0, 0.25};
+    const cd cD = BM ? cd{s * ik4.re, s * ik4.im} : cscale(cmul(beta, ik4), s);
+    cd cS = cscale(cmul(eps, iq), -s);
+    if (!BM) cS = cmul(cS, beta);
+    const cd cDs = cscale(cmul(cmul(c, eps), ik4), s);
+    const cd cNS = cscale(cmul(cmul(c, cmul(k, k)), iq), s);
+    const cd cNE = cscale(cmul(c, ik4), s);
+    const cd du = BM ? cd{0.5, 0.0} : cscale(beta, 0.5);
+    const cd dw = cscale(cmul(c, eps), 0.5);
+    const cf cDf = {(float)cD.re, (float)cD.im}, cSf = {(float)cS.re, (float)cS.im};
+    const cf cDsf = {(float)cDs.re, (float)cDs.im}, cNSf = {(float)cNS.re, (float)cNS.im};
+    const cf cNEf = {(float)cNE.re, (float)cNE.im};
+    const double xi = Ei.cx, yi = Ei.cy;
+    const float tix = (float)Ei.tx, tiy = (float)Ei.ty, nix = (float)Ei.nx, niy = (float)Ei.ny;
+    cf Ea = {0.0f, 0.0f};
+    if (BM) {
+        const ElemRec& E0 = el[j0];
+        const double dx = xi - E0.ax, dy = yi - E0.ay;
+        const double r = sqrt(dx * dx + dy * dy);
+        cf h0, h1;
+        hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+        const float f = (float)((Ei.tx * dx + Ei.ty * dy) / r);
+        Ea = {h1.re * f, h1.im * f};
+    }
+    for (int jj = 0; jj < cnt; ++jj) {
+        const int j = j0 + jj;
+        const ElemRec& Ej = el[j];
+        cf sS = {0.0f, 0.0f}, sD = {0.0f, 0.0f}, sDs = {0.0f, 0.0f};
+        const bool diag = (j == i);
+        if (!diag) {
+            const GaussRec& G = gq[j];
+            const float njx = (float)Ej.nx, njy = (float)Ej.ny;
+#pragma unroll
+            for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
+                if (Q == 0 && g >= q) break;
+                const double rx = xi - G.x[g], ry = yi - G.y[g];
+                const double r = sqrt(fma(rx, rx, ry * ry));
+                cf h0, h1;
+                hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+                const float wg = (float)G.w[g];
+                const float rxf = (float)rx, ryf = (float)ry, rif = (float)(1.0 / r);
+                sS.re = fmaf(wg, h0.re, sS.re);
+                sS.im = fmaf(wg, h0.im, sS.im);
+                const float wd = wg * (rxf * njx + ryf * njy) * rif;
+                sD.re = fmaf(wd, h1.re, sD.re);
+                sD.im = fmaf(wd, h1.im, sD.im);
+                if (BM) {
+                    const float ws = wg * (rxf * nix + ryf * niy) * rif;
+                    sDs.re = fmaf(ws, h1.re, sDs.re);
+                    sDs.im = fmaf(ws, h1.im, sDs.im);
+                }
+            }
+        }
+        // combine in FP64 (few operations per entry), store FP32
+        cd au, aw;
+        cd sS64 = {(double)sS.re, (double)sS.im};
+        if (!diag) {
+            au = cmul(cD, {(double)sD.re, (double)sD.im});
+            aw = cmul(cS, sS64);
+        } else {
+            sS64 = cdiv(selfS, iq);
+            au = du;
+            aw = cmul(cS, sS64);
+            if (BM) aw = cadd(aw, dw);
+        }
+        if (BM) {
+            const double dxb = xi - Ej.bx, dyb = yi - Ej.by;
+            const double r = sqrt(dxb * dxb + dyb * dyb);
+            cf h0, h1;
+            hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+            const float f = (float)((Ei.tx * dxb + Ei.ty * dyb) / r);
+            const cf Eb = {h1.re * f, h1.im * f};
+            const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
+            au = cadd(au, cadd(cscale(cmul(cNS, sS64), ninj),
+                               cmul(cNE, {(double)Eb.re - (double)Ea.re, (double)Eb.im - (double)Ea.im})));
+            aw = cadd(aw, cmul(cDs, {(double)sDs.re, (double)sDs.im}));
+            Ea = Eb;
+        }
+        (void)cDf;
+        (void)cSf;
+        (void)cDsf;
+        (void)cNSf;
+        (void)cNEf;
+        (void)tix;
+        (void)tiy;
+        A[row + (size_t)j * lda] = make_float2((float)au.re, (float)au.im);
+        A[row + (size_t)(N + j) * lda] = make_float2((float)aw.re, (float)aw.im);
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(ROW_TILE) void k_assemble_f32(const char* __restrict__ g, GeomLayout L, int N,
+                                                            int n_if, int q_rt, float2* __restrict__ A, size_t lda)
+{
+    const Tile rt = tab<Tile>(g, L.rtiles)[blockIdx.x];
+    const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
+    const int side = blockIdx.z;
+    const int li = threadIdx.x;
+    if (li >= rt.count) return;
+    const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
+    const int d = side ? P.dr : P.dl;
+    const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
+    const bool bm = side ? (P.bm_r != 0) : false;
+    const int i = rt.start + li;
+    const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
+    if (sg == 0) {
+        for (int jj = 0; jj < cc.count; ++jj) {
+            const int j = cc.start + jj;
+            A[row + (size_t)j * lda] = make_float2(0.0f, 0.0f);
+            A[row + (size_t)(N + j) * lda] = make_float2(0.0f, 0.0f);
+        }
+        return;
+    }
+    const ElemRec* el = tab<ElemRec>(g, L.elem);
+    const GaussRec* gq = tab<GaussRec>(g, L.gauss);
+    const WaveConst& W64 = tab<WaveConst>(g, L.wave)[d];
+    const WaveConst32& W = tab<WaveConst32>(g, L.wave32)[d];
+    const DomConst Dm = tab<DomConst>(g, L.dom)[d];
+    const ElemRec Ei = el[i];
+    cd selfS = {0.0, 0.0};
+    if (i >= cc.start && i < cc.start + cc.count) {
+        const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
+        selfS = {sv.x, sv.y};
+    }
+    if (bm) {
+        if (Dm.cplx)
+            assemble_side_f32<Q, true, true>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
+                                             row, N);
+        else
+            assemble_side_f32<Q, false, true>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
+                                              row, N);
+    } else {
+        if (Dm.cplx)
+            assemble_side_f32<Q, true, false>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
+                                              row, N);
+        else
+            assemble_side_f32<Q, false, false>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A,
+                                               lda, row, N);
+    }
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -512,11 +740,17 @@ hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_
     return hipGetLastError();
 }
 
-}  // namespace bemk
-
-namespace bemk {
-hipError_t launch_assemble_f32(const char*, const GeomLayout&, int, int, int, int, int, float2*, size_t, hipStream_t)
+hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
+                               int q, float2* A, size_t lda, hipStream_t s)
 {
-    return hipErrorNotSupported;
+    dim3 grid(n_rtiles, n_cchunks, 2);
+    if (q == 8)
+        hipLaunchKernelGGL(k_assemble_f32<8>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    else if (q == 10)
+        hipLaunchKernelGGL(k_assemble_f32<10>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    else
+        hipLaunchKernelGGL(k_assemble_f32<0>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+    return hipGetLastError();
 }
+
 }  // namespace bemk

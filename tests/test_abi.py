@@ -1,0 +1,101 @@
+"""The C-ABI library (no GPU needed): it loads, exports every function that
+include/bem.h declares, and its host-only paths (validation, planning, sizes,
+call-order errors) behave as documented.  No call here launches device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bem_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2312_12787_amd as P
+    L = P.lib()
+    names = _declared()
+    assert "bem_solve" in names and "bem_assemble" in names and len(names) >= 14
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert sorted(P.EXPORTS) == names
+
+
+def _problem(spec):
+    import paper_2312_12787_amd as P
+    return P.Problem(spec, device="cpu")
+
+
+def test_create_validation_errors():
+    import paper_2312_12787_amd as P
+    cases = []
+    s = W.disk(16, -1.0, 2.0)
+    cases.append((s, "BEM_E_ARG"))
+    s = W.disk(16, 1.0, 2.0 - 0.1j)
+    cases.append((s, "BEM_E_ARG"))
+    s = W.disk(16, 1.0, 2.0)
+    s.interfaces[0].dom_left, s.interfaces[0].dom_right = 0, 1
+    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.disk(16, 1.0, 2.0)
+    s.interfaces[0].dom_left = 5
+    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.disk(16, 1.0, 2.0)
+    s.interfaces[0].xy[4] = s.interfaces[0].xy[3]
+    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.single_material(W.circle_nodes(2), 1.0, 2.0)
+    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.disk(16, 1.0, 1.0j)  # eps = -1: accumulation point at 0
+    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.disk(16, 1.0, 2.0, quad=17)
+    cases.append((s, "BEM_E_ARG"))
+    s = W.disk(16, 1.0, 2.0)
+    s.k[1] = complex(np.nan, 0)
+    cases.append((s, "BEM_E_ARG"))
+    for spec, code in cases:
+        with pytest.raises(P.BemError, match=code):
+            _problem(spec)
+
+
+def test_sizes_and_order():
+    import paper_2312_12787_amd as P
+    g = _problem(W.concentric(30, 17, [1.0, 2.0, 3.0]))
+    assert g.N == 47 and g.n == 94
+    geom, mat, work = g.sizes(P.F64, 5, 20)
+    assert mat == 94 * 94 * 16
+    assert g.sizes(P.F32, 5, 20)[1] == 94 * 94 * 8
+    assert geom > 47 * 128 and work > 21 * 5 * 94 * 16
+    # an open interface has one element fewer than nodes
+    spec = W.ProblemSpec(k=[1.0, 2.0, 3.0], interfaces=[
+        W.Interface(W.circle_nodes(20), True, 1, 0),
+        W.Interface(np.array([[-0.5, 0.0], [0.0, 0.0], [0.5, 0.0]]), False, 1, 2)])
+    assert _problem(spec).N == 22
+    with pytest.raises(P.BemError, match="BEM_E_ARG"):
+        g.sizes(P.F64, 0, 20)
+    with pytest.raises(P.BemError, match="BEM_E_ARG"):
+        g.sizes(P.F64, 1, 1001)
+
+
+def test_call_order_errors_before_any_device_work():
+    """bem_assemble / bem_rhs / bem_solve / bem_farfield before bem_geometry
+    return BEM_E_STATE from the host, without touching a device."""
+    import paper_2312_12787_amd as P
+    L = P.lib()
+    g = _problem(W.disk(16, 1.0, 2.0))
+    st = L.bem_assemble(g._h, P.F64, C.c_void_p(16), g.n, None)
+    assert P.STATUS[st] == "BEM_E_STATE"
+    ang = np.zeros(1)
+    st = L.bem_rhs(g._h, 1, ang.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(16), g.n, None)
+    assert P.STATUS[st] == "BEM_E_STATE"
+    assert "bem_geometry" in L.bem_last_error().decode()
+    st = L.bem_geometry_update(g._h, None)
+    assert P.STATUS[st] == "BEM_E_STATE"
+    st = L.bem_matvec(g._h, 1, C.c_void_p(16), g.n, C.c_void_p(16), g.n, C.c_void_p(16), 1 << 20, None)
+    assert P.STATUS[st] == "BEM_E_STATE"

@@ -1,0 +1,88 @@
+"""Precision path: FP32 assembly (FP64 distances, phases, small-argument series
+and self terms; FP32 amplitude polynomials and sums) and the mixed solve
+(FP32 matrix and products, FP64 Arnoldi, FP64-accumulated outer residual).
+
+Bars: FP32 entries within 1e-6 of the largest entry (complex64 rounding is
+6e-8 relative; the FP32 Hankel amplitude fit is 7e-10); the refined solution
+and far field within 1e-6 relative of the oracle's FP64 solution (the
+precision target), which holds because the FP32 matrix differs from the FP64
+one by rounding only.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_12787_amd as P
+    return P
+
+
+CASES = [("kite300_k20-30", lambda: W.kite(300, 20.0, 30.0)),
+         ("kite301_k6-9+0.2i", lambda: W.kite(301, 6.0, 9.0 + 0.2j)),
+         ("disk256_k1-2", lambda: W.disk(256, 1.0, 2.0)),
+         ("concentric_mod", lambda: W.concentric(70, 33, [2.0, 2.5, 3.5 + 0.2j])),
+         ("disk97_q5", lambda: W.disk(97, 2.0, 3.0, quad=5))]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fp32_assembly_matches_oracle(name, make):
+    P = _gpu()
+    spec = make()
+    print("case", name, flush=True)
+    g = P.Problem(spec)
+    A = g.assemble(P.F32).T[:g.n].cpu().numpy().astype(np.complex128)
+    Ao = O.Problem(spec).assemble()
+    err = np.abs(A - Ao).max() / np.abs(Ao).max()
+    rel = np.median(np.abs(A - Ao) / np.maximum(np.abs(Ao), 1e-300))
+    print("  max error / max|A|", err, " median entry relative error", rel, flush=True)
+    assert err < 1e-6
+
+
+def test_mixed_solve_matches_fp64_oracle():
+    """16 angles on a kite at k0 = 20, k1 = 30 (+ lossy case): refined solution
+    and far field within 1e-6 of the oracle's FP64 LU solution."""
+    P = _gpu()
+    dirs = W.equispaced_angles(360)
+    ang = W.equispaced_angles(16)
+    for k1 in (30.0, 30.0 + 0.3j):
+        spec = W.kite(400, 20.0, k1)
+        g = P.Problem(spec)
+        g.assemble(P.F32)
+        B = g.rhs(ang)
+        X, info = g.solve(B, restart=100, tol=1e-10, inner_tol=1e-5)
+        print("k1", k1, "iters", info.iters.tolist(), "refinement steps", info.restarts.tolist(),
+              "rel res", info.rel_residual.max(), flush=True)
+        assert info.converged.all()
+        po = O.Problem(spec)
+        Xo = np.linalg.solve(po.assemble(), po.rhs(ang))
+        Xg = X.cpu().numpy().T
+        e = max(rel_err(Xg[:, r], Xo[:, r]) for r in range(16))
+        F = g.farfield(X, dirs).cpu().numpy().T
+        Fo = po.farfield(Xo, dirs)
+        ef = max(rel_err(F[:, r], Fo[:, r]) for r in range(16))
+        print("  solution error", e, "far-field error", ef, flush=True)
+        assert e < 1e-6 and ef < 1e-6
+
+
+def test_fp32_matvec_matches_fp64_product_of_fp32_matrix():
+    P = _gpu()
+    g = P.Problem(W.kite(257, 5.0, 8.0))
+    A32 = g.assemble(P.F32)
+    A = A32.T[:g.n].cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(3)
+    for nrhs in (1, 4, 16, 21):
+        X = (rng.standard_normal((g.n, nrhs)) + 1j * rng.standard_normal((g.n, nrhs))).astype(np.complex64)
+        Y = g.matvec(torch.as_tensor(X.T.copy(), device="cuda")).cpu().numpy().T
+        Yo = A @ X.astype(np.complex128)
+        err = np.abs(Y - Yo).max() / np.abs(Yo).max()
+        print("fp32 matvec nrhs", nrhs, err, flush=True)
+        assert err < 2e-6
