@@ -100,6 +100,10 @@ struct bem_problem {
     std::vector<bemk::DomIn> dom_in;
     bemk::GlobalIn glob{};
     GeomLayout L{};
+    // pinned host slots for the asynchronous read-back of the GMRES flags
+    int* pinned = nullptr;
+    size_t pinned_ints = 0;
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
     // device state recorded by the calls
     char* geom = nullptr;
     void* A = nullptr;
@@ -151,9 +155,9 @@ GeomLayout make_layout(const bem_problem* p)
 
 // Workspace of the solver and products (byte offsets into work_dev).
 struct WorkLayout {
-    size_t V, W, R, Ro, D, X32, W32, mv_part, dot_part, h1, h2, y, H, cs, sn, gvec, norm_part, hnorm, resid, rnorm,
-        bnorm, active, kdim, dirs, total;
-    int ldv, nblk, splits;
+    size_t V, W, R, Ro, D, X32, W32, mv_part, dot_part, dot_part2, h1, h2, y, H, cs, sn, gvec, norm_part, n0, n1, n2,
+        hnorm, resid, rnorm, bnorm, thr, active, kdim, iters, dirs, total;
+    int ldv, nblk, splits, anblk;
 };
 
 WorkLayout make_work(int n, int nr, int m)
@@ -177,7 +181,14 @@ WorkLayout make_work(int n, int nr, int m)
     W.X32 = take((size_t)W.ldv * nr * sizeof(float2));
     W.W32 = take((size_t)W.ldv * nr * sizeof(float2));
     W.mv_part = take((size_t)W.splits * std::min(nr, 16) * n * sizeof(double2));
-    W.dot_part = take((size_t)nr * W.nblk * (m + 1) * sizeof(double2));
+    W.anblk = bemk::arnoldi_blocks(n);
+    W.dot_part = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
+    W.dot_part2 = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
+    W.n0 = take((size_t)nr * W.anblk * sizeof(double));
+    W.n1 = take((size_t)nr * W.anblk * sizeof(double));
+    W.n2 = take((size_t)nr * W.anblk * sizeof(double));
+    W.thr = take((size_t)nr * sizeof(double));
+    W.iters = take((size_t)nr * sizeof(int));
     W.h1 = take((size_t)nr * 1024 * sizeof(double2));
     W.h2 = take((size_t)nr * 1024 * sizeof(double2));
     W.y = take((size_t)nr * 1024 * sizeof(double2));
@@ -360,6 +371,9 @@ void bem_destroy(bem_problem* p)
 {
     if (!p) return;
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->flag_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
 }
 
@@ -520,7 +534,7 @@ namespace {
 
 // Shared state of one bem_solve call.
 struct Solver {
-    const bem_problem* p;
+    bem_problem* p;
     WorkLayout W;
     char* w;
     hipStream_t s;
@@ -615,54 +629,54 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         }
         alive[r] = 1;
     }
-    std::vector<double> resid(nr);
-    std::vector<int> running(nr), kdim(nr);
+    // device-side stopping thresholds and counters
+    std::vector<double> thr(nr);
+    for (int r = 0; r < nr; ++r) thr[r] = tol * bnorm[r];
+    HIP_OK(hipMemcpyAsync(c.at<double>(c.W.thr), thr.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
+    HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), iters.data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
+    if (c.p->pinned_ints < (size_t)2 * nr) {
+        if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
+        c.p->pinned = nullptr;
+        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), 2 * nr * sizeof(int), hipHostMallocDefault));
+        c.p->pinned_ints = 2 * nr;
+    }
+    for (auto& e : c.p->flag_ev)
+        if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    std::vector<int> dev_iters(nr);
     while (std::count(alive.begin(), alive.end(), 1) > 0) {
-        running = alive;
-        if (bem_status st = upload_ints(c, c.W.active, running)) return st;
+        if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
+        HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
         HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
                                         c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
-        std::fill(kdim.begin(), kdim.end(), 0);
+        // The GPU decides per right-hand side when to stop (k_arnoldi_step);
+        // the host reads the flags one step behind, so the queue never drains.
         for (int j = 0; j < m; ++j) {
-            const int* act = c.at<int>(c.W.active);
             if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
-            HIP_OK(bemk::launch_dots(c.V(0), ldv, nr, j + 1, Wv, ldv, n, c.at<double2>(c.W.dot_part),
-                                     c.at<double2>(c.W.h1), act, c.s));
-            HIP_OK(bemk::launch_update(c.V(0), ldv, nr, j + 1, c.at<double2>(c.W.h1), Wv, ldv, n, act, nullptr, c.s));
-            HIP_OK(bemk::launch_dots(c.V(0), ldv, nr, j + 1, Wv, ldv, n, c.at<double2>(c.W.dot_part),
-                                     c.at<double2>(c.W.h2), act, c.s));
-            HIP_OK(bemk::launch_update(c.V(0), ldv, nr, j + 1, c.at<double2>(c.W.h2), Wv, ldv, n, act,
-                                       c.at<double>(c.W.norm_part), c.s));
-            HIP_OK(bemk::launch_arnoldi_givens(nr, j, m, c.at<double2>(c.W.h1), c.at<double2>(c.W.h2),
-                                               c.at<double>(c.W.norm_part), c.W.nblk, c.at<double2>(c.W.H),
-                                               c.at<double2>(c.W.cs), c.at<double2>(c.W.sn),
-                                               c.at<double2>(c.W.gvec), c.at<double>(c.W.hnorm),
-                                               c.at<double>(c.W.resid), act, c.s));
-            HIP_OK(bemk::launch_scale_into(Wv, ldv, n, nr, c.at<double>(c.W.hnorm), c.V(j + 1), ldv, act, c.s));
-            HIP_OK(hipMemcpyAsync(resid.data(), c.at<double>(c.W.resid), nr * sizeof(double), hipMemcpyDeviceToHost,
-                                  c.s));
-            HIP_OK(hipStreamSynchronize(c.s));
-            bool changed = false;
-            for (int r = 0; r < nr; ++r) {
-                if (!running[r]) continue;
-                ++iters[r];
-                kdim[r] = j + 1;
-                const bool stop = !std::isfinite(resid[r]) || resid[r] <= tol * bnorm[r] || iters[r] >= maxit;
-                if (stop) {
-                    running[r] = 0;
-                    changed = true;
-                }
+            HIP_OK(bemk::launch_arnoldi(c.V(0), ldv, nr, j, m, n, Wv, ldv, c.at<double2>(c.W.dot_part),
+                                        c.at<double2>(c.W.dot_part2), c.at<double>(c.W.n0), c.at<double>(c.W.n1),
+                                        c.at<double>(c.W.n2), c.at<double2>(c.W.H), c.at<double2>(c.W.cs),
+                                        c.at<double2>(c.W.sn), c.at<double2>(c.W.gvec), c.at<double>(c.W.hnorm),
+                                        c.at<double>(c.W.resid), c.at<double>(c.W.thr), maxit, c.at<int>(c.W.iters),
+                                        c.at<int>(c.W.kdim), c.at<int>(c.W.active), c.s));
+            int* slot = c.p->pinned + (j & 1) * nr;
+            HIP_OK(hipMemcpyAsync(slot, c.at<int>(c.W.active), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
+            HIP_OK(hipEventRecord(c.p->flag_ev[j & 1], c.s));
+            if (j >= 1) {
+                HIP_OK(hipEventSynchronize(c.p->flag_ev[(j - 1) & 1]));
+                const int* prev = c.p->pinned + ((j - 1) & 1) * nr;
+                bool any = false;
+                for (int r = 0; r < nr; ++r) any = any || prev[r];
+                if (!any) break;
             }
-            if (std::count(running.begin(), running.end(), 1) == 0) break;
-            if (changed)
-                if (bem_status st = upload_ints(c, c.W.active, running)) return st;
         }
-        if (bem_status st = upload_ints(c, c.W.kdim, kdim)) return st;
         HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
                                       c.at<double2>(c.W.y), c.s));
         HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx, c.s));
         if (bem_status st = residual(c, B, ldb, X, ldx, R, ldv)) return st;
+        HIP_OK(hipMemcpyAsync(dev_iters.data(), c.at<int>(c.W.iters), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
         if (bem_status st = col_norms(c, R, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;
+        for (int r = 0; r < nr; ++r)
+            if (alive[r]) iters[r] = dev_iters[r];
         for (int r = 0; r < nr; ++r) {
             if (!alive[r]) continue;
             rel[r] = rnorm[r] / bnorm[r];

@@ -53,20 +53,13 @@ hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double
 // GMRES building blocks (basis V[(i * nr + r) * ldv + q], FP64).
 hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double* partial, double* out,
                             hipStream_t s);
-hipError_t launch_dots(const double2* V, size_t ldv, int nr, int jcount, const double2* W, size_t ldw, int n,
-                       double2* partial, double2* h, const int* active, hipStream_t s);
-hipError_t launch_update(const double2* V, size_t ldv, int nr, int jcount, const double2* h, double2* W,
-                         size_t ldw, int n, const int* active, double* norm_partial, hipStream_t s);
-hipError_t launch_arnoldi_finish(int nr, int j, int m, const double2* h1, const double2* h2,
-                                 const double* norm_partial, int nblk, double2* H, double* hnorm,
-                                 const int* active, hipStream_t s);
-hipError_t launch_scale_into(const double2* W, size_t ldw, int n, int nr, const double* hnorm, double2* V,
-                             size_t ldv, const int* active, hipStream_t s);
-hipError_t launch_arnoldi_givens(int nr, int j, int m, const double2* h1, const double2* h2,
-                                 const double* norm_part, int nblk, double2* H, double2* cs, double2* sn,
-                                 double2* gvec, double* hnorm, double* resid, const int* active, hipStream_t s);
-hipError_t launch_givens(int nr, int j, int m, double2* H, double2* cs, double2* sn, double2* gvec,
-                         double* resid, const int* active, hipStream_t s);
+// One Arnoldi step for all running right-hand sides after W = A V_j: CGS with
+// a conditional second pass, Givens update, stopping decision, V_{j+1}.
+int arnoldi_blocks(int n);
+hipError_t launch_arnoldi(double2* V, size_t ldv, int nr, int j, int m, int n, double2* W, size_t ldw,
+                          double2* p1, double2* p2, double* n0, double* n1, double* n2, double2* H, double2* cs,
+                          double2* sn, double2* gvec, double* hnorm, double* resid, const double* thr, int maxit,
+                          int* iters, int* kdim, int* active, hipStream_t s);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
                               double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,

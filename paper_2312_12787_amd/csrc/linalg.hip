@@ -105,242 +105,13 @@ __global__ void k_col_norm_finish(const double* __restrict__ partial, int nblk, 
     out[r] = sqrt(s);
 }
 
-// partial[(r * nblk + blk) * jcount + i] = sum over the block's rows of conj(V_i) W
-__global__ __launch_bounds__(BS) void k_dots(const double2* __restrict__ V, size_t ldv, int nr, int jcount,
-                                             const double2* __restrict__ W, size_t ldw, int n,
-                                             double2* __restrict__ part, const int* __restrict__ active)
-{
-    __shared__ double lds[4 * 2 * DOT_BATCH];
-    const int r = blockIdx.y;
-    if (!active[r]) return;
-    const int q = blockIdx.x * BS + threadIdx.x;
-    double2 w = make_double2(0.0, 0.0);
-    if (q < n) w = W[(size_t)r * ldw + q];
-    for (int i0 = 0; i0 < jcount; i0 += DOT_BATCH) {
-        double acc[2 * DOT_BATCH];
-#pragma unroll
-        for (int b = 0; b < DOT_BATCH; ++b) {
-            const int i = i0 + b;
-            double2 v = make_double2(0.0, 0.0);
-            if (i < jcount && q < n) v = V[((size_t)i * nr + r) * ldv + q];
-            acc[2 * b] = fma(v.x, w.x, v.y * w.y);      // Re conj(v) w
-            acc[2 * b + 1] = fma(v.x, w.y, -v.y * w.x); // Im conj(v) w
-        }
-        block_sum<2 * DOT_BATCH>(acc, lds);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int b = 0; b < DOT_BATCH; ++b)
-                if (i0 + b < jcount)
-                    part[((size_t)r * gridDim.x + blockIdx.x) * jcount + i0 + b] =
-                        make_double2(acc[2 * b], acc[2 * b + 1]);
-        }
-    }
-}
-
-__global__ void k_dots_reduce(const double2* __restrict__ part, int nblk, int nr, int jcount,
-                              double2* __restrict__ h, const int* __restrict__ active)
-{
-    const int r = blockIdx.x;
-    if (!active[r]) return;
-    for (int i = threadIdx.x; i < jcount; i += blockDim.x) {
-        double sr = 0.0, si = 0.0;
-        for (int b = 0; b < nblk; ++b) {
-            const double2 v = part[((size_t)r * nblk + b) * jcount + i];
-            sr += v.x;
-            si += v.y;
-        }
-        h[(size_t)r * 1024 + i] = make_double2(sr, si);
-    }
-}
-
-// W -= sum_i h_i V_i ; optional per-block partial sums of |W|^2
-__global__ __launch_bounds__(BS) void k_update(const double2* __restrict__ V, size_t ldv, int nr, int jcount,
-                                               const double2* __restrict__ h, double2* __restrict__ W, size_t ldw,
-                                               int n, const int* __restrict__ active,
-                                               double* __restrict__ norm_part)
-{
-    __shared__ double lds[4];
-    const int r = blockIdx.y;
-    if (!active[r]) return;
-    const int q = blockIdx.x * BS + threadIdx.x;
-    double acc[1] = {0.0};
-    if (q < n) {
-        double2 w = W[(size_t)r * ldw + q];
-        const double2* hr = h + (size_t)r * 1024;
-        for (int i = 0; i < jcount; ++i) {
-            const double2 c = hr[i];
-            const double2 v = V[((size_t)i * nr + r) * ldv + q];
-            w.x -= c.x * v.x - c.y * v.y;
-            w.y -= c.x * v.y + c.y * v.x;
-        }
-        W[(size_t)r * ldw + q] = w;
-        acc[0] = fma(w.x, w.x, w.y * w.y);
-    }
-    if (norm_part) {
-        block_sum<1>(acc, lds);
-        if (threadIdx.x == 0) norm_part[r * gridDim.x + blockIdx.x] = acc[0];
-    }
-}
-
-// H[:, j] = h1 + h2 (two Gram-Schmidt passes), H[j+1, j] = ||w||
-__global__ void k_arnoldi_finish(int nr, int j, int m, const double2* __restrict__ h1,
-                                 const double2* __restrict__ h2, const double* __restrict__ norm_part, int nblk,
-                                 double2* __restrict__ H, double* __restrict__ hnorm, const int* __restrict__ active)
-{
-    const int r = blockIdx.x;
-    if (!active[r]) return;
-    double2* Hr = H + (size_t)r * (m + 1) * m;
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        const double2 a = h1[(size_t)r * 1024 + i], b = h2[(size_t)r * 1024 + i];
-        Hr[i + (size_t)j * (m + 1)] = make_double2(a.x + b.x, a.y + b.y);
-    }
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += norm_part[r * nblk + b];
-        const double nv = sqrt(s);
-        Hr[j + 1 + (size_t)j * (m + 1)] = make_double2(nv, 0.0);
-        hnorm[r] = nv;
-    }
-}
-
-__global__ void k_scale_into(const double2* __restrict__ W, size_t ldw, int n, const double* __restrict__ hnorm,
-                             double2* __restrict__ V, size_t ldv, int nr, const int* __restrict__ active)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (q >= n || !active[r]) return;
-    const double nv = hnorm[r];
-    const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
-    const double2 w = W[(size_t)r * ldw + q];
-    V[(size_t)r * ldv + q] = make_double2(w.x * inv, w.y * inv);
-}
-
-// Apply the earlier rotations to column j of H, make the rotation that zeroes
-// H[j+1, j], update g and the residual estimate |g[j+1]|.
-__global__ void k_givens(int nr, int j, int m, double2* __restrict__ H, double2* __restrict__ cs,
-                         double2* __restrict__ sn, double2* __restrict__ gvec, double* __restrict__ resid,
-                         const int* __restrict__ active)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr || !active[r]) return;
-    double2* Hc = H + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
-    double2* c = cs + (size_t)r * m;
-    double2* s = sn + (size_t)r * m;
-    double2* gv = gvec + (size_t)r * (m + 1);
-    for (int i = 0; i < j; ++i) {
-        const double2 hi = Hc[i], hn = Hc[i + 1];
-        const double2 ci = c[i], si = s[i];
-        // [hi; hn] <- [c s; -conj(s) conj(c)] [hi; hn]
-        const double2 t = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
-                                       ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
-        const double2 u = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
-                                       -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
-        Hc[i] = t;
-        Hc[i + 1] = u;
-    }
-    const double2 a = Hc[j], b = Hc[j + 1];
-    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-    const double rho = hypot(na, nb);
-    double2 cj, sj;
-    if (rho == 0.0) {
-        cj = make_double2(1.0, 0.0);
-        sj = make_double2(0.0, 0.0);
-    } else if (na == 0.0) {
-        cj = make_double2(0.0, 0.0);
-        sj = make_double2(b.x / nb, -b.y / nb);
-    } else {
-        // c = |a|/rho, s = (a/|a|) conj(b) / rho
-        cj = make_double2(na / rho, 0.0);
-        const double ux = a.x / na, uy = a.y / na;
-        sj = make_double2((ux * b.x + uy * b.y) / rho, (uy * b.x - ux * b.y) / rho);
-    }
-    c[j] = cj;
-    s[j] = sj;
-    Hc[j] = make_double2(cj.x * a.x + sj.x * b.x - sj.y * b.y, cj.x * a.y + sj.x * b.y + sj.y * b.x);
-    Hc[j + 1] = make_double2(0.0, 0.0);
-    const double2 gj = gv[j];
-    // g[j+1] = -conj(s) g[j]; g[j] = c g[j]
-    gv[j + 1] = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
-    gv[j] = make_double2(cj.x * gj.x, cj.x * gj.y);
-    resid[r] = hypot(gv[j + 1].x, gv[j + 1].y);
-}
 
 
-// Column j of the Hessenberg matrix (h1 + h2 from the two Gram-Schmidt passes,
-// ||w|| below the diagonal), then the Givens update of that column and of g:
-// one wave per right-hand side; the column and the rotations sit in LDS and
-// lane 0 applies the rotations in order.
-__global__ __launch_bounds__(64) void k_arnoldi_givens(int nr, int j, int m, const double2* __restrict__ h1,
-                                                       const double2* __restrict__ h2,
-                                                       const double* __restrict__ norm_part, int nblk,
-                                                       double2* __restrict__ H, double2* __restrict__ cs,
-                                                       double2* __restrict__ sn, double2* __restrict__ gvec,
-                                                       double* __restrict__ hnorm, double* __restrict__ resid,
-                                                       const int* __restrict__ active)
-{
-    __shared__ double2 col[1024 + 1];
-    __shared__ double2 lc[1024], ls[1024];
-    const int r = blockIdx.x;
-    if (!active[r]) return;
-    const int lane = threadIdx.x;
-    double2* Hc = H + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
-    for (int i = lane; i <= j; i += 64) {
-        const double2 a = h1[(size_t)r * 1024 + i], b = h2[(size_t)r * 1024 + i];
-        col[i] = make_double2(a.x + b.x, a.y + b.y);
-    }
-    for (int i = lane; i < j; i += 64) {
-        lc[i] = cs[(size_t)r * m + i];
-        ls[i] = sn[(size_t)r * m + i];
-    }
-    double part = 0.0;
-    for (int b = lane; b < nblk; b += 64) part += norm_part[r * nblk + b];
-    // fixed-order sum over the wave
-    __shared__ double red[64];
-    red[lane] = part;
-    __syncthreads();
-    if (lane == 0) {
-        double sum = 0.0;
-        for (int k = 0; k < 64; ++k) sum += red[k];
-        const double nv = sqrt(sum);
-        hnorm[r] = nv;
-        col[j + 1] = make_double2(nv, 0.0);
-        for (int i = 0; i < j; ++i) {
-            const double2 hi = col[i], hn = col[i + 1];
-            const double2 ci = lc[i], si = ls[i];
-            col[i] = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
-                                  ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
-            col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
-                                      -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
-        }
-        const double2 a = col[j], b = col[j + 1];
-        const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-        const double rho = hypot(na, nb);
-        double2 cj, sj;
-        if (rho == 0.0) {
-            cj = make_double2(1.0, 0.0);
-            sj = make_double2(0.0, 0.0);
-        } else if (na == 0.0) {
-            cj = make_double2(0.0, 0.0);
-            sj = make_double2(b.x / nb, -b.y / nb);
-        } else {
-            cj = make_double2(na / rho, 0.0);
-            const double ux = a.x / na, uy = a.y / na;
-            sj = make_double2((ux * b.x + uy * b.y) / rho, (uy * b.x - ux * b.y) / rho);
-        }
-        cs[(size_t)r * m + j] = cj;
-        sn[(size_t)r * m + j] = sj;
-        col[j] = make_double2(cj.x * a.x + sj.x * b.x - sj.y * b.y, cj.x * a.y + sj.x * b.y + sj.y * b.x);
-        col[j + 1] = make_double2(0.0, 0.0);
-        double2* gv = gvec + (size_t)r * (m + 1);
-        const double2 gj = gv[j];
-        const double2 gn = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
-        gv[j + 1] = gn;
-        gv[j] = make_double2(cj.x * gj.x, cj.x * gj.y);
-        resid[r] = hypot(gn.x, gn.y);
-    }
-    __syncthreads();
-    for (int i = lane; i <= j + 1; i += 64) Hc[i] = col[i];
-}
+
+
+
+
+
 
 // y = H(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution: one wave per
 // right-hand side, g in LDS; step i divides by H(i, i) and removes column i
@@ -381,6 +152,228 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Arnoldi step with device-side control (classical Gram-Schmidt, second pass
+// only where the Daniel-Gragg-Kaufman-Stewart test asks for it: ||w1||^2 <
+// ||w0||^2 / 2).  Every kernel that needs the test re-derives it from the
+// same per-block partial sums in the same order, so all agree bitwise.
+// ---------------------------------------------------------------------------
+constexpr int DOT_ROWS = 2048;               // rows per block of the projection kernel
+constexpr int DOT_RPT = DOT_ROWS / BS;       // rows per thread
+
+__device__ __forceinline__ double sum_parts(const double* __restrict__ p, int r, int nb)
+{
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += p[r * nb + b];
+    return s;
+}
+
+// n0: partials of ||w0||^2 (ns per right-hand side), n1: of ||w1||^2 (nu each)
+__device__ __forceinline__ bool needs_second_pass(const double* __restrict__ n0, int ns,
+                                                  const double* __restrict__ n1, int nu, int r)
+{
+    return sum_parts(n1, r, nu) < 0.5 * sum_parts(n0, r, ns);
+}
+
+// Projection coefficients conj(V_i) . W for a batch of DOT_BATCH basis
+// vectors (grid x), one right-hand side (grid y) and one chunk of DOT_ROWS rows
+// (grid z): every thread accumulates DOT_RPT rows, then one block reduction.
+// part[(r * ns + s) * jc + i]; norm_out (first pass, batch 0) gets the partial
+// of ||W||^2 of the chunk.  With n0 / n1 given this is the second pass and
+// runs only where the test asks for it.
+__global__ __launch_bounds__(BS) void k_cgs_dots(const double2* __restrict__ V, size_t ldv, int nr, int jc,
+                                                 const double2* __restrict__ W, size_t ldw, int n,
+                                                 double2* __restrict__ part, double* __restrict__ norm_out,
+                                                 const double* __restrict__ n0, const double* __restrict__ n1, int nu,
+                                                 const int* __restrict__ active)
+{
+    __shared__ double lds[4 * 2 * DOT_BATCH];
+    const int r = blockIdx.y, sblk = blockIdx.z, ns = gridDim.z;
+    const int i0 = blockIdx.x * DOT_BATCH;
+    if (!active[r]) return;
+    if (n0 && !needs_second_pass(n0, ns, n1, nu, r)) return;
+    double acc[2 * DOT_BATCH];
+#pragma unroll
+    for (int b = 0; b < 2 * DOT_BATCH; ++b) acc[b] = 0.0;
+    double nn[1] = {0.0};
+    const double2* wr = W + (size_t)r * ldw;
+#pragma unroll 2
+    for (int k = 0; k < DOT_RPT; ++k) {
+        const int q = sblk * DOT_ROWS + k * BS + threadIdx.x;
+        if (q >= n) break;
+        const double2 w = wr[q];
+        nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
+#pragma unroll
+        for (int b = 0; b < DOT_BATCH; ++b) {
+            const int i = i0 + b;
+            if (i < jc) {
+                const double2 v = V[((size_t)i * nr + r) * ldv + q];
+                acc[2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * b]));
+                acc[2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * b + 1]));
+            }
+        }
+    }
+    block_sum<2 * DOT_BATCH>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int b = 0; b < DOT_BATCH; ++b)
+            if (i0 + b < jc) part[((size_t)r * ns + sblk) * jc + i0 + b] = make_double2(acc[2 * b], acc[2 * b + 1]);
+    }
+    if (norm_out && blockIdx.x == 0) {
+        block_sum<1>(nn, lds);
+        if (threadIdx.x == 0) norm_out[r * ns + sblk] = nn[0];
+    }
+}
+
+// W -= sum_i h_i V_i with h_i summed from the ns dot partials inside the
+// block; norm_out gets the partials (one per block of BS rows) of the new ||W||^2.
+__global__ __launch_bounds__(BS) void k_cgs_update(const double2* __restrict__ V, size_t ldv, int nr, int jc,
+                                                   const double2* __restrict__ part, int ns, double2* __restrict__ W,
+                                                   size_t ldw, int n, double* __restrict__ norm_out,
+                                                   const double* __restrict__ n0, const double* __restrict__ n1,
+                                                   const int* __restrict__ active)
+{
+    __shared__ double2 h[1024];
+    __shared__ double lds[4];
+    const int r = blockIdx.y;
+    const int nu = gridDim.x;
+    if (!active[r]) return;
+    if (n0 && !needs_second_pass(n0, ns, n1, nu, r)) return;
+    for (int i = threadIdx.x; i < jc; i += BS) {
+        double sr = 0.0, si = 0.0;
+        for (int b = 0; b < ns; ++b) {
+            const double2 v = part[((size_t)r * ns + b) * jc + i];
+            sr += v.x;
+            si += v.y;
+        }
+        h[i] = make_double2(sr, si);
+    }
+    __syncthreads();
+    double nn[1] = {0.0};
+    const int q = blockIdx.x * BS + threadIdx.x;
+    if (q < n) {
+        double2 w = W[(size_t)r * ldw + q];
+        for (int i = 0; i < jc; ++i) {
+            const double2 c = h[i];
+            const double2 v = V[((size_t)i * nr + r) * ldv + q];
+            w.x -= c.x * v.x - c.y * v.y;
+            w.y -= c.x * v.y + c.y * v.x;
+        }
+        W[(size_t)r * ldw + q] = w;
+        nn[0] = fma(w.x, w.x, w.y * w.y);
+    }
+    block_sum<1>(nn, lds);
+    if (threadIdx.x == 0) norm_out[r * nu + blockIdx.x] = nn[0];
+}
+
+// Column j of H from the two passes, ||w||, Givens update, residual estimate,
+// and the stopping decision of this right-hand side (residual estimate below
+// thr[r], or the product budget spent): one wave per right-hand side.
+__global__ __launch_bounds__(64) void k_arnoldi_step(int nr, int j, int m, int ns, int nu, const double2* __restrict__ p1,
+                                                     const double2* __restrict__ p2, const double* __restrict__ n0,
+                                                     const double* __restrict__ n1, const double* __restrict__ n2,
+                                                     double2* __restrict__ H, double2* __restrict__ cs,
+                                                     double2* __restrict__ sn, double2* __restrict__ gvec,
+                                                     double* __restrict__ hnorm, double* __restrict__ resid,
+                                                     const double* __restrict__ thr, int maxit,
+                                                     int* __restrict__ iters, int* __restrict__ kdim,
+                                                     int* __restrict__ active)
+{
+    __shared__ double2 col[1024 + 1];
+    __shared__ double2 lc[1024], ls[1024];
+    __shared__ int two;
+    const int r = blockIdx.x;
+    if (!active[r]) return;
+    const int lane = threadIdx.x;
+    const int jc = j + 1;
+    if (lane == 0) two = needs_second_pass(n0, ns, n1, nu, r) ? 1 : 0;
+    __syncthreads();
+    for (int i = lane; i < jc; i += 64) {
+        double sr = 0.0, si = 0.0;
+        for (int b = 0; b < ns; ++b) {
+            const double2 v = p1[((size_t)r * ns + b) * jc + i];
+            sr += v.x;
+            si += v.y;
+        }
+        if (two) {
+            double tr = 0.0, ti = 0.0;
+            for (int b = 0; b < ns; ++b) {
+                const double2 v = p2[((size_t)r * ns + b) * jc + i];
+                tr += v.x;
+                ti += v.y;
+            }
+            sr += tr;
+            si += ti;
+        }
+        col[i] = make_double2(sr, si);
+    }
+    for (int i = lane; i < j; i += 64) {
+        lc[i] = cs[(size_t)r * m + i];
+        ls[i] = sn[(size_t)r * m + i];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const double nv = sqrt(sum_parts(two ? n2 : n1, r, nu));
+        hnorm[r] = nv;
+        col[j + 1] = make_double2(nv, 0.0);
+        for (int i = 0; i < j; ++i) {
+            const double2 hi = col[i], hn = col[i + 1];
+            const double2 ci = lc[i], si = ls[i];
+            col[i] = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
+                                  ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
+            col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
+                                      -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
+        }
+        const double2 a = col[j], b = col[j + 1];
+        const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+        const double rho = hypot(na, nb);
+        double2 cj, sj;
+        if (rho == 0.0) {
+            cj = make_double2(1.0, 0.0);
+            sj = make_double2(0.0, 0.0);
+        } else if (na == 0.0) {
+            cj = make_double2(0.0, 0.0);
+            sj = make_double2(b.x / nb, -b.y / nb);
+        } else {
+            cj = make_double2(na / rho, 0.0);
+            const double ux = a.x / na, uy = a.y / na;
+            sj = make_double2((ux * b.x + uy * b.y) / rho, (uy * b.x - ux * b.y) / rho);
+        }
+        cs[(size_t)r * m + j] = cj;
+        sn[(size_t)r * m + j] = sj;
+        col[j] = make_double2(cj.x * a.x + sj.x * b.x - sj.y * b.y, cj.x * a.y + sj.x * b.y + sj.y * b.x);
+        col[j + 1] = make_double2(0.0, 0.0);
+        double2* gv = gvec + (size_t)r * (m + 1);
+        const double2 gj = gv[j];
+        const double2 gn = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
+        gv[j + 1] = gn;
+        gv[j] = make_double2(cj.x * gj.x, cj.x * gj.y);
+        const double res = hypot(gn.x, gn.y);
+        resid[r] = res;
+        const int it = iters[r] + 1;
+        iters[r] = it;
+        kdim[r] = jc;
+        // stop on convergence, a spent budget, a breakdown (||w|| = 0) or a non-finite value
+        if (!(res > thr[r]) || it >= maxit || !(nv > 0.0)) active[r] = 0;
+    }
+    __syncthreads();
+    double2* Hc = H + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
+    for (int i = lane; i <= j + 1; i += 64) Hc[i] = col[i];
+}
+
+// V_{j+1} = W / ||W|| for the right-hand sides still running
+__global__ void k_next_basis(const double2* __restrict__ W, size_t ldw, int n, const double* __restrict__ hnorm,
+                             double2* __restrict__ V, size_t ldv, const int* __restrict__ active)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q >= n || !active[r]) return;
+    const double inv = 1.0 / hnorm[r];
+    const double2 w = W[(size_t)r * ldw + q];
+    V[(size_t)r * ldv + q] = make_double2(w.x * inv, w.y * inv);
+}
+
 __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, int nr,
                               const double* __restrict__ rnorm, int m, double2* __restrict__ V, size_t ldv,
                               double2* __restrict__ gvec, const int* __restrict__ active)
@@ -397,27 +390,6 @@ __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, 
     if (q <= m) gvec[(size_t)r * (m + 1) + q] = make_double2(q == 0 ? nv : 0.0, 0.0);
 }
 
-__global__ void k_backsolve(int nr, int m, const double2* __restrict__ H, const double2* __restrict__ gvec,
-                            const int* __restrict__ kdim, double2* __restrict__ y)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const int k = kdim[r];
-    const double2* Hr = H + (size_t)r * (m + 1) * m;
-    double2* yr = y + (size_t)r * 1024;
-    for (int i = k - 1; i >= 0; --i) {
-        double sr = gvec[(size_t)r * (m + 1) + i].x, si = gvec[(size_t)r * (m + 1) + i].y;
-        for (int p = i + 1; p < k; ++p) {
-            const double2 h = Hr[i + (size_t)p * (m + 1)], v = yr[p];
-            sr -= h.x * v.x - h.y * v.y;
-            si -= h.x * v.y + h.y * v.x;
-        }
-        const double2 d = Hr[i + (size_t)i * (m + 1)];
-        const double den = d.x * d.x + d.y * d.y;
-        yr[i] = den > 0.0 ? make_double2((sr * d.x + si * d.y) / den, (si * d.x - sr * d.y) / den)
-                          : make_double2(0.0, 0.0);
-    }
-}
 
 __global__ void k_xupdate(const double2* __restrict__ V, size_t ldv, int nr, int n, const double2* __restrict__ y,
                           const int* __restrict__ kdim, double2* __restrict__ X, size_t ldx)
@@ -562,54 +534,28 @@ hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double*
     return hipGetLastError();
 }
 
-hipError_t launch_dots(const double2* V, size_t ldv, int nr, int jcount, const double2* W, size_t ldw, int n,
-                       double2* partial, double2* h, const int* active, hipStream_t s)
-{
-    const int nblk = (n + BS - 1) / BS;
-    hipLaunchKernelGGL(k_dots, dim3(nblk, nr), dim3(BS), 0, s, V, ldv, nr, jcount, W, ldw, n, partial, active);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(nr), dim3(128), 0, s, partial, nblk, nr, jcount, h, active);
-    return hipGetLastError();
-}
+int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + DOT_ROWS - 1) / DOT_ROWS); }
 
-hipError_t launch_update(const double2* V, size_t ldv, int nr, int jcount, const double2* h, double2* W,
-                         size_t ldw, int n, const int* active, double* norm_part, hipStream_t s)
+hipError_t launch_arnoldi(double2* V, size_t ldv, int nr, int j, int m, int n, double2* W, size_t ldw,
+                          double2* p1, double2* p2, double* n0, double* n1, double* n2, double2* H, double2* cs,
+                          double2* sn, double2* gvec, double* hnorm, double* resid, const double* thr, int maxit,
+                          int* iters, int* kdim, int* active, hipStream_t s)
 {
-    const int nblk = (n + BS - 1) / BS;
-    hipLaunchKernelGGL(k_update, dim3(nblk, nr), dim3(BS), 0, s, V, ldv, nr, jcount, h, W, ldw, n, active,
-                       norm_part);
-    return hipGetLastError();
-}
-
-hipError_t launch_arnoldi_finish(int nr, int j, int m, const double2* h1, const double2* h2,
-                                 const double* norm_part, int nblk, double2* H, double* hnorm, const int* active,
-                                 hipStream_t s)
-{
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(nr), dim3(128), 0, s, nr, j, m, h1, h2, norm_part, nblk, H, hnorm,
+    const int ns = (n + DOT_ROWS - 1) / DOT_ROWS;  // row chunks of the projection kernel
+    const int nu = (n + BS - 1) / BS;              // blocks of the update kernel
+    const int jc = j + 1;
+    dim3 gd((jc + DOT_BATCH - 1) / DOT_BATCH, nr, ns);
+    dim3 gu(nu, nr);
+    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, p1, n0, nullptr, nullptr, nu,
                        active);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale_into(const double2* W, size_t ldw, int n, int nr, const double* hnorm, double2* V,
-                             size_t ldv, const int* active, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scale_into, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, W, ldw, n, hnorm, V, ldv, nr,
+    hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p1, ns, W, ldw, n, n1, nullptr, nullptr,
                        active);
-    return hipGetLastError();
-}
-
-hipError_t launch_arnoldi_givens(int nr, int j, int m, const double2* h1, const double2* h2,
-                                 const double* norm_part, int nblk, double2* H, double2* cs, double2* sn,
-                                 double2* gvec, double* hnorm, double* resid, const int* active, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_arnoldi_givens, dim3(nr), dim3(64), 0, s, nr, j, m, h1, h2, norm_part, nblk, H, cs, sn, gvec,
-                       hnorm, resid, active);
-    return hipGetLastError();
-}
-
-hipError_t launch_givens(int nr, int j, int m, double2* H, double2* cs, double2* sn, double2* gvec, double* resid,
-                         const int* active, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_givens, dim3((nr + 63) / 64), dim3(64), 0, s, nr, j, m, H, cs, sn, gvec, resid, active);
+    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, p2, nullptr, n0, n1, nu, active);
+    hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p2, ns, W, ldw, n, n2, n0, n1, active);
+    hipLaunchKernelGGL(k_arnoldi_step, dim3(nr), dim3(64), 0, s, nr, j, m, ns, nu, p1, p2, n0, n1, n2, H, cs, sn,
+                       gvec, hnorm, resid, thr, maxit, iters, kdim, active);
+    hipLaunchKernelGGL(k_next_basis, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, W, ldw, n, hnorm,
+                       V + (size_t)jc * nr * ldv, ldv, active);
     return hipGetLastError();
 }
 
