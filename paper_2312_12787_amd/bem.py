@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbem_hip.so")
+LIB_PATH = os.environ.get("BEM_LIB_PATH") or os.path.join(_HERE, "libbem_hip.so")
 
 F64, F32 = 0, 1
 CALDERON, CALDERON_BETA1, CONVENTIONAL, CALDERON_ORIG = 0, 1, 2, 3

@@ -14,6 +14,16 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr double EULER = 0.57721566490153286061;
+// Assembly kernels: minimum waves per SIMD (1: the compiler may keep every
+// polynomial coefficient and two interleaved Gauss points in registers; a
+// higher floor forces scratch spills, measured 2-7x slower on gfx950) and
+// Gauss points unrolled together.
+#ifndef ASM_WAVES_PER_SIMD
+#define ASM_WAVES_PER_SIMD 1
+#endif
+#ifndef ASM_GAUSS_UNROLL
+#define ASM_GAUSS_UNROLL 2
+#endif
 
 template <class T>
 __device__ __forceinline__ const T* tab(const char* g, size_t off) { return reinterpret_cast<const T*>(g + off); }
@@ -132,114 +142,45 @@ __device__ void build_wave(cd k, WaveConst& W)
     const cd xk = cdiv({HANKEL_XS_F64, 0.0}, k);  // XS / k
     W.ur = xk.re;
     W.ui = xk.im;
+    const cd w = cmul(xk, xk);
+    W.wr = w.re;
+    W.wi = w.im;
     const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));  // sqrt(2/(pi k))
     const double c4 = 0.70710678118654752440;
     W.a0r = sq.re * c4 + sq.im * c4;  // * e^{-i pi/4} = (1 - i)/sqrt2
     W.a0i = sq.im * c4 - sq.re * c4;
     W.a1r = -sq.re * c4 + sq.im * c4;  // * e^{-3 i pi/4} = (-1 - i)/sqrt2
     W.a1i = -sq.im * c4 - sq.re * c4;
-    const cd lk = clog_(cscale(k, 0.5));
-    W.lk0r = (2.0 / PI) * (lk.re + EULER);
-    W.lk0i = (2.0 / PI) * lk.im;
-    W.lk1r = (2.0 / PI) * lk.re;
-    W.lk1i = (2.0 / PI) * lk.im;
+    const cd h = cscale(k, 0.5);
+    W.hr = h.re;
+    W.hi = h.im;
+    const cd t = cmul(h, h);
+    W.tr = t.re;
+    W.ti = t.im;
+    const cd lk = clog_(h);
+    W.lkr = lk.re;
+    W.lki = lk.im;
     const cd y1 = cdiv({-2.0 / PI, 0.0}, k);
     W.y1r = y1.re;
     W.y1i = y1.im;
-    // amplitude polynomials: a_m w^m with w = (XS/k)^2 rho
-    const cd w1 = cmul(xk, xk);
-    cd pw = {1.0, 0.0};
-    for (int m = 0; m < NAMP; ++m) {
-        W.m0r[m] = HANKEL_M0_F64[m] * pw.re;
-        W.m0i[m] = HANKEL_M0_F64[m] * pw.im;
-        W.n0r[m] = HANKEL_N0_F64[m] * pw.re;
-        W.n0i[m] = HANKEL_N0_F64[m] * pw.im;
-        W.m1r[m] = HANKEL_M1_F64[m] * pw.re;
-        W.m1i[m] = HANKEL_M1_F64[m] * pw.im;
-        W.n1r[m] = HANKEL_N1_F64[m] * pw.re;
-        W.n1i[m] = HANKEL_N1_F64[m] * pw.im;
-        pw = cmul(pw, w1);
-    }
-    // ascending series: t = -k^2/4
-    const cd t = cscale(cmul(k, k), -0.25);
-    cd c0 = {1.0, 0.0};                  // (-k^2/4)^m / (m!)^2
-    cd c1 = cscale(k, 0.5);              // (k/2) (-k^2/4)^m / (m! (m+1)!)
-    double hm = 0.0;                     // harmonic number H_m
-    for (int m = 0; m < NSER; ++m) {
-        if (m > 0) {
-            c0 = cscale(cmul(c0, t), 1.0 / ((double)m * m));
-            c1 = cscale(cmul(c1, t), 1.0 / ((double)m * (m + 1)));
-            hm += 1.0 / m;
-        }
-        W.j0r[m] = c0.re;
-        W.j0i[m] = c0.im;
-        // Y0 remainder: -(2/pi) H_m c0_m  (m >= 1)
-        W.e0r[m] = (m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.re;
-        W.e0i[m] = (m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.im;
-        W.j1r[m] = c1.re;
-        W.j1i[m] = c1.im;
-        // Y1 remainder: -(1/pi)(psi(m+1) + psi(m+2)) c1_m, psi(m+1) = H_m - gamma
-        const double ps = (hm - EULER) + (hm + 1.0 / (m + 1) - EULER);
-        W.e1r[m] = -(1.0 / PI) * ps * c1.re;
-        W.e1i[m] = -(1.0 / PI) * ps * c1.im;
-    }
 }
 
 __device__ void build_wave32(cd k, WaveConst32& W)
 {
     const double ak = hypot(k.re, k.im);
-    W.kr = (float)k.re;
-    W.ki = (float)k.im;
     W.r2_small = (float)((HANKEL_XS_F32 / ak) * (HANKEL_XS_F32 / ak));
     const cd xk = cdiv({HANKEL_XS_F32, 0.0}, k);
     W.ur = (float)xk.re;
     W.ui = (float)xk.im;
+    const cd w = cmul(xk, xk);
+    W.wr = (float)w.re;
+    W.wi = (float)w.im;
     const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));
     const double c4 = 0.70710678118654752440;
     W.a0r = (float)(sq.re * c4 + sq.im * c4);
     W.a0i = (float)(sq.im * c4 - sq.re * c4);
     W.a1r = (float)(-sq.re * c4 + sq.im * c4);
     W.a1i = (float)(-sq.im * c4 - sq.re * c4);
-    const cd lk = clog_(cscale(k, 0.5));
-    W.lk0r = (float)((2.0 / PI) * (lk.re + EULER));
-    W.lk0i = (float)((2.0 / PI) * lk.im);
-    W.lk1r = (float)((2.0 / PI) * lk.re);
-    W.lk1i = (float)((2.0 / PI) * lk.im);
-    const cd y1 = cdiv({-2.0 / PI, 0.0}, k);
-    W.y1r = (float)y1.re;
-    W.y1i = (float)y1.im;
-    const cd w1 = cmul(xk, xk);
-    cd pw = {1.0, 0.0};
-    for (int m = 0; m < NAMP32; ++m) {
-        W.m0r[m] = (float)(HANKEL_M0_F32[m] * pw.re);
-        W.m0i[m] = (float)(HANKEL_M0_F32[m] * pw.im);
-        W.n0r[m] = (float)(HANKEL_N0_F32[m] * pw.re);
-        W.n0i[m] = (float)(HANKEL_N0_F32[m] * pw.im);
-        W.m1r[m] = (float)(HANKEL_M1_F32[m] * pw.re);
-        W.m1i[m] = (float)(HANKEL_M1_F32[m] * pw.im);
-        W.n1r[m] = (float)(HANKEL_N1_F32[m] * pw.re);
-        W.n1i[m] = (float)(HANKEL_N1_F32[m] * pw.im);
-        pw = cmul(pw, w1);
-    }
-    const cd t = cscale(cmul(k, k), -0.25);
-    cd c0 = {1.0, 0.0}, c1 = cscale(k, 0.5);
-    double hm = 0.0;
-    for (int m = 0; m < NSER32; ++m) {
-        if (m > 0) {
-            c0 = cscale(cmul(c0, t), 1.0 / ((double)m * m));
-            c1 = cscale(cmul(c1, t), 1.0 / ((double)m * (m + 1)));
-            hm += 1.0 / m;
-        }
-        W.j0r[m] = (float)c0.re;
-        W.j0i[m] = (float)c0.im;
-        W.e0r[m] = (float)((m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.re);
-        W.e0i[m] = (float)((m == 0) ? 0.0 : -(2.0 / PI) * hm * c0.im);
-        W.j1r[m] = (float)c1.re;
-        W.j1i[m] = (float)c1.im;
-        const double ps = (hm - EULER) + (hm + 1.0 / (m + 1) - EULER);
-        W.e1r[m] = (float)(-(1.0 / PI) * ps * c1.re);
-        W.e1i[m] = (float)(-(1.0 / PI) * ps * c1.im);
-    }
 }
 
 __global__ void k_domains(char* g, GeomLayout L)
@@ -387,7 +328,7 @@ __device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, co
         const bool diag = (j == i);
         if (!diag) {
             const GaussRec& G = gq[j];
-#pragma unroll
+#pragma unroll ASM_GAUSS_UNROLL
             for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
                 if (Q == 0 && g >= q) break;
                 const double rx = xi - G.x[g], ry = yi - G.y[g];
@@ -438,20 +379,19 @@ __device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, co
     }
 }
 
-template <int Q>
-__global__ __launch_bounds__(ROW_TILE) void k_assemble_f64(const char* __restrict__ g, GeomLayout L, int N,
-                                                            int n_if, int q_rt, double2* __restrict__ A,
-                                                            size_t lda)
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f64(const char* __restrict__ g, GeomLayout L,
+                                                                                int N, int n_if, int q_rt,
+                                                                                const int* __restrict__ tiles, int side,
+                                                                                double2* __restrict__ A, size_t lda)
 {
-    const Tile rt = tab<Tile>(g, L.rtiles)[blockIdx.x];
+    const Tile rt = tab<Tile>(g, L.rtiles)[tiles[blockIdx.x]];
     const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
-    const int side = blockIdx.z;
     const int li = threadIdx.x;
     if (li >= rt.count) return;
     const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
     const int d = side ? P.dr : P.dl;
     const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
-    const bool bm = side ? (P.bm_r != 0) : false;
     const int i = rt.start + li;
     const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
     if (sg == 0) {
@@ -469,20 +409,10 @@ __global__ __launch_bounds__(ROW_TILE) void k_assemble_f64(const char* __restric
     const ElemRec Ei = el[i];
     cd selfS = {0.0, 0.0};
     if (i >= cc.start && i < cc.start + cc.count) {
-        const double2 s = tab<double2>(g, L.self)[(size_t)d * N + i];
-        selfS = {s.x, s.y};
+        const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
+        selfS = {sv.x, sv.y};
     }
-    if (bm) {
-        if (Dm.cplx)
-            assemble_side<Q, true, true>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
-        else
-            assemble_side<Q, false, true>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
-    } else {
-        if (Dm.cplx)
-            assemble_side<Q, true, false>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
-        else
-            assemble_side<Q, false, false>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
-    }
+    assemble_side<Q, CPLX, BM>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
 }
 
 
@@ -498,26 +428,6 @@ struct cf {
     float re, im;
 };
 __device__ __forceinline__ cf cmulf(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-
-template <int N>
-__device__ __forceinline__ float hornerf(const float* __restrict__ c, float x)
-{
-    float acc = c[N - 1];
-#pragma unroll
-    for (int m = N - 2; m >= 0; --m) acc = fmaf(acc, x, c[m]);
-    return acc;
-}
-template <int N>
-__device__ __forceinline__ cf hornerf_c(const float* __restrict__ cr, const float* __restrict__ ci, float x)
-{
-    float ar = cr[N - 1], ai = ci[N - 1];
-#pragma unroll
-    for (int m = N - 2; m >= 0; --m) {
-        ar = fmaf(ar, x, cr[m]);
-        ai = fmaf(ai, x, ci[m]);
-    }
-    return {ar, ai};
-}
 
 // H0, H1 at k r with r given in FP64; result in FP32.
 template <bool CPLX>
@@ -542,15 +452,21 @@ __device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveC
     const float rho = rinv * rinv;
     const float srinv = sqrtf(rinv);
     if (!CPLX) {
-        const float m0 = hornerf<NAMP32>(W.m0r, rho), n0 = hornerf<NAMP32>(W.n0r, rho);
-        const float m1 = hornerf<NAMP32>(W.m1r, rho), n1 = hornerf<NAMP32>(W.n1r, rho);
+        const float w = W.wr * rho;
+        const float m0 = poly_real(HANKEL_M0_F32, w), n0 = poly_real(HANKEL_N0_F32, w);
+        const float m1 = poly_real(HANKEL_M1_F32, w), n1 = poly_real(HANKEL_N1_F32, w);
         const float u = W.ur * rinv;
         const cf e = {cs * srinv, sn * srinv};
         h0 = cmulf(cmulf(e, {W.a0r, W.a0i}), {m0, u * n0});
         h1 = cmulf(cmulf(e, {W.a1r, W.a1i}), {m1, u * n1});
     } else {
-        const cf m0 = hornerf_c<NAMP32>(W.m0r, W.m0i, rho), n0 = hornerf_c<NAMP32>(W.n0r, W.n0i, rho);
-        const cf m1 = hornerf_c<NAMP32>(W.m1r, W.m1i, rho), n1 = hornerf_c<NAMP32>(W.n1r, W.n1i, rho);
+        const float x = W.wr * rho, y = W.wi * rho;
+        const float R = 2.0f * x, S = fmaf(x, x, y * y);
+        cf m0, n0, m1, n1;
+        poly_cplx(HANKEL_M0_F32, x, y, R, S, m0.re, m0.im);
+        poly_cplx(HANKEL_N0_F32, x, y, R, S, n0.re, n0.im);
+        poly_cplx(HANKEL_M1_F32, x, y, R, S, m1.re, m1.im);
+        poly_cplx(HANKEL_N1_F32, x, y, R, S, n1.re, n1.im);
         const cf u = {W.ur * rinv, W.ui * rinv};
         const cf un0 = cmulf(u, n0), un1 = cmulf(u, n1);
         const float damp = (float)exp(-W64.ki * r) * srinv;
@@ -605,7 +521,7 @@ __device__ __forceinline__ void assemble_side_f32(const ElemRec* __restrict__ el
         if (!diag) {
             const GaussRec& G = gq[j];
             const float njx = (float)Ej.nx, njy = (float)Ej.ny;
-#pragma unroll
+#pragma unroll ASM_GAUSS_UNROLL
             for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
                 if (Q == 0 && g >= q) break;
                 const double rx = xi - G.x[g], ry = yi - G.y[g];
@@ -663,19 +579,19 @@ __device__ __forceinline__ void assemble_side_f32(const ElemRec* __restrict__ el
     }
 }
 
-template <int Q>
-__global__ __launch_bounds__(ROW_TILE) void k_assemble_f32(const char* __restrict__ g, GeomLayout L, int N,
-                                                            int n_if, int q_rt, float2* __restrict__ A, size_t lda)
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f32(const char* __restrict__ g, GeomLayout L,
+                                                                                int N, int n_if, int q_rt,
+                                                                                const int* __restrict__ tiles, int side,
+                                                                                float2* __restrict__ A, size_t lda)
 {
-    const Tile rt = tab<Tile>(g, L.rtiles)[blockIdx.x];
+    const Tile rt = tab<Tile>(g, L.rtiles)[tiles[blockIdx.x]];
     const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
-    const int side = blockIdx.z;
     const int li = threadIdx.x;
     if (li >= rt.count) return;
     const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
     const int d = side ? P.dr : P.dl;
     const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
-    const bool bm = side ? (P.bm_r != 0) : false;
     const int i = rt.start + li;
     const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
     if (sg == 0) {
@@ -697,21 +613,7 @@ __global__ __launch_bounds__(ROW_TILE) void k_assemble_f32(const char* __restric
         const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
         selfS = {sv.x, sv.y};
     }
-    if (bm) {
-        if (Dm.cplx)
-            assemble_side_f32<Q, true, true>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
-                                             row, N);
-        else
-            assemble_side_f32<Q, false, true>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
-                                              row, N);
-    } else {
-        if (Dm.cplx)
-            assemble_side_f32<Q, true, false>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda,
-                                              row, N);
-        else
-            assemble_side_f32<Q, false, false>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A,
-                                               lda, row, N);
-    }
+    assemble_side_f32<Q, CPLX, BM>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
 }
 }  // namespace
 
@@ -727,29 +629,54 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
-                               int q, double2* A, size_t lda, hipStream_t s)
+// One launch per variant (side of the interface, row type, complex wavenumber)
+// over the row tiles of that variant; lists[v] / counts[v] are device / host.
+template <class T2, bool F64, int Q>
+void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
+                     const int* const* lists, const int* counts, T2* A, size_t lda, hipStream_t s)
 {
-    dim3 grid(n_rtiles, n_cchunks, 2);
+    for (int v = 0; v < ASM_VARIANTS; ++v) {
+        if (counts[v] == 0) continue;
+        const int side = v >> 2 & 1, bm = v >> 1 & 1, cplx = v & 1;
+        dim3 grid(counts[v], n_cchunks, 1);
+#define BEM_ASM_LAUNCH(C_, B_)                                                                                  \
+    if (cplx == C_ && bm == B_) {                                                                               \
+        if constexpr (F64)                                                                                      \
+            hipLaunchKernelGGL((k_assemble_f64<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
+                               side, reinterpret_cast<double2*>(A), lda);                                        \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_assemble_f32<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
+                               side, reinterpret_cast<float2*>(A), lda);                                         \
+    }
+        BEM_ASM_LAUNCH(false, false)
+        BEM_ASM_LAUNCH(true, false)
+        BEM_ASM_LAUNCH(false, true)
+        BEM_ASM_LAUNCH(true, true)
+#undef BEM_ASM_LAUNCH
+    }
+}
+
+hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
+                               const int* const* lists, const int* counts, double2* A, size_t lda, hipStream_t s)
+{
     if (q == 8)
-        hipLaunchKernelGGL(k_assemble_f64<8>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     else if (q == 10)
-        hipLaunchKernelGGL(k_assemble_f64<10>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     else
-        hipLaunchKernelGGL(k_assemble_f64<0>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
-                               int q, float2* A, size_t lda, hipStream_t s)
+hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
+                               const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s)
 {
-    dim3 grid(n_rtiles, n_cchunks, 2);
     if (q == 8)
-        hipLaunchKernelGGL(k_assemble_f32<8>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     else if (q == 10)
-        hipLaunchKernelGGL(k_assemble_f32<10>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     else
-        hipLaunchKernelGGL(k_assemble_f32<0>, grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, A, lda);
+        launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
     return hipGetLastError();
 }
 

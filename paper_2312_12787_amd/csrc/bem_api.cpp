@@ -94,6 +94,8 @@ struct bem_problem {
     std::vector<IfacePlan> iface;
     std::vector<int> sigma;        // [d * n_if + m]
     std::vector<Tile> rtiles, cchunks;
+    std::vector<int> vtiles;                     // row-tile ids grouped by assembly variant
+    int vcount[bemk::ASM_VARIANTS] = {0}, voff[bemk::ASM_VARIANTS] = {0};
     std::vector<int> elif;          // interface of each element
     std::vector<int> elnodes;       // (a, b) node indices per element
     bemk::DomIn dummy{};
@@ -139,6 +141,7 @@ GeomLayout make_layout(const bem_problem* p)
     L.sigma = take((size_t)p->n_dom * p->n_if * sizeof(int));
     L.dom_in = take((size_t)p->n_dom * sizeof(bemk::DomIn));
     L.glob_in = take(sizeof(bemk::GlobalIn));
+    L.vtiles = take(p->vtiles.size() * sizeof(int) + sizeof(int));
     size_t upload_end = off;
     (void)upload_end;
     L.elem = take((size_t)p->N * sizeof(bemk::ElemRec));
@@ -345,6 +348,24 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
         for (int s = 0; s < P.count; s += bemk::COL_CHUNK)
             p->cchunks.push_back(Tile{m, P.off + s, std::min(bemk::COL_CHUNK, P.count - s), 0});
     }
+    // row tiles grouped by assembly variant (side, row type, complex wavenumber)
+    {
+        std::vector<std::vector<int>> lists(bemk::ASM_VARIANTS);
+        for (size_t t = 0; t < p->rtiles.size(); ++t) {
+            const IfacePlan& P = p->iface[p->rtiles[t].iface];
+            for (int side = 0; side < 2; ++side) {
+                const int d = side ? P.dr : P.dl;
+                const int bm = side ? P.bm_r : 0;
+                const int cplx = p->k[d].imag() != 0.0;
+                lists[side * 4 + bm * 2 + cplx].push_back((int)t);
+            }
+        }
+        for (int v = 0; v < bemk::ASM_VARIANTS; ++v) {
+            p->voff[v] = (int)p->vtiles.size();
+            p->vcount[v] = (int)lists[v].size();
+            p->vtiles.insert(p->vtiles.end(), lists[v].begin(), lists[v].end());
+        }
+    }
     // inputs for the device-side constant tables
     p->dom_in.resize(p->n_dom);
     for (int d = 0; d < p->n_dom; ++d) {
@@ -448,6 +469,7 @@ bem_status bem_geometry(bem_problem* p, void* geom_dev, size_t geom_bytes, hipSt
     put(L.sigma, p->sigma.data(), p->sigma.size() * sizeof(int));
     put(L.dom_in, p->dom_in.data(), p->dom_in.size() * sizeof(bemk::DomIn));
     put(L.glob_in, &p->glob, sizeof(bemk::GlobalIn));
+    put(L.vtiles, p->vtiles.data(), p->vtiles.size() * sizeof(int));
     char* g = static_cast<char*>(geom_dev);
     HIP_OK(hipMemcpyAsync(g, img.data(), img.size(), hipMemcpyHostToDevice, stream));
     HIP_OK(bemk::launch_setup(g, L, p->N, p->n_dom, p->quad, stream));
@@ -479,12 +501,15 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
     if (lda < n) return fail(BEM_E_ARG, "lda < n");
     const int nrt = (int)p->rtiles.size(), ncc = (int)p->cchunks.size();
     if (nrt > 65535 || ncc > 65535) return fail(BEM_E_ARG, "problem too large for one assembly grid");
+    const int* lists[bemk::ASM_VARIANTS];
+    for (int v = 0; v < bemk::ASM_VARIANTS; ++v)
+        lists[v] = reinterpret_cast<const int*>(p->geom + p->L.vtiles) + p->voff[v];
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
     if (prec == BEM_F64)
-        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, nrt, ncc, p->quad,
+        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
                                          static_cast<double2*>(A_dev), lda, stream));
     else
-        HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, nrt, ncc, p->quad,
+        HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
                                          static_cast<float2*>(A_dev), lda, stream));
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 1, stream);
     p->A = A_dev;

@@ -2,22 +2,23 @@
 // wavenumber k (Im k >= 0) and many distances r > 0 (fundamental solution,
 // eq. (fundamental_sol), and its derivative).
 //
-// Two regimes, chosen per lane by |k r| against XS:
-//  * |k r| < XS: ascending series (DLMF 10.2.2, 10.8.1, 10.8.2) written as
-//    polynomials in s = r^2 whose coefficients already carry the powers of k
-//    (built once per wavenumber by the setup kernel):
-//        J0 = sum j0_m s^m,        Y0 = (2/pi) ln r J0 + lk0 J0 + sum e0_m s^m,
-//        J1 = r sum j1_m s^m,      Y1 = y1 / r + ((2/pi) ln r + lk1) J1 + r sum e1_m s^m;
-//    ln(k r / 2) = ln r + ln(k / 2) splits the logarithm into a real part per
-//    lane and a per-wavenumber constant.
+// Every polynomial has compile-time real coefficients (hankel_tables.h); the
+// wavenumber enters only through the argument, so a launch keeps a handful
+// of per-wavenumber constants (WaveConst) instead of coefficient tables.
+//  * |k r| < XS: ascending series (DLMF 10.2.2, 10.8.1, 10.8.2) in
+//    t = (k r / 2)^2 = (k/2)^2 r^2:
+//        J0 = J0(t),  Y0 = (2/pi)(ln(kr/2) + gamma) J0 + E0(t),
+//        J1 = (kr/2) J1(t),  Y1 = -(2/pi)/(k r) + (2/pi) ln(kr/2) J1 + (kr/2) E1(t),
+//    with ln(kr/2) = ln r + ln(k/2) (a real logarithm per lane);
 //  * |k r| >= XS: H_nu = sqrt(2/(pi k)) r^{-1/2} e^{i(k r - nu pi/2 - pi/4)} P_nu,
-//    P_nu = m_nu(w) + i (XS/(k r)) n_nu(w), w = (XS/(k r))^2, with m, n the
-//    fitted amplitude polynomials; with rho = 1/r^2 they are polynomials in
-//    rho whose (complex) coefficients are a_m (XS/k)^(2m).
-// For real k every polynomial has real coefficients (CPLX = false); for lossy
-// media the same code runs on complex coefficients (CPLX = true).
+//    P_nu = m_nu(w) + i (XS/(k r)) n_nu(w),  w = (XS/k)^2 / r^2, with m, n the
+//    fitted amplitude polynomials.
+// Real k: Horner in a real argument.  Complex k (lossy media): the same real
+// polynomials at a complex argument z = x + i y by dividing out the quadratic
+// z^2 - 2 x z + |z|^2 (Knuth's scheme): two multiply-adds per coefficient.
 #pragma once
 
+#include "hankel_tables.h"
 #include "internal.h"
 
 namespace bemk {
@@ -30,26 +31,32 @@ __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.
 __device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
 
-template <int N>
-__device__ __forceinline__ double horner(const double* __restrict__ c, double x)
+// sum_m c[m] x^m, x real
+template <int N, class T>
+__device__ __forceinline__ T poly_real(const T (&c)[N], T x)
 {
-    double acc = c[N - 1];
+    T acc = c[N - 1];
 #pragma unroll
     for (int m = N - 2; m >= 0; --m) acc = fma(acc, x, c[m]);
     return acc;
 }
 
-// complex coefficients (re[], im[]) at a real argument
-template <int N>
-__device__ __forceinline__ cd horner_c(const double* __restrict__ cr, const double* __restrict__ ci, double x)
+// sum_m c[m] z^m at complex z = x + i y for real c: with R = 2x, S = |z|^2,
+// b_{N-1} = c_{N-1}, b_{N-2} = c_{N-2} + R b_{N-1}, b_m = c_m + R b_{m+1} - S b_{m+2},
+// p(z) = (x b_1 + c_0 - S b_2) + i y b_1.   (N >= 3)
+template <int N, class T>
+__device__ __forceinline__ void poly_cplx(const T (&c)[N], T x, T y, T R, T S, T& pr, T& pi)
 {
-    double ar = cr[N - 1], ai = ci[N - 1];
+    T b2 = c[N - 1];
+    T b1 = fma(R, b2, c[N - 2]);
 #pragma unroll
-    for (int m = N - 2; m >= 0; --m) {
-        ar = fma(ar, x, cr[m]);
-        ai = fma(ai, x, ci[m]);
+    for (int m = N - 3; m >= 1; --m) {
+        const T b0 = fma(R, b1, fma(-S, b2, c[m]));
+        b2 = b1;
+        b1 = b0;
     }
-    return {ar, ai};
+    pr = fma(x, b1, fma(-S, b2, c[0]));
+    pi = y * b1;
 }
 
 // H0(k r), H1(k r).  r2 = r^2, rinv = 1/r, srinv = r^{-1/2}.
@@ -58,26 +65,34 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
                                          cd& h1)
 {
     constexpr double TWO_OVER_PI = 0.63661977236758134308;
+    constexpr double EULER = 0.57721566490153286061;
     if (r2 < W.r2_small) {
         const double lnr = log(r);
-        const double tl = TWO_OVER_PI * lnr;
         if (!CPLX) {
-            const double j0 = horner<NSER>(W.j0r, r2);
-            const double e0 = horner<NSER>(W.e0r, r2);
-            const double j1 = r * horner<NSER>(W.j1r, r2);
-            const double e1 = horner<NSER>(W.e1r, r2);
-            const double y0 = fma(tl + W.lk0r, j0, e0);
-            const double y1 = fma(W.y1r, rinv, fma(tl + W.lk1r, j1, r * e1));
+            const double t = W.tr * r2;
+            const double j0 = poly_real(SERIES_J0, t);
+            const double e0 = poly_real(SERIES_E0, t);
+            const double zh = W.hr * r;
+            const double j1 = zh * poly_real(SERIES_J1, t);
+            const double e1 = poly_real(SERIES_E1, t);
+            const double lz = lnr + W.lkr;
+            const double y0 = fma(TWO_OVER_PI * (lz + EULER), j0, e0);
+            const double y1 = fma(W.y1r, rinv, fma(TWO_OVER_PI * lz, j1, zh * e1));
             h0 = {j0, y0};
             h1 = {j1, y1};
         } else {
-            const cd j0 = horner_c<NSER>(W.j0r, W.j0i, r2);
-            const cd e0 = horner_c<NSER>(W.e0r, W.e0i, r2);
-            cd j1 = horner_c<NSER>(W.j1r, W.j1i, r2);
-            j1 = cscale(j1, r);
-            const cd e1 = horner_c<NSER>(W.e1r, W.e1i, r2);
-            const cd y0 = cadd(cmul({tl + W.lk0r, W.lk0i}, j0), e0);
-            const cd y1 = cadd(cadd(cscale({W.y1r, W.y1i}, rinv), cmul({tl + W.lk1r, W.lk1i}, j1)), cscale(e1, r));
+            const double x = W.tr * r2, y = W.ti * r2;
+            const double R = 2.0 * x, S = fma(x, x, y * y);
+            cd j0, e0, p1, e1;
+            poly_cplx(SERIES_J0, x, y, R, S, j0.re, j0.im);
+            poly_cplx(SERIES_E0, x, y, R, S, e0.re, e0.im);
+            poly_cplx(SERIES_J1, x, y, R, S, p1.re, p1.im);
+            poly_cplx(SERIES_E1, x, y, R, S, e1.re, e1.im);
+            const cd zh = {W.hr * r, W.hi * r};
+            const cd j1 = cmul(zh, p1);
+            const cd lz = {lnr + W.lkr, W.lki};
+            const cd y0 = cadd(cmul({TWO_OVER_PI * (lz.re + EULER), TWO_OVER_PI * lz.im}, j0), e0);
+            const cd y1 = cadd(cadd(cscale({W.y1r, W.y1i}, rinv), cmul(cscale(lz, TWO_OVER_PI), j1)), cmul(zh, e1));
             h0 = {j0.re - y0.im, j0.im + y0.re};
             h1 = {j1.re - y1.im, j1.im + y1.re};
         }
@@ -86,21 +101,21 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
         double sn, cs;
         sincos(W.kr * r, &sn, &cs);
         if (!CPLX) {
-            const double m0 = horner<NAMP>(W.m0r, rho);
-            const double n0 = horner<NAMP>(W.n0r, rho);
-            const double m1 = horner<NAMP>(W.m1r, rho);
-            const double n1 = horner<NAMP>(W.n1r, rho);
+            const double w = W.wr * rho;
+            const double m0 = poly_real(HANKEL_M0_F64, w), n0 = poly_real(HANKEL_N0_F64, w);
+            const double m1 = poly_real(HANKEL_M1_F64, w), n1 = poly_real(HANKEL_N1_F64, w);
             const double u = W.ur * rinv;
             const cd e = {cs * srinv, sn * srinv};
-            const cd p0 = {m0, u * n0};
-            const cd p1 = {m1, u * n1};
-            h0 = cmul(cmul(e, {W.a0r, W.a0i}), p0);
-            h1 = cmul(cmul(e, {W.a1r, W.a1i}), p1);
+            h0 = cmul(cmul(e, {W.a0r, W.a0i}), {m0, u * n0});
+            h1 = cmul(cmul(e, {W.a1r, W.a1i}), {m1, u * n1});
         } else {
-            const cd m0 = horner_c<NAMP>(W.m0r, W.m0i, rho);
-            const cd n0 = horner_c<NAMP>(W.n0r, W.n0i, rho);
-            const cd m1 = horner_c<NAMP>(W.m1r, W.m1i, rho);
-            const cd n1 = horner_c<NAMP>(W.n1r, W.n1i, rho);
+            const double x = W.wr * rho, y = W.wi * rho;
+            const double R = 2.0 * x, S = fma(x, x, y * y);
+            cd m0, n0, m1, n1;
+            poly_cplx(HANKEL_M0_F64, x, y, R, S, m0.re, m0.im);
+            poly_cplx(HANKEL_N0_F64, x, y, R, S, n0.re, n0.im);
+            poly_cplx(HANKEL_M1_F64, x, y, R, S, m1.re, m1.im);
+            poly_cplx(HANKEL_N1_F64, x, y, R, S, n1.re, n1.im);
             const cd u = {W.ur * rinv, W.ui * rinv};
             const cd un0 = cmul(u, n0), un1 = cmul(u, n1);
             const cd p0 = {m0.re - un0.im, m0.im + un0.re};

@@ -12,10 +12,6 @@
 namespace bemk {
 
 constexpr int QMAX = 16;      // largest Gauss rule
-constexpr int NAMP = 15;      // coefficients of each FP64 amplitude polynomial
-constexpr int NAMP32 = 7;     // ... FP32
-constexpr int NSER = 22;      // terms of each FP64 ascending series (|z| < 6)
-constexpr int NSER32 = 12;    // ... FP32 (|z| < 4)
 constexpr int ROW_TILE = 256; // collocation rows per assembly workgroup
 constexpr int COL_CHUNK = 32; // source elements per assembly workgroup
 constexpr int MAX_DIRS = 4096;
@@ -65,35 +61,26 @@ struct DomConst {
     int pad;
 };
 
-// Per-wavenumber tables of the device Hankel evaluator (FP64).
-//   |k r| <  XS: ascending series in s = r^2 with complex coefficients,
-//   |k r| >= XS: fitted amplitude polynomials in rho = 1/r^2 with the
-//                coefficients of w = (XS/z)^2 rescaled by (XS/k)^(2m).
+// Per-wavenumber constants of the device Hankel evaluator (hankel_dev.h): the
+// polynomial coefficients are compile-time constants, the wavenumber enters
+// through the arguments w = (XS/k)^2 / r^2 and t = (k/2)^2 r^2.
 struct WaveConst {
     double kr, ki;
-    double r2_small;                // (XS / |k|)^2
-    double ur, ui;                  // XS / k
-    double a0r, a0i, a1r, a1i;      // sqrt(2/(pi k)) e^{-i pi/4}, sqrt(2/(pi k)) e^{-3 i pi/4}
-    double lk0r, lk0i;              // (2/pi) (ln(k/2) + gamma)
-    double lk1r, lk1i;              // (2/pi) ln(k/2)
-    double y1r, y1i;                // -2 / (pi k)
-    double m0r[NAMP], m0i[NAMP], n0r[NAMP], n0i[NAMP];
-    double m1r[NAMP], m1i[NAMP], n1r[NAMP], n1i[NAMP];
-    double j0r[NSER], j0i[NSER], e0r[NSER], e0i[NSER];
-    double j1r[NSER], j1i[NSER], e1r[NSER], e1i[NSER];
+    double r2_small;            // (XS / |k|)^2: below it the ascending series
+    double wr, wi;              // (XS / k)^2
+    double ur, ui;              // XS / k
+    double a0r, a0i, a1r, a1i;  // sqrt(2/(pi k)) e^{-i pi/4}, sqrt(2/(pi k)) e^{-3 i pi/4}
+    double tr, ti;              // (k / 2)^2
+    double hr, hi;              // k / 2
+    double lkr, lki;            // ln(k / 2)
+    double y1r, y1i;            // -2 / (pi k)
 };
 
-// FP32 version (|k r| < 4: series, else amplitude fit).
+// FP32 amplitude evaluation (|k r| >= 4); the series below it runs in FP64.
 struct WaveConst32 {
-    float kr, ki;
     float r2_small;
-    float ur, ui;
+    float wr, wi, ur, ui;
     float a0r, a0i, a1r, a1i;
-    float lk0r, lk0i, lk1r, lk1i, y1r, y1i;
-    float m0r[NAMP32], m0i[NAMP32], n0r[NAMP32], n0i[NAMP32];
-    float m1r[NAMP32], m1i[NAMP32], n1r[NAMP32], n1i[NAMP32];
-    float j0r[NSER32], j0i[NSER32], e0r[NSER32], e0i[NSER32];
-    float j1r[NSER32], j1i[NSER32], e1r[NSER32], e1i[NSER32];
 };
 
 // Interface plan (host-computed integer bookkeeping).
@@ -112,7 +99,7 @@ struct Tile {
 
 struct GeomLayout {
     size_t nodes, elnodes, elem, gauss, gauss32, gl, dom_in, glob_in, dom, wave, wave32, self,
-        iface, rtiles, cchunks, sigma, elif, total;
+        iface, rtiles, cchunks, sigma, elif, vtiles, total;
 };
 
 }  // namespace bemk

@@ -20,10 +20,13 @@ inline void hook_call(const KernelHook* h, int kind, int phase, hipStream_t s)
 }
 
 hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, hipStream_t s);
-hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
-                               int q, double2* A, size_t lda, hipStream_t s);
-hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_rtiles, int n_cchunks,
-                               int q, float2* A, size_t lda, hipStream_t s);
+// Assembly variants: v = side * 4 + burton_miller * 2 + complex_k; lists[v]
+// (device) holds the row-tile ids of variant v, counts[v] (host) their number.
+constexpr int ASM_VARIANTS = 8;
+hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
+                               const int* const* lists, const int* counts, double2* A, size_t lda, hipStream_t s);
+hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
+                               const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s);
 
 // angles / dirs are HOST arrays: they travel to the kernels by value in
 // chunks of ANGLE_CHUNK.

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 #include "launch.h"
@@ -170,9 +172,10 @@ struct Mfma<float> {
     }
 };
 
-constexpr int MF_UNROLL = 4;
-
-template <class TA, class T>
+// RT: 16-row tiles per wave (they share each X load); U: column steps in flight;
+// G3: complex product with three real products (P1 = Ar Xr, P2 = Ai Xi,
+// P3 = (Ar + Ai)(Xr + Xi); Yr = P1 - P2, Yi = P3 - P1 - P2) instead of four.
+template <class TA, class T, int RT, int U, bool G3>
 __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, size_t lda, int n,
                                                     const typename Mfma<T>::v2* __restrict__ XT, int nrhs,
                                                     typename Mfma<T>::v2* __restrict__ part, int cps)
@@ -182,62 +185,96 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
     using V2 = typename M::v2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int row0 = (blockIdx.x * MV_WAVES + wave) * 16;
-    const int row = row0 + lr;
-    const bool rok = row < n;
+    const int row0 = (blockIdx.x * MV_WAVES + wave) * 16 * RT;
+    bool rok[RT];
+    const TA* ap[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int row = row0 + 16 * t + lr;
+        rok[t] = row < n;
+        ap[t] = A + (rok[t] ? row : 0);
+    }
     const int c0 = blockIdx.y * cps;
     const int c1 = min(n, c0 + cps);
-    acc rr0 = {0, 0, 0, 0}, rr1 = {0, 0, 0, 0}, ii0 = {0, 0, 0, 0}, ii1 = {0, 0, 0, 0};
-    const TA* ap = A + (rok ? row : 0);
-    int c = c0;
-    for (; c + 4 * MF_UNROLL <= c1; c += 4 * MF_UNROLL) {
-        TA a[MF_UNROLL];
-        V2 x[MF_UNROLL];
+    acc rr0[RT], rr1[RT], ii0[RT], ii1[RT];
 #pragma unroll
-        for (int u = 0; u < MF_UNROLL; ++u) {
+    for (int t = 0; t < RT; ++t) rr0[t] = rr1[t] = ii0[t] = ii1[t] = acc{0, 0, 0, 0};
+    int c = c0;
+    for (; c + 4 * U <= c1; c += 4 * U) {
+        TA a[U][RT];
+        V2 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             const int col = c + 4 * u + lk;
-            a[u] = ap[(size_t)col * lda];
             x[u] = XT[(size_t)col * 16 + lr];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) a[u][t] = ap[t][(size_t)col * lda];
         }
 #pragma unroll
-        for (int u = 0; u < MF_UNROLL; ++u) {
-            const T ar = rok ? (T)a[u].x : T(0), ai = rok ? (T)a[u].y : T(0);
-            rr0 = M::run(ar, x[u].x, rr0);
-            rr1 = M::run(ai, -x[u].y, rr1);
-            ii0 = M::run(ar, x[u].y, ii0);
-            ii1 = M::run(ai, x[u].x, ii1);
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const T ar = rok[t] ? (T)a[u][t].x : T(0), ai = rok[t] ? (T)a[u][t].y : T(0);
+                if (G3) {
+                    rr0[t] = M::run(ar, x[u].x, rr0[t]);
+                    rr1[t] = M::run(ai, x[u].y, rr1[t]);
+                    ii0[t] = M::run(ar + ai, x[u].x + x[u].y, ii0[t]);
+                } else {
+                    rr0[t] = M::run(ar, x[u].x, rr0[t]);
+                    rr1[t] = M::run(ai, -x[u].y, rr1[t]);
+                    ii0[t] = M::run(ar, x[u].y, ii0[t]);
+                    ii1[t] = M::run(ai, x[u].x, ii1[t]);
+                }
+            }
         }
     }
     for (; c < c1; c += 4) {
         const int col = c + lk;
         const bool ok = col < c1;
-        T ar = T(0), ai = T(0), xr = T(0), xi = T(0);
+        T xr = T(0), xi = T(0);
         if (ok) {
             const V2 x = XT[(size_t)col * 16 + lr];
             xr = x.x;
             xi = x.y;
-            if (rok) {
-                const TA a = ap[(size_t)col * lda];
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            T ar = T(0), ai = T(0);
+            if (ok && rok[t]) {
+                const TA a = ap[t][(size_t)col * lda];
                 ar = (T)a.x;
                 ai = (T)a.y;
             }
+            if (G3) {
+                rr0[t] = M::run(ar, xr, rr0[t]);
+                rr1[t] = M::run(ai, xi, rr1[t]);
+                ii0[t] = M::run(ar + ai, xr + xi, ii0[t]);
+            } else {
+                rr0[t] = M::run(ar, xr, rr0[t]);
+                rr1[t] = M::run(ai, -xi, rr1[t]);
+                ii0[t] = M::run(ar, xi, ii0[t]);
+                ii1[t] = M::run(ai, xr, ii1[t]);
+            }
         }
-        rr0 = M::run(ar, xr, rr0);
-        rr1 = M::run(ai, -xi, rr1);
-        ii0 = M::run(ar, xi, ii0);
-        ii1 = M::run(ai, xr, ii1);
     }
     if (lr < nrhs) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = row0 + M::out_row(lk, j);
-            if (r < n) {
-                V2 v;
-                v.x = rr0[j] + rr1[j];
-                v.y = ii0[j] + ii1[j];
-                part[((size_t)blockIdx.y * nrhs + lr) * n + r] = v;
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = row0 + 16 * t + M::out_row(lk, j);
+                if (r < n) {
+                    V2 v;
+                    if (G3) {
+                        v.x = rr0[t][j] - rr1[t][j];
+                        v.y = ii0[t][j] - rr0[t][j] - rr1[t][j];
+                    } else {
+                        v.x = rr0[t][j] + rr1[t][j];
+                        v.y = ii0[t][j] + ii1[t][j];
+                    }
+                    part[((size_t)blockIdx.y * nrhs + lr) * n + r] = v;
+                }
             }
-        }
     }
 }
 
@@ -259,14 +296,58 @@ __global__ void k_pack_xt(const TX* __restrict__ X, size_t ldx, int n, int nr, V
     XT[(size_t)c * 16 + r] = v;
 }
 
-int mfma_splits(int n)
+// Launch shape of the matrix-core product: row tiles per wave, column steps
+// in flight, column splits.  BEM_MV_CFG="rt,u,splits" overrides it (tuning).
+struct MfmaCfg {
+    int rt, u, splits, g3;
+};
+
+MfmaCfg mfma_cfg(int n)
 {
-    const int rowblocks = (n + 16 * MV_WAVES - 1) / (16 * MV_WAVES);
-    int s = (1024 + rowblocks - 1) / rowblocks;
-    const int maxs = std::max(1, n / 256);
-    if (s > maxs) s = maxs;
-    if (s > 64) s = 64;
-    return std::max(1, s);
+    MfmaCfg c{2, 8, 8, 1};
+    if (const char* e = getenv("BEM_MV_CFG")) {
+        int a = 0, b = 0, d = 0, g = 0;
+        const int got = sscanf(e, "%d,%d,%d,%d", &a, &b, &d, &g);
+        if (got >= 3 && (a == 1 || a == 2 || a == 4) && (b == 2 || b == 4 || b == 8) && d >= 0 && d <= 64) {
+            c = {a, b, d, got == 4 ? (g != 0) : 0};
+        }
+    }
+    if (c.splits == 0) {
+        const int rowblocks = (n + 16 * c.rt * MV_WAVES - 1) / (16 * c.rt * MV_WAVES);
+        int s = (1024 + rowblocks - 1) / rowblocks;
+        s = std::min(s, std::max(1, n / 256));
+        c.splits = std::max(1, std::min(s, 64));
+    }
+    c.splits = std::max(1, std::min(c.splits, std::max(1, n / 64)));
+    return c;
+}
+
+int mfma_splits(int n) { return mfma_cfg(n).splits; }
+
+template <class TA, class T, class V2>
+void launch_mfma_variant(const MfmaCfg& c, dim3 grid, hipStream_t s, const TA* A, size_t lda, int n, const V2* xt,
+                         int nr, V2* part, int cps)
+{
+#define BEM_MV_CASE(RT_, U_)                                                                                   \
+    if (c.rt == RT_ && c.u == U_) {                                                                            \
+        if (c.g3)                                                                                              \
+            hipLaunchKernelGGL((k_matvec_mfma<TA, T, RT_, U_, true>), grid, dim3(BS), 0, s, A, lda, n, xt, nr, part, \
+                               cps);                                                                           \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_matvec_mfma<TA, T, RT_, U_, false>), grid, dim3(BS), 0, s, A, lda, n, xt, nr,    \
+                               part, cps);                                                                     \
+        return;                                                                                                \
+    }
+    BEM_MV_CASE(1, 2)
+    BEM_MV_CASE(1, 4)
+    BEM_MV_CASE(1, 8)
+    BEM_MV_CASE(2, 2)
+    BEM_MV_CASE(2, 4)
+    BEM_MV_CASE(2, 8)
+    BEM_MV_CASE(4, 2)
+    BEM_MV_CASE(4, 4)
+    BEM_MV_CASE(4, 8)
+#undef BEM_MV_CASE
 }
 
 template <class TA, class TX, class ACC, class TY>
@@ -283,13 +364,15 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
         const TX* Xg = X + (size_t)r0 * ldx;
         if (nr > 4) {
             // pack X right-hand-side fastest into the tail of the partial buffer
-            const int ms = mfma_splits(n);
-            const int mcps = ((n + ms - 1) / ms + 15) / 16 * 16;
+            const MfmaCfg cfg = mfma_cfg(n);
+            const int ms = cfg.splits;
+            const int mcps = ((n + ms - 1) / ms + 31) / 32 * 32;
             ACC* xt = part + (size_t)ms * nr * n;
             hipLaunchKernelGGL((k_pack_xt<TX, ACC>), dim3((n * 16 + BS - 1) / BS), dim3(BS), 0, s, Xg, ldx, n, nr, xt);
             hook_call(hook, KIND_MATVEC, 0, s);
-            hipLaunchKernelGGL((k_matvec_mfma<TA, S>), dim3((n + 16 * MV_WAVES - 1) / (16 * MV_WAVES), ms), dim3(BS),
-                               0, s, A, lda, n, xt, nr, part, mcps);
+            const int rows_per_block = 16 * cfg.rt * MV_WAVES;
+            launch_mfma_variant<TA, S, ACC>(cfg, dim3((n + rows_per_block - 1) / rows_per_block, ms), s, A, lda, n, xt,
+                                            nr, part, mcps);
             hook_call(hook, KIND_MATVEC, 1, s);
             hipLaunchKernelGGL((k_matvec_reduce<ACC, TY>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, part, ms, n,
                                nr, Y + (size_t)r0 * ldy, ldy, B ? B + (size_t)r0 * ldb : nullptr, ldb);
@@ -328,7 +411,9 @@ int matvec_splits_valu(int n)
     return std::max(1, s);
 }
 
-int matvec_splits(int n) { return std::max(matvec_splits_valu(n), mfma_splits(n) + 16); }
+// partial-sum buffer in units of n complex values: the largest split count any
+// launch shape may use plus the packed copy of X (16 columns)
+int matvec_splits(int n) { return std::max(matvec_splits_valu(n), 64 + 16); }
 
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s, const KernelHook* hook)
