@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256"])
+    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256", "sectors"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "matvec"],
                     help="matvec: assemble case 1 and run only --steps 16-right-hand-side products, then one plain "
@@ -138,7 +138,8 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.workload_kite4096() if args.workload == "kite4096" else W.workload_disk256()
+    wl = {"kite4096": W.workload_kite4096, "disk256": W.workload_disk256,
+          "sectors": W.workload_sectors}[args.workload]()
     if args.mode == "matvec":
         return matvec_mode(args, wl, P, torch)
     dirs = wl.far_dirs

@@ -1,0 +1,89 @@
+"""Several materials with junction points on the GPU: a disk cut into three
+120-degree sectors (graded elements toward the centre and the triple points),
+host k0 = 10, sectors k = 12, 18, 9 + 0.5i (the multi-material workload)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+K = [10.0, 12.0, 18.0, 9.0 + 0.5j]
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_12787_amd as P
+    return P
+
+
+@pytest.mark.parametrize("form", [W.CALDERON, W.CALDERON_ORIG, W.CONVENTIONAL])
+def test_sector_assembly_fp64_fp32_match_oracle(form):
+    P = _gpu()
+    spec = W.sectors(K, h=1 / 20, form=form)
+    print("form", form, "elements", spec.n_elements, flush=True)
+    g = P.Problem(spec)
+    Ao = O.Problem(spec).assemble()
+    A = g.assemble(P.F64).T[:g.n].cpu().numpy()
+    e64 = np.abs(A - Ao).max() / np.abs(Ao).max()
+    A32 = g.assemble(P.F32).T[:g.n].cpu().numpy().astype(np.complex128)
+    e32 = np.abs(A32 - Ao).max() / np.abs(Ao).max()
+    print("  fp64", e64, "fp32", e32, flush=True)
+    assert e64 < 5e-13 and e32 < 1e-6
+
+
+def test_sector_solve_matches_oracle():
+    P = _gpu()
+    spec = W.sectors(K, h=1 / 20)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    ang = [0.0, 2.0]
+    X, info = g.solve(g.rhs(ang), restart=60, tol=1e-12)
+    print("iters", info.iters, flush=True)
+    assert info.converged.all()
+    po = O.Problem(spec)
+    Xo = O.lu_solve(po.assemble(), po.rhs(ang))
+    assert rel_err(X.cpu().numpy().T, Xo) < 1e-10
+    dirs = W.equispaced_angles(90)
+    assert rel_err(g.farfield(X, dirs).cpu().numpy().T, po.farfield(Xo, dirs)) < 1e-10
+
+
+def test_modified_formulation_converges_fastest():
+    """Sec. 7.2 (junction example): the modified Calderon form needs the
+    fewest GMRES iterations, the conventional Burton-Miller form the most
+    (GMRES without restart, tolerance 1e-8 as in Sec. 7)."""
+    P = _gpu()
+    its = {}
+    for form in (W.CALDERON, W.CALDERON_ORIG, W.CONVENTIONAL):
+        g = P.Problem(W.sectors(K, h=1 / 100, form=form))
+        g.assemble(P.F64)
+        X, info = g.solve(g.rhs([0.0]), restart=1000, tol=1e-8, max_iter=1000)
+        its[form] = int(info.iters[0])
+        print("form", form, "n", g.n, "iters", its[form], "converged", bool(info.converged[0]), flush=True)
+    assert its[W.CALDERON] < its[W.CALDERON_ORIG] < its[W.CONVENTIONAL]
+
+
+def test_sectors_full_size_solve_residual_on_oracle_rows():
+    """The multi-material workload at full size (h = 1/800, graded: 7485
+    elements, 14970 x 14970 complex128): GMRES(100) to 1e-10; the residual is
+    checked on sampled rows of the oracle's own matrix."""
+    P = _gpu()
+    spec = W.sectors(K)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    B = g.rhs([0.0])
+    X, info = g.solve(B, restart=100, tol=1e-10, max_iter=5000)
+    print("sectors full size n", g.n, "iters", info.iters, "restarts", info.restarts, "rel",
+          info.rel_residual, flush=True)
+    assert info.converged.all()
+    rows = np.array([0, 1700, 5000, 7484, 7485, 9000, 12000, 14969], dtype=np.int32)
+    po = O.Problem(spec)
+    Ar = po.assemble_rows(rows)
+    Bo = po.rhs([0.0])
+    res = Bo[rows, 0] - Ar @ X.cpu().numpy()[0]
+    scale = np.linalg.norm(Bo) / np.sqrt(g.n)
+    print("sampled residual / rms(b)", np.abs(res).max() / scale, flush=True)
+    assert np.abs(res).max() < 1e-7 * scale

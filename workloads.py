@@ -140,6 +140,57 @@ def concentric(n_outer: int, n_inner: int, k: Sequence[complex], r_outer: float 
                        name=f"concentric{n_outer}+{n_inner}")
 
 
+def graded_params(length: float, h: float, grade_start: bool, grade_end: bool, hmin_ratio: float = 16.0,
+                  ratio: float = 1.5) -> np.ndarray:
+    """Node parameters in [0, length]: element size h in the middle, refined
+    geometrically (sizes h/hmin_ratio, x ratio, ...) toward the graded ends."""
+    ramp = []
+    size = h / hmin_ratio
+    while size < h:
+        ramp.append(size)
+        size *= ratio
+    ramp = np.array(ramp)
+    left = ramp if grade_start else np.array([])
+    right = ramp[::-1] if grade_end else np.array([])
+    middle_len = length - left.sum() - right.sum()
+    if middle_len <= h:  # too short to grade: uniform
+        n = max(1, int(round(length / h)))
+        return np.linspace(0.0, length, n + 1)
+    n_mid = max(1, int(round(middle_len / h)))
+    mid = np.full(n_mid, middle_len / n_mid)
+    sizes = np.concatenate([left, mid, right])
+    t = np.concatenate([[0.0], np.cumsum(sizes)])
+    t[-1] = length
+    return t
+
+
+def sectors(k: Sequence[complex], h: float = 1.0 / 800, graded: bool = True, angles_deg=(90.0, 210.0, 330.0),
+            quad: int = 8, form: int = CALDERON, hmin_ratio: float = 16.0) -> ProblemSpec:
+    """Unit disk split into three 120-degree sectors (domains 1, 2, 3; sector s
+    spans [theta_s, theta_s + 120 deg)) in the host medium (domain 0).  Six
+    open interfaces: the three arcs (normal into the sector, leaving the host)
+    and the three radii at theta_s from the centre outwards (normal into
+    sector s, leaving sector s-1).  Junctions: the centre and the three outer
+    triple points; with graded=True the elements shrink geometrically (ratio
+    1.5, down to h/16) toward every junction."""
+    th = [np.deg2rad(a) for a in angles_deg]
+    ifs = []
+    for s_ in range(3):
+        t = graded_params(2 * np.pi / 3, h, graded, graded, hmin_ratio)
+        phi = th[s_] + t
+        xy = np.stack([np.cos(phi), np.sin(phi)], axis=1)
+        xy[0] = [np.cos(th[s_]), np.sin(th[s_])]
+        xy[-1] = [np.cos(th[(s_ + 1) % 3]), np.sin(th[(s_ + 1) % 3])]
+        ifs.append(Interface(xy, False, s_ + 1, 0))
+    for s_ in range(3):
+        t = graded_params(1.0, h, graded, graded, hmin_ratio)
+        xy = np.stack([t * np.cos(th[s_]), t * np.sin(th[s_])], axis=1)
+        xy[0] = [0.0, 0.0]
+        xy[-1] = [np.cos(th[s_]), np.sin(th[s_])]
+        ifs.append(Interface(xy, False, s_ + 1, (s_ - 1) % 3 + 1))
+    return ProblemSpec(k=[complex(v) for v in k], interfaces=ifs, quad=quad, form=form, name="sectors")
+
+
 def equispaced_angles(n: int) -> np.ndarray:
     return 2.0 * np.pi * np.arange(n) / n
 
@@ -168,6 +219,14 @@ def workload_kite4096(n: int = 4096) -> Workload:
     GMRES(100) to 1e-10."""
     return Workload(f"kite{n}_k20-30_x16", [kite(n, 20.0, 30.0), kite(n, 20.0, 30.0 + 0.3j)],
                     equispaced_angles(16), 100, 1e-10)
+
+
+def workload_sectors(h: float = 1.0 / 800) -> Workload:
+    """Unit disk in three 120-degree sectors, k0 = 10, k = 12, 18, 9 + 0.5i,
+    junctions at the centre and the outer triple points, graded elements,
+    modified Calderon formulation, FP64."""
+    spec = sectors([10.0, 12.0, 18.0, 9.0 + 0.5j], h=h)
+    return Workload(f"sectors{spec.n_elements}_k10-12-18-9+0.5i", [spec], np.array([0.0]), 100, 1e-10)
 
 
 def workload_kite16384_fp32(n: int = 16384) -> Workload:
