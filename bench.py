@@ -16,7 +16,13 @@ Also reported: p50/p99 latency of one case (16 solves), the assembly rate, and
 the roofline record of the dominant kernel measured with the library's HIP
 events on the solve stream, plus the CPU oracle timed on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload kite4096|disk256]
+Other workloads (--workload): disk256 (unit disk, N = 256), sectors (three
+material sectors with junctions, about 7500 graded elements), kite16384_mixed
+(the precision path: N = 16384, FP32 matrix and products with FP64 residual
+refinement, 64 angles; also reports the FP64 path on the same workload and the
+far-field error of both against an FP64 solution).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--mode full|matvec]
 """
 import argparse
 import hashlib
@@ -31,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFS = 157.3
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. err vs FP64; assembly FLOP/s, matvec GB/s"
 
 
@@ -42,10 +49,11 @@ def source_sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def traffic_record(kernel_src):
+def traffic_record(kernel_src, workload):
     """HBM traffic of the product kernel from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "matvec_traffic_kite4096.json")
+    summary of this workload, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"matvec_traffic_{workload.split('_')[0]}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -54,44 +62,51 @@ def traffic_record(kernel_src):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(workload, gpu_iters, rows_per_case=48):
+def cpu_baseline(workload, gpu_iters, rows_per_case=None):
     """The oracle (single thread) on a bounded sample of the same workload:
-    rows_per_case strided matrix rows of each case and one full-size product;
-    scaled to full assembly (rows x n) plus the product count the GPU solve
-    needed (sum of GMRES iterations and restart residuals)."""
+    strided matrix rows of each case (48 at N = 4096, fewer for larger N so
+    the sample stays near the same CPU time) and one product of at most
+    8192 x 8192; scaled to full assembly (rows x n), to the full product size
+    (n^2) and to the product count the GPU solve needed (sum of GMRES
+    iterations and restart residuals)."""
     import oracle as O
     t_total = 0.0
     spent = 0.0
+    mv_n = None
     for spec, iters in zip(workload.problems, gpu_iters):
         P = O.Problem(spec)
         n = P.n
-        rows = np.linspace(0, n - 1, rows_per_case).round().astype(np.int32)
+        rows_n = rows_per_case or max(12, int(48 * 8192 / n))
+        rows = np.linspace(0, n - 1, rows_n).round().astype(np.int32)
         t0 = time.perf_counter()
         P.assemble_rows(rows)
         t_rows = time.perf_counter() - t0
-        A = np.zeros((n, n), dtype=np.complex128, order="F")
-        x = np.ones(n, dtype=np.complex128)
+        mv_n = min(n, 8192)
+        A = np.zeros((mv_n, mv_n), dtype=np.complex128, order="F")
+        x = np.ones(mv_n, dtype=np.complex128)
         t0 = time.perf_counter()
         O.matvec(A, x)
         t_mv = time.perf_counter() - t0
         del A
         spent += t_rows + t_mv
-        t_total += t_rows / rows_per_case * n + iters * t_mv
+        t_total += t_rows / rows_n * n + iters * t_mv * (n / mv_n) ** 2
     solves = len(workload.problems) * len(workload.angles)
     return {"value": solves / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{rows_per_case} strided rows per case assembled by the oracle and one full-size "
-                       f"oracle product, scaled to {workload.problems[0].order} rows and to the "
-                       f"{sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation, about "
-                       f"1% of a product here, not modelled); {spent:.1f} s of CPU work")}
+            "sample": (f"{rows_n} strided rows per case assembled by the oracle (FP64) and one {mv_n} x {mv_n} "
+                       f"oracle product, scaled to {workload.problems[0].order} rows, to the full product size "
+                       f"and to the {sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation not "
+                       f"modelled); {spent:.1f} s of CPU work")}
 
 
-def matvec_mode(args, wl, P, torch):
+def matvec_mode(args, wl, P, torch, prec):
     """Assemble the first case, then time --steps block products with all the
     workload's right-hand sides, then one plain device copy of 1 GiB (a
     kernel of known traffic for scaling hardware counters)."""
     g = P.Problem(wl.problems[0])
-    g.assemble(P.F64)
+    g.assemble(prec)
     X = g.rhs(wl.angles)
+    if prec == P.F32:
+        X = X.to(torch.complex64)
     for _ in range(max(1, args.warmup)):
         g.matvec(X)
     torch.cuda.synchronize()
@@ -108,12 +123,67 @@ def matvec_mode(args, wl, P, torch):
     dst.copy_(src)
     torch.cuda.synchronize()
     n, nr = g.n, len(wl.angles)
-    mv_bytes = 16.0 * n * n + 2 * 16.0 * n * nr
+    esz = 8.0 if prec == P.F32 else 16.0
+    mv_bytes = esz * n * n + 2 * esz * n * nr
     avg = pr["matvec_ms"] / max(1, pr["matvec_launches"])
     print(json.dumps({"mode": "matvec", "workload": wl.name, "launches": pr["matvec_launches"], "avg_ms": avg,
                       "algorithmic_bytes_per_launch": mv_bytes, "GB_per_s": mv_bytes / (avg * 1e-3) / 1e9,
+                      "TFLOP_per_s": 8.0 * n * n * nr / (avg * 1e-3) / 1e12,
                       "wall_ms_per_product": T / args.steps * 1e3, "copy_bytes": 1 << 30}), flush=True)
     del Y
+
+
+def assembly_evals(spec):
+    """(H0, H1) evaluations of one assembly: for every domain, each row element
+    on its boundary against each other element on its boundary, at every Gauss
+    point (single material: 2 N (N - 1) q)."""
+    sizes = {}
+    for f in spec.interfaces:
+        n_el = len(f.xy) if f.closed else len(f.xy) - 1
+        for d in (f.dom_left, f.dom_right):
+            sizes[d] = sizes.get(d, 0) + n_el
+    return float(spec.quad) * sum(e * (e - 1) for e in sizes.values())
+
+
+def max_rel_err(F, Fr):
+    """max over right-hand sides of ||F_r - Fr_r|| / ||Fr_r|| (rows = right-hand sides)."""
+    import torch
+    return float(torch.max(torch.linalg.vector_norm(F - Fr, dim=1) / torch.linalg.vector_norm(Fr, dim=1)))
+
+
+def fp64_comparison(wl, probs, P, torch, F_mixed):
+    """Mixed path only, outside the timed region: the FP64 path on the same
+    workload (assembly, right-hand sides, GMRES to the same tolerance, far
+    field), timed once per case, and the far-field error of both against an
+    FP64 solution to 1e-12."""
+    nr = len(wl.angles)
+    out = {"solves": 0, "seconds": 0.0, "mixed_rel_err": 0.0, "fp64_rel_err": 0.0}
+    for g, Fm in zip(probs, F_mixed):
+        A64 = torch.empty((g.n, g.n), dtype=torch.complex128, device="cuda")
+        g.assemble(P.F64, out=A64)
+        Xr, ir = g.solve(g.rhs(wl.angles), restart=wl.restart, tol=1e-12, max_iter=20000)
+        Fr = g.farfield(Xr, wl.far_dirs)
+        del Xr
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.geometry_update()
+        g.assemble(P.F64, out=A64)
+        X, info = g.solve(g.rhs(wl.angles), restart=wl.restart, tol=wl.tol, max_iter=20000)
+        F = g.farfield(X, wl.far_dirs)
+        torch.cuda.synchronize()
+        out["seconds"] += time.perf_counter() - t0
+        out["solves"] += nr
+        out["mixed_rel_err"] = max(out["mixed_rel_err"], max_rel_err(Fm, Fr))
+        out["fp64_rel_err"] = max(out["fp64_rel_err"], max_rel_err(F, Fr))
+        out["fp64_iterations_per_rhs"] = float(info.iters.mean())
+        out["reference_converged"] = bool(ir.converged.all())
+        del A64, X, F, Fr
+        torch.cuda.empty_cache()
+    return {"fp64_path_solves_per_s": out["solves"] / out["seconds"],
+            "fp64_path_iterations_per_rhs": out["fp64_iterations_per_rhs"],
+            "far_field_rel_err_mixed": out["mixed_rel_err"], "far_field_rel_err_fp64_path": out["fp64_rel_err"],
+            "reference": f"FP64 assembly and GMRES to 1e-12 (converged: {out['reference_converged']}), "
+                         f"{len(wl.far_dirs)} directions, max over right-hand sides of the relative 2-norm error"}
 
 
 def main():
@@ -121,11 +191,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256", "sectors"])
+    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256", "sectors", "kite16384_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "matvec"],
-                    help="matvec: assemble case 1 and run only --steps 16-right-hand-side products, then one plain "
-                         "1 GiB device copy (for hardware-counter runs)")
+                    help="matvec: assemble case 1 and run only --steps block products with all the workload's "
+                         "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1 "
@@ -139,17 +209,19 @@ def main():
 
     torch.cuda.set_device(0)
     wl = {"kite4096": W.workload_kite4096, "disk256": W.workload_disk256,
-          "sectors": W.workload_sectors}[args.workload]()
+          "sectors": W.workload_sectors, "kite16384_mixed": W.workload_kite16384_fp32}[args.workload]()
+    mixed = wl.precision == "f32"
+    prec = P.F32 if mixed else P.F64
     if args.mode == "matvec":
-        return matvec_mode(args, wl, P, torch)
+        return matvec_mode(args, wl, P, torch, prec)
     dirs = wl.far_dirs
-    stream = torch.cuda.current_stream()
     probs, mats = [], []
+    nr = len(wl.angles)
     for spec in wl.problems:
         g = P.Problem(spec)
         g.geometry()  # uploads the inputs (nodes, plan) once
-        mats.append(torch.empty((g.n, g.n), dtype=torch.complex128, device="cuda"))
-        _, _, wb = g.sizes(P.F64, len(wl.angles), wl.restart)
+        mats.append(torch.empty((g.n, g.n), dtype=torch.complex64 if mixed else torch.complex128, device="cuda"))
+        _, _, wb = g.sizes(P.F64, nr, wl.restart)
         g._workspace(wb)
         probs.append(g)
     torch.cuda.synchronize()
@@ -157,28 +229,29 @@ def main():
     lat = []
     iters = [0] * len(probs)
     products = [0] * len(probs)
-    infos = []
-    nr = len(wl.angles)
+    refine = [0] * len(probs)
+    last_F = [None] * len(probs)
 
     def step(record):
         for ci, (g, A) in enumerate(zip(probs, mats)):
             t0 = time.perf_counter()
             g.geometry_update()
-            g.assemble(P.F64, out=A)
+            g.assemble(prec, out=A)
             B = g.rhs(wl.angles)
-            X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000)
+            X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000,
+                              inner_tol=wl.inner_tol if mixed else 0.0)
             F = g.farfield(X, dirs)
             torch.cuda.synchronize()
             if record:
                 lat.append(time.perf_counter() - t0)
                 iters[ci] += int(info.iters.sum())
+                refine[ci] += int(info.restarts.sum())
                 # products a one-right-hand-side-at-a-time solver needs: one per
                 # Arnoldi step plus one residual per cycle
                 products[ci] += int(info.iters.sum() + info.restarts.sum()) + nr
-                infos.append(info)
+                last_F[ci] = F
             if not info.converged.all():
                 raise RuntimeError(f"case {ci} did not converge: {info}")
-            del F
 
     for _ in range(args.warmup):
         step(False)
@@ -198,19 +271,33 @@ def main():
     n = probs[0].n
     N = probs[0].N
     q = wl.problems[0].quad
+    esz = 8.0 if mixed else 16.0
     solves = args.steps * len(probs) * nr
     mv_launch = sum(p["matvec_launches"] for p in prof)
     mv_ms = sum(p["matvec_ms"] for p in prof)
+    rs_launch = sum(p["residual_launches"] for p in prof)
+    rs_ms = sum(p["residual_ms"] for p in prof)
     as_launch = sum(p["assemble_launches"] for p in prof)
     as_ms = sum(p["assemble_ms"] for p in prof)
-    mv_bytes = 16.0 * n * n + 2 * 16.0 * n * nr  # matrix + X + Y per launch (algorithmic)
+    mv_bytes = esz * n * n + 2 * esz * n * nr  # matrix + X + Y per launch (algorithmic)
+    mv_flops = 8.0 * n * n * nr
     mv_avg_ms = mv_ms / max(1, mv_launch)
     mv_gbs = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
+    mv_tfs = mv_flops / (mv_avg_ms * 1e-3) / 1e12
     as_avg_ms = as_ms / max(1, as_launch)
-    evals = 2.0 * N * (N - 1) * q  # (H0, H1) pairs at Gauss points, both wavenumbers
+    evals = sum(assembly_evals(s) for s in wl.problems) / len(wl.problems)
     kernel_src = os.path.join(ROOT, "paper_2312_12787_amd", "csrc", "matvec.hip")
-    traffic = traffic_record(kernel_src)
     lat_ms = np.array(lat) * 1e3
+    if mixed:
+        roofline = {"kernel": f"k_matvec_mfma (FP32 MFMA split-K block product, {nr} right-hand sides in one pass "
+                              f"over A)", "bound": "mfma", "achieved": mv_tfs, "peak": FP32_MFMA_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": mv_tfs / FP32_MFMA_PEAK_TFS,
+                    "traffic": traffic_record(kernel_src, wl.name)}
+    else:
+        roofline = {"kernel": f"k_matvec_mfma (FP64 MFMA split-K block product, {nr} right-hand sides)"
+                    if nr > 4 else f"k_matvec (FP64 VALU split-K product, {nr} right-hand side(s))",
+                    "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(kernel_src, wl.name)}
     out = {
         "metric": METRIC,
         "value": solves / T,
@@ -222,22 +309,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "elements": N, "system_order": n, "cases": [str(s.k[1]) for s in wl.problems],
-                   "k0": float(np.real(wl.problems[0].k[0])), "rhs_per_case": nr, "restart": wl.restart,
-                   "tol": wl.tol, "quad": q, "far_field_dirs": len(dirs), "solves_per_step": len(probs) * nr},
+        "config": {"workload": wl.name, "elements": N, "system_order": n,
+                   "wavenumbers": [[str(k) for k in s.k] for s in wl.problems], "rhs_per_case": nr,
+                   "restart": wl.restart, "tol": wl.tol, "quad": q, "far_field_dirs": len(dirs),
+                   "solves_per_step": len(probs) * nr, "precision": wl.precision},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "unit": "one case: geometry tables + assembly + 16 solves + far field"},
+                       "unit": f"one case: geometry tables + assembly + {nr} solves + far field"},
         "gmres_iterations_per_rhs": [it / (args.steps * nr) for it in iters],
-        "assembly": {"launches": as_launch, "avg_ms": as_avg_ms,
+        "assembly": {"launches": as_launch, "avg_ms": as_avg_ms, "evals": evals,
                      "evals_per_s": evals / (as_avg_ms * 1e-3) if as_launch else None},
-        "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs,
+        "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
                    "share_of_step_time": mv_ms / (T * 1e3)},
-        "roofline": {"kernel": "k_matvec_mfma (FP64 MFMA split-K block product, 16 right-hand sides)", "bound": "hbm",
-                     "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic},
+        "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
+        "roofline": roofline,
     }
+    if mixed:
+        out["refinement_steps_per_rhs"] = [r / (args.steps * nr) for r in refine]
+        log("FP64 path on the same workload (reference solve, then one timed run) ...")
+        out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl, [p // args.steps for p in products])

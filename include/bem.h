@@ -203,9 +203,11 @@ bem_status bem_farfield(const bem_problem *p, int nrhs, const void *X_dev, size_
 
 /* Kernel timing for measurement.  While enabled, the library records HIP
  * events on the caller's stream immediately before and after the main kernel
- * of every assembly (the fused block-assembly kernel) and every dense product
- * (the split-K product kernel, not its small reduction pass), including the
- * products inside bem_solve.  bem_profile_read waits for the recorded events,
+ * of every assembly (the fused block-assembly kernel), every dense product
+ * Y = A X (the split-K product kernel, not its small reduction pass; including
+ * the products inside bem_solve) and every residual product R = B - A X of
+ * bem_solve (FP64 accumulation; with an FP32 matrix these are the outer
+ * refinement residuals).  bem_profile_read waits for the recorded events,
  * returns the launch counts and summed durations, and with reset != 0 starts
  * a new tally.  Host event objects are created by the library as needed and
  * released by bem_destroy; no device memory is used.                        */
@@ -214,6 +216,8 @@ typedef struct {
     double assemble_ms;
     int matvec_launches;
     double matvec_ms;
+    int residual_launches;
+    double residual_ms;
 } bem_profile;
 bem_status bem_profile_enable(bem_problem *p, int on);
 bem_status bem_profile_read(bem_problem *p, bem_profile *out, int reset);

@@ -53,7 +53,7 @@ class bem_solve_opts(C.Structure):
 
 class bem_profile(C.Structure):
     _fields_ = [("assemble_launches", C.c_int), ("assemble_ms", C.c_double), ("matvec_launches", C.c_int),
-                ("matvec_ms", C.c_double)]
+                ("matvec_ms", C.c_double), ("residual_launches", C.c_int), ("residual_ms", C.c_double)]
 
 
 class bem_solve_info(C.Structure):
@@ -240,7 +240,7 @@ class Problem:
         X = X.contiguous()
         nrhs = X.shape[0]
         Y = torch.empty_like(X)
-        _, _, wb = self.sizes(self.prec if self.prec is not None else F64, min(nrhs, 16), 1)
+        _, _, wb = self.sizes(self.prec if self.prec is not None else F64, min(nrhs, 64), 1)
         W = self._workspace(wb)
         _check(lib().bem_matvec(self._h, nrhs, C.c_void_p(X.data_ptr()), X.shape[1], C.c_void_p(Y.data_ptr()),
                                 Y.shape[1], C.c_void_p(W.data_ptr()), W.numel(), _stream(stream)))
@@ -273,7 +273,8 @@ class Problem:
         pr = bem_profile()
         _check(lib().bem_profile_read(self._h, C.byref(pr), 1 if reset else 0))
         return dict(assemble_launches=pr.assemble_launches, assemble_ms=pr.assemble_ms,
-                    matvec_launches=pr.matvec_launches, matvec_ms=pr.matvec_ms)
+                    matvec_launches=pr.matvec_launches, matvec_ms=pr.matvec_ms,
+                    residual_launches=pr.residual_launches, residual_ms=pr.residual_ms)
 
     def farfield(self, X, dirs: Sequence[float], stream=None):
         import torch

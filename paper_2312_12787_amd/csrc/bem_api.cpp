@@ -52,7 +52,7 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    hipEvent_t pending[2] = {nullptr, nullptr};
+    hipEvent_t pending[bemk::N_KINDS] = {};
     struct Rec {
         int kind;
         hipEvent_t a, b;
@@ -77,6 +77,7 @@ void prof_cb(void* ctx, int kind, int phase, hipStream_t s)
     hipEvent_t e = P->pool[P->used++];
     hipError_t r = hipEventRecord(e, s);
     if (r != hipSuccess) P->err = r;
+    if (kind < 0 || kind >= bemk::N_KINDS) return;
     if (phase == 0)
         P->pending[kind] = e;
     else if (P->pending[kind])
@@ -160,7 +161,7 @@ GeomLayout make_layout(const bem_problem* p)
 struct WorkLayout {
     size_t V, W, R, Ro, D, X32, W32, mv_part, dot_part, dot_part2, h1, h2, y, H, cs, sn, gvec, norm_part, n0, n1, n2,
         hnorm, resid, rnorm, bnorm, thr, active, kdim, iters, dirs, total;
-    int ldv, nblk, splits, anblk;
+    int ldv, nblk, anblk;
 };
 
 WorkLayout make_work(int n, int nr, int m)
@@ -174,7 +175,6 @@ WorkLayout make_work(int n, int nr, int m)
     };
     W.ldv = (n + 63) / 64 * 64;
     W.nblk = (n + 255) / 256;
-    W.splits = bemk::matvec_splits(n);
     const size_t vec = (size_t)W.ldv * nr * sizeof(double2);
     W.V = take((size_t)(m + 1) * vec);
     W.W = take(vec);
@@ -183,7 +183,7 @@ WorkLayout make_work(int n, int nr, int m)
     W.D = take(vec);
     W.X32 = take((size_t)W.ldv * nr * sizeof(float2));
     W.W32 = take((size_t)W.ldv * nr * sizeof(float2));
-    W.mv_part = take((size_t)W.splits * std::min(nr, 16) * n * sizeof(double2));
+    W.mv_part = take(bemk::matvec_part_elems(n, nr) * sizeof(double2));
     W.anblk = bemk::arnoldi_blocks(n);
     W.dot_part = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
     W.dot_part2 = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
@@ -419,15 +419,18 @@ bem_status bem_profile_read(bem_problem* p, bem_profile* out, int reset)
         if (r.kind == bemk::KIND_ASSEMBLE) {
             out->assemble_launches += 1;
             out->assemble_ms += ms;
-        } else {
+        } else if (r.kind == bemk::KIND_MATVEC) {
             out->matvec_launches += 1;
             out->matvec_ms += ms;
+        } else {
+            out->residual_launches += 1;
+            out->residual_ms += ms;
         }
     }
     if (reset) {
         P.recs.clear();
         P.used = 0;
-        P.pending[0] = P.pending[1] = nullptr;
+        for (hipEvent_t& e : P.pending) e = nullptr;
     }
     return BEM_OK;
 }
@@ -538,18 +541,17 @@ bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t 
     const int n = 2 * p->N;
     if (nrhs < 1 || !X_dev || !Y_dev || !work_dev) return fail(BEM_E_ARG, "bad matvec arguments");
     if (ldx < (size_t)n || ldy < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
-    const WorkLayout W = make_work(n, std::min(nrhs, 16), 1);
-    const size_t need = W.mv_part + (size_t)W.splits * std::min(nrhs, 16) * n * sizeof(double2);
+    const size_t need = bemk::matvec_part_elems(n, nrhs) * sizeof(double2);
     if (work_bytes < need) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
     char* w = static_cast<char*>(work_dev);
     if (p->prec == BEM_F64)
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n,
                                        static_cast<const double2*>(X_dev), ldx, nrhs, static_cast<double2*>(Y_dev),
-                                       ldy, reinterpret_cast<double2*>(w + W.mv_part), stream, p->hk()));
+                                       ldy, reinterpret_cast<double2*>(w), stream, p->hk()));
     else
         HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, n, static_cast<const float2*>(X_dev),
                                        ldx, nrhs, static_cast<float2*>(Y_dev), ldy,
-                                       reinterpret_cast<float2*>(w + W.mv_part), stream, p->hk()));
+                                       reinterpret_cast<float2*>(w), stream, p->hk()));
     return BEM_OK;
 }
 

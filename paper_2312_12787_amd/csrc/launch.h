@@ -9,7 +9,7 @@ namespace bemk {
 
 // Optional callback around the main kernel of a launcher (phase 0 before the
 // launch, 1 after), used by the library's HIP-event timing.
-enum { KIND_ASSEMBLE = 0, KIND_MATVEC = 1 };
+enum { KIND_ASSEMBLE = 0, KIND_MATVEC = 1, KIND_RESIDUAL = 2, N_KINDS = 3 };
 struct KernelHook {
     void (*fn)(void* ctx, int kind, int phase, hipStream_t s);
     void* ctx;
@@ -37,8 +37,8 @@ struct AngleChunk {
 hipError_t launch_rhs(const char* g, const GeomLayout& L, int N, const double* angles, int nang, double2* B,
                       size_t ldb, hipStream_t s);
 
-// Y = A X; partial holds splits * nrhs * n complex values.
-int matvec_splits(int n);
+// Y = A X; partial holds matvec_part_elems(n, nrhs) complex values.
+size_t matvec_part_elems(int n, int nrhs);
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s,
                              const KernelHook* hook = nullptr);

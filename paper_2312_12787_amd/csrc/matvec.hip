@@ -4,7 +4,7 @@
 //
 // Layouts: A column-major (lda); X, Y column-major blocks, one column per
 // right-hand side.  Up to 4 right-hand sides: VALU kernel (k_matvec); more:
-// matrix-core kernel (k_matvec_mfma).  Both split the columns over blocks and
+// matrix-core kernel (k_matvec_mfma), up to 64 right-hand sides per pass over A.  Both split the columns over blocks and
 // add the split partial sums in a fixed order (k_matvec_reduce).
 #include <hip/hip_runtime.h>
 
@@ -174,8 +174,10 @@ struct Mfma<float> {
 
 // RT: 16-row tiles per wave (they share each X load); U: column steps in flight;
 // G3: complex product with three real products (P1 = Ar Xr, P2 = Ai Xi,
-// P3 = (Ar + Ai)(Xr + Xi); Yr = P1 - P2, Yi = P3 - P1 - P2) instead of four.
-template <class TA, class T, int RT, int U, bool G3>
+// P3 = (Ar + Ai)(Xr + Xi); Yr = P1 - P2, Yi = P3 - P1 - P2) instead of four;
+// NG: groups of 16 right-hand sides taken in the same pass over A (X packed
+// XT[c * 16 NG + r]), so that one read of A serves up to 64 right-hand sides.
+template <class TA, class T, int RT, int U, bool G3, int NG>
 __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, size_t lda, int n,
                                                     const typename Mfma<T>::v2* __restrict__ XT, int nrhs,
                                                     typename Mfma<T>::v2* __restrict__ part, int cps)
@@ -183,6 +185,7 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
     using M = Mfma<T>;
     using acc = typename M::acc;
     using V2 = typename M::v2;
+    constexpr int XW = 16 * NG;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int row0 = (blockIdx.x * MV_WAVES + wave) * 16 * RT;
@@ -196,94 +199,113 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
     }
     const int c0 = blockIdx.y * cps;
     const int c1 = min(n, c0 + cps);
-    acc rr0[RT], rr1[RT], ii0[RT], ii1[RT];
+    acc rr0[NG][RT], rr1[NG][RT], ii0[NG][RT], ii1[NG][RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) rr0[t] = rr1[t] = ii0[t] = ii1[t] = acc{0, 0, 0, 0};
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) rr0[g][t] = rr1[g][t] = ii0[g][t] = ii1[g][t] = acc{0, 0, 0, 0};
+    // one 16 x 4 tile of A (per row tile) against 4 x 16 NG of X
+    auto step = [&](const T (&ar)[RT], const T (&ai)[RT], const T (&xr)[NG], const T (&xi)[NG]) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (G3) {
+                    rr0[g][t] = M::run(ar[t], xr[g], rr0[g][t]);
+                    rr1[g][t] = M::run(ai[t], xi[g], rr1[g][t]);
+                    ii0[g][t] = M::run(ar[t] + ai[t], xr[g] + xi[g], ii0[g][t]);
+                } else {
+                    rr0[g][t] = M::run(ar[t], xr[g], rr0[g][t]);
+                    rr1[g][t] = M::run(ai[t], -xi[g], rr1[g][t]);
+                    ii0[g][t] = M::run(ar[t], xi[g], ii0[g][t]);
+                    ii1[g][t] = M::run(ai[t], xr[g], ii1[g][t]);
+                }
+            }
+    };
     int c = c0;
     for (; c + 4 * U <= c1; c += 4 * U) {
         TA a[U][RT];
-        V2 x[U];
+        V2 x[U][NG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int col = c + 4 * u + lk;
-            x[u] = XT[(size_t)col * 16 + lr];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
 #pragma unroll
             for (int t = 0; t < RT; ++t) a[u][t] = ap[t][(size_t)col * lda];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            T ar[RT], ai[RT], xr[NG], xi[NG];
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                const T ar = rok[t] ? (T)a[u][t].x : T(0), ai = rok[t] ? (T)a[u][t].y : T(0);
-                if (G3) {
-                    rr0[t] = M::run(ar, x[u].x, rr0[t]);
-                    rr1[t] = M::run(ai, x[u].y, rr1[t]);
-                    ii0[t] = M::run(ar + ai, x[u].x + x[u].y, ii0[t]);
-                } else {
-                    rr0[t] = M::run(ar, x[u].x, rr0[t]);
-                    rr1[t] = M::run(ai, -x[u].y, rr1[t]);
-                    ii0[t] = M::run(ar, x[u].y, ii0[t]);
-                    ii1[t] = M::run(ai, x[u].x, ii1[t]);
-                }
+                ar[t] = rok[t] ? (T)a[u][t].x : T(0);
+                ai[t] = rok[t] ? (T)a[u][t].y : T(0);
             }
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                xr[g] = x[u][g].x;
+                xi[g] = x[u][g].y;
+            }
+            step(ar, ai, xr, xi);
         }
     }
     for (; c < c1; c += 4) {
         const int col = c + lk;
         const bool ok = col < c1;
-        T xr = T(0), xi = T(0);
-        if (ok) {
-            const V2 x = XT[(size_t)col * 16 + lr];
-            xr = x.x;
-            xi = x.y;
+        T ar[RT], ai[RT], xr[NG], xi[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            xr[g] = T(0);
+            xi[g] = T(0);
+            if (ok) {
+                const V2 x = XT[(size_t)col * XW + 16 * g + lr];
+                xr[g] = x.x;
+                xi[g] = x.y;
+            }
         }
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
-            T ar = T(0), ai = T(0);
+            ar[t] = T(0);
+            ai[t] = T(0);
             if (ok && rok[t]) {
                 const TA a = ap[t][(size_t)col * lda];
-                ar = (T)a.x;
-                ai = (T)a.y;
-            }
-            if (G3) {
-                rr0[t] = M::run(ar, xr, rr0[t]);
-                rr1[t] = M::run(ai, xi, rr1[t]);
-                ii0[t] = M::run(ar + ai, xr + xi, ii0[t]);
-            } else {
-                rr0[t] = M::run(ar, xr, rr0[t]);
-                rr1[t] = M::run(ai, -xi, rr1[t]);
-                ii0[t] = M::run(ar, xi, ii0[t]);
-                ii1[t] = M::run(ai, xr, ii1[t]);
+                ar[t] = (T)a.x;
+                ai[t] = (T)a.y;
             }
         }
+        step(ar, ai, xr, xi);
     }
-    if (lr < nrhs) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int r = 16 * g + lr;
+        if (r >= nrhs) continue;
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int r = row0 + 16 * t + M::out_row(lk, j);
-                if (r < n) {
+                const int row = row0 + 16 * t + M::out_row(lk, j);
+                if (row < n) {
                     V2 v;
                     if (G3) {
-                        v.x = rr0[t][j] - rr1[t][j];
-                        v.y = ii0[t][j] - rr0[t][j] - rr1[t][j];
+                        v.x = rr0[g][t][j] - rr1[g][t][j];
+                        v.y = ii0[g][t][j] - rr0[g][t][j] - rr1[g][t][j];
                     } else {
-                        v.x = rr0[t][j] + rr1[t][j];
-                        v.y = ii0[t][j] + ii1[t][j];
+                        v.x = rr0[g][t][j] + rr1[g][t][j];
+                        v.y = ii0[g][t][j] + ii1[g][t][j];
                     }
-                    part[((size_t)blockIdx.y * nrhs + lr) * n + r] = v;
+                    part[((size_t)blockIdx.y * nrhs + r) * n + row] = v;
                 }
             }
     }
 }
 
-// XT[c * 16 + r] = X[r * ldx + c] (r < nr), 0 for nr <= r < 16
+// XT[c * xw + r] = X[r * ldx + c] (r < nr), 0 for nr <= r < xw (xw = 16, 32, 48, 64)
 template <class TX, class V2>
-__global__ void k_pack_xt(const TX* __restrict__ X, size_t ldx, int n, int nr, V2* __restrict__ XT)
+__global__ void k_pack_xt(const TX* __restrict__ X, size_t ldx, int n, int nr, int xw, V2* __restrict__ XT)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = t >> 4, r = t & 15;
+    const int c = t / xw, r = t - c * xw;
     if (c >= n) return;
     V2 v;
     v.x = 0;
@@ -293,24 +315,26 @@ __global__ void k_pack_xt(const TX* __restrict__ X, size_t ldx, int n, int nr, V
         v.x = x.x;
         v.y = x.y;
     }
-    XT[(size_t)c * 16 + r] = v;
+    XT[(size_t)c * xw + r] = v;
 }
 
 // Launch shape of the matrix-core product: row tiles per wave, column steps
-// in flight, column splits.  BEM_MV_CFG="rt,u,splits" overrides it (tuning).
+// in flight, column splits (0: enough for about 1024 blocks), for one group
+// of 16 right-hand sides (BEM_MV_CFG="rt,u,splits[,g3]" overrides it, for
+// tuning) and for 2-4 groups per pass (BEM_MV_CFG_WIDE="rt,u,splits").
 struct MfmaCfg {
     int rt, u, splits, g3;
 };
 
-MfmaCfg mfma_cfg(int n)
+MfmaCfg mfma_cfg(int n, int ng, bool f64)
 {
-    MfmaCfg c{2, 8, 8, 1};
-    if (const char* e = getenv("BEM_MV_CFG")) {
-        int a = 0, b = 0, d = 0, g = 0;
+    MfmaCfg c = ng == 1 ? MfmaCfg{2, 8, 8, 1} : (f64 ? MfmaCfg{1, 4, 0, 1} : MfmaCfg{2, 4, 0, 1});
+    if (const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE")) {
+        int a = 0, b = 0, d = 0, g = 1;
         const int got = sscanf(e, "%d,%d,%d,%d", &a, &b, &d, &g);
-        if (got >= 3 && (a == 1 || a == 2 || a == 4) && (b == 2 || b == 4 || b == 8) && d >= 0 && d <= 64) {
-            c = {a, b, d, got == 4 ? (g != 0) : 0};
-        }
+        const bool ok = ng == 1 ? ((a == 1 || a == 2 || a == 4) && (b == 2 || b == 4 || b == 8))
+                                : ((a == 1 || a == 2) && (b == 2 || b == 4));
+        if (got >= 3 && ok && d >= 0 && d <= 64) c = {a, b, d, ng == 1 && got == 4 ? (g != 0) : 1};
     }
     if (c.splits == 0) {
         const int rowblocks = (n + 16 * c.rt * MV_WAVES - 1) / (16 * c.rt * MV_WAVES);
@@ -322,32 +346,51 @@ MfmaCfg mfma_cfg(int n)
     return c;
 }
 
-int mfma_splits(int n) { return mfma_cfg(n).splits; }
+constexpr int MFMA_MAX_RHS = 64;  // right-hand sides per pass over A
 
 template <class TA, class T, class V2>
-void launch_mfma_variant(const MfmaCfg& c, dim3 grid, hipStream_t s, const TA* A, size_t lda, int n, const V2* xt,
-                         int nr, V2* part, int cps)
+void launch_mfma_variant(const MfmaCfg& c, int ng, dim3 grid, hipStream_t s, const TA* A, size_t lda, int n,
+                         const V2* xt, int nr, V2* part, int cps)
 {
-#define BEM_MV_CASE(RT_, U_)                                                                                   \
-    if (c.rt == RT_ && c.u == U_) {                                                                            \
-        if (c.g3)                                                                                              \
-            hipLaunchKernelGGL((k_matvec_mfma<TA, T, RT_, U_, true>), grid, dim3(BS), 0, s, A, lda, n, xt, nr, part, \
-                               cps);                                                                           \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_matvec_mfma<TA, T, RT_, U_, false>), grid, dim3(BS), 0, s, A, lda, n, xt, nr,    \
-                               part, cps);                                                                     \
-        return;                                                                                                \
+#define BEM_MV_LAUNCH(RT_, U_, G3_, NG_) \
+    hipLaunchKernelGGL((k_matvec_mfma<TA, T, RT_, U_, G3_, NG_>), grid, dim3(BS), 0, s, A, lda, n, xt, nr, part, cps)
+#define BEM_MV_CASE(RT_, U_)                         \
+    if (c.rt == RT_ && c.u == U_) {                  \
+        if (c.g3)                                    \
+            BEM_MV_LAUNCH(RT_, U_, true, 1);         \
+        else                                         \
+            BEM_MV_LAUNCH(RT_, U_, false, 1);        \
+        return;                                      \
     }
-    BEM_MV_CASE(1, 2)
-    BEM_MV_CASE(1, 4)
-    BEM_MV_CASE(1, 8)
-    BEM_MV_CASE(2, 2)
-    BEM_MV_CASE(2, 4)
-    BEM_MV_CASE(2, 8)
-    BEM_MV_CASE(4, 2)
-    BEM_MV_CASE(4, 4)
-    BEM_MV_CASE(4, 8)
+#define BEM_MV_WIDE(RT_, U_)                                  \
+    if (c.rt == RT_ && c.u == U_) {                           \
+        if (ng == 2)                                          \
+            BEM_MV_LAUNCH(RT_, U_, true, 2);                  \
+        else if (ng == 3)                                     \
+            BEM_MV_LAUNCH(RT_, U_, true, 3);                  \
+        else                                                  \
+            BEM_MV_LAUNCH(RT_, U_, true, 4);                  \
+        return;                                               \
+    }
+    if (ng == 1) {
+        BEM_MV_CASE(1, 2)
+        BEM_MV_CASE(1, 4)
+        BEM_MV_CASE(1, 8)
+        BEM_MV_CASE(2, 2)
+        BEM_MV_CASE(2, 4)
+        BEM_MV_CASE(2, 8)
+        BEM_MV_CASE(4, 2)
+        BEM_MV_CASE(4, 4)
+        BEM_MV_CASE(4, 8)
+    } else {
+        BEM_MV_WIDE(1, 2)
+        BEM_MV_WIDE(1, 4)
+        BEM_MV_WIDE(2, 2)
+        BEM_MV_WIDE(2, 4)
+    }
+#undef BEM_MV_WIDE
 #undef BEM_MV_CASE
+#undef BEM_MV_LAUNCH
 }
 
 template <class TA, class TX, class ACC, class TY>
@@ -358,39 +401,37 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
     const int cps = (n + splits - 1) / splits;
     const int rowblocks = (n + 64 * MV_WAVES - 1) / (64 * MV_WAVES);
     using S = decltype(ACC{}.x);
-    for (int r0 = 0; r0 < nrhs; r0 += 16) {
-        const int nr = std::min(16, nrhs - r0);
-        dim3 grid(rowblocks, splits);
+    const int kind = B ? KIND_RESIDUAL : KIND_MATVEC;
+    for (int r0 = 0; r0 < nrhs; r0 += MFMA_MAX_RHS) {
+        const int nr = std::min(MFMA_MAX_RHS, nrhs - r0);
         const TX* Xg = X + (size_t)r0 * ldx;
         if (nr > 4) {
             // pack X right-hand-side fastest into the tail of the partial buffer
-            const MfmaCfg cfg = mfma_cfg(n);
+            const int ng = (nr + 15) / 16;
+            const MfmaCfg cfg = mfma_cfg(n, ng, sizeof(S) == 8);
             const int ms = cfg.splits;
             const int mcps = ((n + ms - 1) / ms + 31) / 32 * 32;
             ACC* xt = part + (size_t)ms * nr * n;
-            hipLaunchKernelGGL((k_pack_xt<TX, ACC>), dim3((n * 16 + BS - 1) / BS), dim3(BS), 0, s, Xg, ldx, n, nr, xt);
-            hook_call(hook, KIND_MATVEC, 0, s);
+            hipLaunchKernelGGL((k_pack_xt<TX, ACC>), dim3(((size_t)n * 16 * ng + BS - 1) / BS), dim3(BS), 0, s, Xg,
+                               ldx, n, nr, 16 * ng, xt);
+            hook_call(hook, kind, 0, s);
             const int rows_per_block = 16 * cfg.rt * MV_WAVES;
-            launch_mfma_variant<TA, S, ACC>(cfg, dim3((n + rows_per_block - 1) / rows_per_block, ms), s, A, lda, n, xt,
-                                            nr, part, mcps);
-            hook_call(hook, KIND_MATVEC, 1, s);
+            launch_mfma_variant<TA, S, ACC>(cfg, ng, dim3((n + rows_per_block - 1) / rows_per_block, ms), s, A, lda,
+                                            n, xt, nr, part, mcps);
+            hook_call(hook, kind, 1, s);
             hipLaunchKernelGGL((k_matvec_reduce<ACC, TY>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, part, ms, n,
                                nr, Y + (size_t)r0 * ldy, ldy, B ? B + (size_t)r0 * ldb : nullptr, ldb);
             continue;
         }
-        hook_call(hook, KIND_MATVEC, 0, s);
+        dim3 grid(rowblocks, splits);
+        hook_call(hook, kind, 0, s);
         if (nr == 1)
             hipLaunchKernelGGL((k_matvec<1, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part, cps);
         else if (nr == 2)
             hipLaunchKernelGGL((k_matvec<2, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part, cps);
-        else if (nr <= 4)
-            hipLaunchKernelGGL((k_matvec<4, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part, cps);
-        else if (nr <= 8)
-            hipLaunchKernelGGL((k_matvec<8, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part, cps);
         else
-            hipLaunchKernelGGL((k_matvec<16, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part,
-                               cps);
-        hook_call(hook, KIND_MATVEC, 1, s);
+            hipLaunchKernelGGL((k_matvec<4, TA, TX, ACC>), grid, dim3(BS), 0, s, A, lda, n, Xg, ldx, nr, part, cps);
+        hook_call(hook, kind, 1, s);
         hipLaunchKernelGGL((k_matvec_reduce<ACC, TY>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, part, splits, n,
                            nr, Y + (size_t)r0 * ldy, ldy, B ? B + (size_t)r0 * ldb : nullptr, ldb);
     }
@@ -411,9 +452,21 @@ int matvec_splits_valu(int n)
     return std::max(1, s);
 }
 
-// partial-sum buffer in units of n complex values: the largest split count any
-// launch shape may use plus the packed copy of X (16 columns)
-int matvec_splits(int n) { return std::max(matvec_splits_valu(n), 64 + 16); }
+// Partial-sum buffer of a product with nrhs right-hand sides, in complex
+// values of the accumulation type: the column-split partial sums of the
+// largest chunk plus the packed copy of X (matrix-core path).  Sized for the
+// FP64 shape; an FP32 product uses the same shape with half-size values.
+size_t matvec_part_elems(int n, int nrhs)
+{
+    const int nr = std::min(nrhs, MFMA_MAX_RHS);
+    size_t e = (size_t)matvec_splits_valu(n) * std::min(nr, 4);
+    if (nr > 4) {
+        const int ng = (nr + 15) / 16;
+        const MfmaCfg c64 = mfma_cfg(n, ng, true), c32 = mfma_cfg(n, ng, false);
+        e = std::max(e, (size_t)std::max(c64.splits, c32.splits) * nr + 16 * ng);
+    }
+    return e * (size_t)n;
+}
 
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s, const KernelHook* hook)

@@ -93,7 +93,9 @@ def test_rhs_matvec_farfield_match_oracle():
     Bo = po.rhs(angles)
     assert rel_err(B, Bo) < 1e-14
     rng = np.random.default_rng(7)
-    for nrhs in (1, 3, 16, 19):
+    # VALU widths, one group of 16 on the matrix cores, 2-4 groups in one pass
+    # over A, and more than 64 (two passes)
+    for nrhs in (1, 3, 16, 19, 33, 48, 64, 70):
         X = rng.standard_normal((g.n, nrhs)) + 1j * rng.standard_normal((g.n, nrhs))
         Y = g.matvec(torch.as_tensor(X.T.copy(), device="cuda")).cpu().numpy().T
         Ao = _A_np(A_t, g.n)
@@ -206,3 +208,21 @@ def test_kite4096_block_solve_residuals_against_oracle_rows():
     scale = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
     _say("sampled residual / rms(b)", np.abs(res).max() / scale.min())
     assert np.abs(res).max() < 1e-7 * scale.min()
+
+
+def test_profile_counts_assembly_products_and_residuals():
+    """The library's kernel timing tallies every assembly, product and
+    residual launch of a solve (FP64 and mixed), and a reset clears it."""
+    P = _gpu()
+    for prec in (P.F64, P.F32):
+        g = P.Problem(W.kite(200, 4.0, 6.0))
+        g.profile(True)
+        g.assemble(prec)
+        X, info = g.solve(g.rhs([0.0, 1.0, 2.0, 3.0, 4.0, 5.0]), restart=20, tol=1e-10, inner_tol=1e-5)
+        pr = g.profile_read(reset=True)
+        _say("profile", prec, pr, "iters", info.iters.tolist(), "restarts", info.restarts.tolist())
+        assert pr["assemble_launches"] == 1 and pr["assemble_ms"] > 0
+        assert pr["matvec_launches"] >= info.iters.max() and pr["matvec_ms"] > 0
+        assert pr["residual_launches"] >= 1 and pr["residual_ms"] > 0
+        assert g.profile_read(reset=True)["matvec_launches"] == 0
+        g.profile(False)

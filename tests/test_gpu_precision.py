@@ -79,10 +79,51 @@ def test_fp32_matvec_matches_fp64_product_of_fp32_matrix():
     A32 = g.assemble(P.F32)
     A = A32.T[:g.n].cpu().numpy().astype(np.complex128)
     rng = np.random.default_rng(3)
-    for nrhs in (1, 4, 16, 21):
+    for nrhs in (1, 4, 16, 21, 40, 64, 67):
         X = (rng.standard_normal((g.n, nrhs)) + 1j * rng.standard_normal((g.n, nrhs))).astype(np.complex64)
         Y = g.matvec(torch.as_tensor(X.T.copy(), device="cuda")).cpu().numpy().T
         Yo = A @ X.astype(np.complex128)
         err = np.abs(Y - Yo).max() / np.abs(Yo).max()
         print("fp32 matvec nrhs", nrhs, err, flush=True)
         assert err < 2e-6
+
+
+@pytest.mark.parametrize("k1", [30.0, 30.0 + 0.3j], ids=["k1=30", "k1=30+0.3i"])
+def test_precision_path_full_size_kite16384(k1):
+    """The precision workload at full size: kite with N = 16384 (32768 x 32768),
+    k0 = 20, 64 equispaced angles as one block.  Mixed path (FP32 matrix and
+    products, FP64 refinement to 1e-8) against the FP64 path solved to 1e-12:
+    far field at 360 directions within 1e-6 for every angle.  The FP64
+    solution itself is checked on sampled rows of the oracle's matrix."""
+    P = _gpu()
+    spec = W.kite(16384, 20.0, k1)
+    ang = W.equispaced_angles(64)
+    dirs = W.equispaced_angles(360)
+    g = P.Problem(spec)
+    print("precision full size k1", k1, "n", g.n, flush=True)
+    A32 = g.assemble(P.F32)
+    X, info = g.solve(g.rhs(ang), restart=100, tol=1e-8, inner_tol=1e-5)
+    print("  mixed: iters mean", info.iters.mean(), "max", info.iters.max(), "refinement steps",
+          info.restarts.max(), "rel res", info.rel_residual.max(), flush=True)
+    assert info.converged.all()
+    F = g.farfield(X, dirs)
+    del A32, X
+    torch.cuda.empty_cache()
+    g.assemble(P.F64)
+    B = g.rhs(ang)
+    Xr, ir = g.solve(B, restart=100, tol=1e-12, max_iter=5000)
+    print("  fp64: iters mean", ir.iters.mean(), "rel res", ir.rel_residual.max(), flush=True)
+    assert ir.converged.all()
+    Fr = g.farfield(Xr, dirs)
+    err = (torch.linalg.vector_norm(F - Fr, dim=1) / torch.linalg.vector_norm(Fr, dim=1)).max().item()
+    print("  far-field error of the mixed path (max over 64 angles)", err, flush=True)
+    assert err < 1e-6
+    rows = np.array([0, 5000, 16383, 16384, 25000, 32767], dtype=np.int32)
+    po = O.Problem(spec)
+    Ar = po.assemble_rows(rows)
+    Bo = po.rhs(ang[:4])
+    Xo = Xr[:4].cpu().numpy().T
+    res = Bo[rows] - Ar @ Xo
+    scale = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
+    print("  oracle-row residual / rms(b)", (np.abs(res) / scale).max(), flush=True)
+    assert (np.abs(res) / scale).max() < 1e-9

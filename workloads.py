@@ -206,6 +206,8 @@ class Workload:
     restart: int
     tol: float
     far_dirs: np.ndarray = field(default_factory=lambda: equispaced_angles(360))
+    precision: str = "f64"       # "f32": FP32 matrix and products, FP64 refinement
+    inner_tol: float = 1e-5      # inner (FP32-product) GMRES tolerance of the mixed path
 
 
 def workload_disk256() -> Workload:
@@ -229,8 +231,13 @@ def workload_sectors(h: float = 1.0 / 800) -> Workload:
     return Workload(f"sectors{spec.n_elements}_k10-12-18-9+0.5i", [spec], np.array([0.0]), 100, 1e-10)
 
 
-def workload_kite16384_fp32(n: int = 16384) -> Workload:
-    return Workload(f"kite{n}_k20-30_x64", [kite(n, 20.0, 30.0)], equispaced_angles(64), 100, 1e-6)
+def workload_kite16384_fp32(n: int = 16384, k1: complex = 30.0) -> Workload:
+    """Precision path: the kite refined to N = 16384 (32768 x 32768 complex64
+    matrix), k0 = 20, k1 = 30, 64 equispaced angles as one block, GMRES(100)
+    with FP32 products inside FP64 residual refinement to 1e-8 (far field
+    within 1e-6 of the FP64 solution at 360 directions)."""
+    return Workload(f"kite{n}_k20-{k1:g}_x64_mixed", [kite(n, 20.0, k1)], equispaced_angles(64), 100, 1e-8,
+                    precision="f32")
 
 
 def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0):
