@@ -186,12 +186,105 @@ def fp64_comparison(wl, probs, P, torch, F_mixed):
                          f"{len(wl.far_dirs)} directions, max over right-hand sides of the relative 2-norm error"}
 
 
+def serve_mode(args, P, torch):
+    """Served stream: requests with Poisson arrivals at 20/s, perturbed circles
+    with N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32
+    angles.  Capacity: every request submitted at once (closed loop), solves/s
+    = right-hand sides / wall time, for the mixed server and the FP64 server;
+    accuracy: far field of every request, mixed against FP64.  Latency: the
+    arrivals replayed in real time (open loop) on the mixed server, p50/p99 of
+    completion minus arrival."""
+    import workloads as W
+    from paper_2312_12787_amd import serve as S
+    reqs = W.request_stream(args.requests)
+    dirs = W.equispaced_angles(360)
+    arena = int(args.arena_gb * (1 << 30))
+    solves = sum(len(r["angles"]) for r in reqs)
+
+    def closed_loop(prec, tol):
+        with S.Server(arena, slots=args.slots, prec=prec, tol=tol, dirs=dirs) as srv:
+            for r in reqs[:8]:  # warm-up: code objects, host paths
+                srv.submit(r["spec"], r["angles"])
+            srv.drain()
+            t0 = time.perf_counter()
+            ids = {srv.submit(r["spec"], r["angles"]): i for i, r in enumerate(reqs)}
+            out = srv.drain()
+            T = time.perf_counter() - t0
+            st = srv.stats()
+        res = {ids[o.id]: o for o in out}
+        return T, res, st
+
+    log(f"serve: {len(reqs)} requests, {solves} solves, closed loop, mixed ...")
+    T32, r32, st32 = closed_loop(P.F32, args.serve_tol)
+    log(f"  {T32:.1f} s; FP64 ...")
+    T64, r64, _ = closed_loop(P.F64, args.serve_tol)
+    log(f"  {T64:.1f} s")
+    bad = [i for i in range(len(reqs)) if r32[i].status != 0 or r64[i].status != 0]
+    err = max(float(np.max(np.linalg.norm(r32[i].far_field - r64[i].far_field, axis=1) /
+                           np.linalg.norm(r64[i].far_field, axis=1))) for i in range(len(reqs)))
+    lat = []
+    if not args.no_open_loop:
+        log("  open loop at the arrival times ...")
+        with S.Server(arena, slots=args.slots, prec=P.F32, tol=args.serve_tol, dirs=dirs) as srv:
+            for r in reqs[:8]:
+                srv.submit(r["spec"], r["angles"])
+            srv.drain()
+            t0 = time.perf_counter()
+            lag = {}
+            for r in reqs:
+                dt = r["arrival"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                late = (time.perf_counter() - t0) - r["arrival"]
+                lag[srv.submit(r["spec"], r["angles"])] = late
+                lat.extend(srv.poll(0))
+            lat.extend(srv.drain())
+        # latency = completion - arrival: the server's own submit-to-done time
+        # plus how late the replay submitted the request
+        lat_ms = np.array([(o.t_done - o.t_submit + lag[o.id]) * 1e3 for o in lat])
+    out = {
+        "metric": METRIC,
+        "value": solves / T32,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": T32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"served stream: {len(reqs)} requests, Poisson 20/s, perturbed circles N 512-8192 "
+                               f"log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
+                   "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
+                   "tol": args.serve_tol, "restart": 100, "far_field_dirs": len(dirs)},
+        "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
+                     "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
+                     "arena_high_water_GiB": st32["arena_high_water"] / 2**30},
+        "accuracy": {"far_field_rel_err_mixed_vs_fp64_max": err, "failed_requests": bad},
+        "gmres_iterations_max_per_request": {"p50": float(np.median([r32[i].iters_max for i in r32])),
+                                             "max": int(max(r32[i].iters_max for i in r32))},
+        "roofline": None,
+    }
+    if lat:
+        out["latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                             "unit": "open loop at the stream's arrival times: completion - submission, mixed server"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kite4096", choices=["kite4096", "disk256", "sectors", "kite16384_mixed"])
+    ap.add_argument("--workload", default="kite4096",
+                    choices=["kite4096", "disk256", "sectors", "kite16384_mixed", "serve"])
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
+    ap.add_argument("--slots", type=int, default=4, help="serve: requests in flight")
+    ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: device arena in GiB")
+    ap.add_argument("--serve-tol", type=float, default=1e-8, help="serve: GMRES / refinement tolerance")
+    ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "matvec"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
@@ -208,6 +301,8 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        return serve_mode(args, P, torch)
     wl = {"kite4096": W.workload_kite4096, "disk256": W.workload_disk256,
           "sectors": W.workload_sectors, "kite16384_mixed": W.workload_kite16384_fp32}[args.workload]()
     mixed = wl.precision == "f32"

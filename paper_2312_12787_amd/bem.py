@@ -131,6 +131,36 @@ class SolveInfo:
     status: int
 
 
+def make_desc(spec):
+    """bem_desc of a problem statement (attributes k, interfaces with xy,
+    closed, dom_left, dom_right, and quad, form, alpha, beta, bm_coef); returns
+    (desc, keep) where keep holds the ctypes arrays desc points into."""
+    ks = list(spec.k)
+    n_nodes = [len(f.xy) for f in spec.interfaces]
+    xy = np.ascontiguousarray(np.concatenate([np.asarray(f.xy, np.float64) for f in spec.interfaces]).ravel())
+    keep = dict(k=_zarr(ks), nn=(C.c_int * len(n_nodes))(*n_nodes),
+                cl=(C.c_int * len(n_nodes))(*[1 if f.closed else 0 for f in spec.interfaces]),
+                dl=(C.c_int * len(n_nodes))(*[int(f.dom_left) for f in spec.interfaces]),
+                dr=(C.c_int * len(n_nodes))(*[int(f.dom_right) for f in spec.interfaces]),
+                xy=xy, alpha=_zptr(spec.alpha), beta=_zptr(spec.beta),
+                bm=_zarr(spec.bm_coef) if spec.bm_coef is not None else None)
+    d = bem_desc()
+    d.n_dom = len(ks)
+    d.k = C.cast(keep["k"], C.POINTER(bem_z))
+    d.n_if = len(n_nodes)
+    d.n_nodes = keep["nn"]
+    d.closed = keep["cl"]
+    d.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+    d.dom_left = keep["dl"]
+    d.dom_right = keep["dr"]
+    d.quad = int(spec.quad)
+    d.form = int(spec.form)
+    d.alpha = keep["alpha"][1]
+    d.beta = keep["beta"][1]
+    d.bm_coef = C.cast(keep["bm"], C.POINTER(bem_z)) if keep["bm"] is not None else None
+    return d, keep
+
+
 class Problem:
     """A transmission problem on the GPU.
 
@@ -143,32 +173,7 @@ class Problem:
         L = lib()
         self.spec = spec
         self.device = torch.device(device)
-        ks = list(spec.k)
-        n_nodes = [len(f.xy) for f in spec.interfaces]
-        xy = np.ascontiguousarray(np.concatenate([np.asarray(f.xy, np.float64) for f in spec.interfaces]).ravel())
-        self._k = _zarr(ks)
-        self._nn = (C.c_int * len(n_nodes))(*n_nodes)
-        self._cl = (C.c_int * len(n_nodes))(*[1 if f.closed else 0 for f in spec.interfaces])
-        self._dl = (C.c_int * len(n_nodes))(*[int(f.dom_left) for f in spec.interfaces])
-        self._dr = (C.c_int * len(n_nodes))(*[int(f.dom_right) for f in spec.interfaces])
-        self._xy = xy
-        self._alpha = _zptr(spec.alpha)
-        self._beta = _zptr(spec.beta)
-        self._bm = _zarr(spec.bm_coef) if spec.bm_coef is not None else None
-        d = bem_desc()
-        d.n_dom = len(ks)
-        d.k = C.cast(self._k, C.POINTER(bem_z))
-        d.n_if = len(n_nodes)
-        d.n_nodes = self._nn
-        d.closed = self._cl
-        d.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
-        d.dom_left = self._dl
-        d.dom_right = self._dr
-        d.quad = int(spec.quad)
-        d.form = int(spec.form)
-        d.alpha = self._alpha[1]
-        d.beta = self._beta[1]
-        d.bm_coef = C.cast(self._bm, C.POINTER(bem_z)) if self._bm is not None else None
+        d, self._keep = make_desc(spec)
         h = C.c_void_p()
         _check(L.bem_create(C.byref(d), C.byref(h)))
         self._h = h

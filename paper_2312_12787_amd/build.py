@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbem_hip.so")
-SOURCES = ["assemble.hip", "linalg.hip", "matvec.hip", "bem_api.cpp"]
+SOURCES = ["assemble.hip", "linalg.hip", "matvec.hip", "bem_api.cpp", "serve.cpp"]
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -19,7 +19,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     common = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result"]
+              "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result", "-pthread"]
     objs = []
     procs = []
     for src in SOURCES:
@@ -33,7 +33,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     bad = [p.wait() for p in procs]
     if any(bad):
         raise RuntimeError("hipcc failed")
-    link = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
+    link = [hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -107,6 +107,7 @@ struct bem_problem {
     int* pinned = nullptr;
     size_t pinned_ints = 0;
     hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    bool lent = false;  // pinned / flag_ev belong to the caller (request server slot)
     // device state recorded by the calls
     char* geom = nullptr;
     void* A = nullptr;
@@ -392,9 +393,11 @@ void bem_destroy(bem_problem* p)
 {
     if (!p) return;
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
-    for (hipEvent_t e : p->flag_ev)
-        if (e) (void)hipEventDestroy(e);
-    if (p->pinned) (void)hipHostFree(p->pinned);
+    if (!p->lent) {
+        for (hipEvent_t e : p->flag_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (p->pinned) (void)hipHostFree(p->pinned);
+    }
     delete p;
 }
 
@@ -662,6 +665,7 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     HIP_OK(hipMemcpyAsync(c.at<double>(c.W.thr), thr.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
     HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), iters.data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
     if (c.p->pinned_ints < (size_t)2 * nr) {
+        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than 2 * nrhs");
         if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
         c.p->pinned = nullptr;
         HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), 2 * nr * sizeof(int), hipHostMallocDefault));
@@ -830,3 +834,22 @@ bem_status bem_farfield(const bem_problem* p, int nrhs, const void* X_dev, size_
 }
 
 }  // extern "C"
+
+namespace bemk {
+
+// The request server keeps one pinned flag buffer and two events per slot and
+// lends them to each problem it runs, so that no request allocates or frees
+// pinned memory (hipHostFree may wait for the whole device).
+void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, hipEvent_t e0, hipEvent_t e1)
+{
+    p->pinned = pinned;
+    p->pinned_ints = ints;
+    p->flag_ev[0] = e0;
+    p->flag_ev[1] = e1;
+    p->lent = true;
+}
+
+// bem_last_error() text for the calls of the request server.
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace bemk

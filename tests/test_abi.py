@@ -1,5 +1,5 @@
 """The C-ABI library (no GPU needed): it loads, exports every function that
-include/bem.h declares, and its host-only paths (validation, planning, sizes,
+include/bem.h and include/bem_serve.h declare, and its host-only paths (validation, planning, sizes,
 call-order errors) behave as documented.  No call here launches device work."""
 import ctypes as C
 import os
@@ -14,19 +14,53 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "bem.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bem_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(bem_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     import paper_2312_12787_amd as P
+    from paper_2312_12787_amd.serve import SERVE_EXPORTS
     L = P.lib()
     names = _declared()
-    assert "bem_solve" in names and "bem_assemble" in names and len(names) >= 14
+    assert "bem_solve" in names and "bem_assemble" in names and "bem_server_submit" in names
     for nm in names:
         assert hasattr(L, nm), nm
-    assert sorted(P.EXPORTS) == names
+    assert sorted(P.EXPORTS + SERVE_EXPORTS) == names
+
+
+def test_server_option_validation_before_any_device_work():
+    """bem_server_create rejects bad options from the host, before it selects
+    a device or creates a stream."""
+    import paper_2312_12787_amd as P
+    from paper_2312_12787_amd import serve as S
+    L = S._serve_lib()
+    dirs = np.zeros(4)
+
+    def opts(**kw):
+        o = S.bem_server_opts()
+        o.slots, o.device, o.arena_dev, o.arena_bytes, o.prec = 4, 0, 1 << 20, 1 << 30, P.F32
+        o.solve = P.bem.bem_solve_opts(100, 1000, 1e-8, 1e-5, 0)
+        o.ndir, o.dirs = 4, dirs.ctypes.data_as(C.POINTER(C.c_double))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    for bad in (dict(slots=0), dict(slots=17), dict(arena_dev=None), dict(arena_dev=(1 << 20) + 8),
+                dict(ndir=0), dict(ndir=5000), dict(prec=7), dict(dirs=None)):
+        h = C.c_void_p()
+        st = L.bem_server_create(C.byref(opts(**bad)), C.byref(h))
+        assert P.STATUS[st] == "BEM_E_ARG", bad
+        assert h.value is None
+    o = opts()
+    o.solve = P.bem.bem_solve_opts(0, 1000, 1e-8, 1e-5, 0)
+    assert P.STATUS[L.bem_server_create(C.byref(o), C.byref(C.c_void_p()))] == "BEM_E_ARG"
+    assert "solve options" in L.bem_last_error().decode()
 
 
 def _problem(spec):

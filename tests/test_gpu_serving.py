@@ -1,0 +1,126 @@
+"""Served path (continuous batching, include/bem_serve.h) on the GPU.
+
+* Each request's far field is the same alone (one slot, one request at a
+  time) and in the mix (several slots, all requests in flight together),
+  within 1e-6 (the path's reductions have a fixed order, so it is in fact
+  bit-identical).
+* Served results agree with the oracle's FP64 LU solution within 1e-6.
+* Admission by footprint: the arena never holds more than it has, requests
+  wait for memory instead of failing, and one larger than the whole arena is
+  refused at submission.
+* A request that does not converge is reported as such and does not stop
+  the server.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_12787_amd as P
+    from paper_2312_12787_amd import serve as S
+    return P, S
+
+
+def _small_stream(n, seed=1):
+    return W.request_stream(n, seed=seed, n_range=(64, 600), k0_range=(1.0, 12.0), max_rhs=12)
+
+
+def _rel(a, b):
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+
+
+DIRS = W.equispaced_angles(72)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F64"])
+def test_each_result_is_the_same_alone_and_in_the_mix(prec):
+    P, S = _gpu()
+    pr = getattr(P, prec)
+    reqs = _small_stream(24)
+    print("requests", [(r["spec"].n_elements, len(r["angles"])) for r in reqs], flush=True)
+    alone = {}
+    with S.Server(1 << 30, slots=1, prec=pr, dirs=DIRS) as srv:
+        for i, r in enumerate(reqs):
+            srv.submit(r["spec"], r["angles"])
+            (res,) = srv.drain()
+            assert res.status == 0, res.message
+            alone[i] = res.far_field
+    with S.Server(4 << 30, slots=4, prec=pr, dirs=DIRS) as srv:
+        ids = {srv.submit(r["spec"], r["angles"]): i for i, r in enumerate(reqs)}
+        mixed = srv.drain()
+        st = srv.stats()
+    overlap = 0
+    for a in mixed:
+        overlap += sum(1 for b in mixed if b.id != a.id and b.t_admit < a.t_done and a.t_admit < b.t_done)
+    print("pairs of requests that overlapped in time", overlap // 2, "arena high water", st["arena_high_water"],
+          flush=True)
+    assert overlap > 0
+    worst = 0.0
+    for res in mixed:
+        assert res.status == 0, res.message
+        worst = max(worst, _rel(res.far_field, alone[ids[res.id]]))
+    print("largest relative far-field difference alone vs mix", worst, flush=True)
+    assert worst <= 1e-6
+
+
+def test_served_results_match_the_oracle():
+    P, S = _gpu()
+    reqs = _small_stream(4, seed=5)
+    with S.Server(1 << 30, slots=3, prec=P.F32, tol=1e-8, dirs=DIRS) as srv:
+        ids = {srv.submit(r["spec"], r["angles"]): i for i, r in enumerate(reqs)}
+        out = srv.drain()
+    for res in out:
+        r = reqs[ids[res.id]]
+        po = O.Problem(r["spec"])
+        Xo = np.linalg.solve(po.assemble(), po.rhs(r["angles"]))
+        Fo = po.farfield(Xo, DIRS).T
+        e = _rel(res.far_field, Fo)
+        print("request", ids[res.id], "N", r["spec"].n_elements, "k0", r["spec"].k[0], "rhs", len(r["angles"]),
+              "iters", res.iters_max, "refine", res.refine_max, "far-field error vs oracle", e, flush=True)
+        assert res.status == 0 and e < 1e-6
+
+
+def test_admission_by_footprint():
+    P, S = _gpu()
+    reqs = _small_stream(10, seed=7)
+    with S.Server(64 << 20, slots=4, prec=P.F32, dirs=DIRS) as probe:
+        fps = [probe.footprint(r["spec"], len(r["angles"])) for r in reqs]
+    arena = int(max(fps) * 1.6) // 256 * 256
+    print("footprints MB", [round(f / 2**20, 1) for f in fps], "arena MB", arena / 2**20, flush=True)
+    with S.Server(arena, slots=4, prec=P.F32, dirs=DIRS) as srv:
+        big = W.request_stream(1, seed=3, n_range=(4000, 4001))[0]
+        with pytest.raises(P.BemError, match="BEM_E_NOMEM"):
+            srv.submit(big["spec"], big["angles"])
+        for r in reqs:
+            srv.submit(r["spec"], r["angles"])
+        out = srv.drain()
+        st = srv.stats()
+    assert len(out) == len(reqs) and all(o.status == 0 for o in out)
+    assert st["arena_high_water"] <= arena and st["arena_in_use"] == 0
+    # at every admission instant the running requests fit in the arena
+    for a in out:
+        live = sum(b.footprint for b in out if b.t_admit <= a.t_admit < b.t_done)
+        assert live <= arena
+    waited = sum(1 for o in out if o.t_admit - o.t_submit > 1e-3)
+    print("requests that waited for memory or a slot", waited, flush=True)
+    assert waited > 0
+
+
+def test_nonconvergence_is_reported_and_the_server_goes_on():
+    P, S = _gpu()
+    reqs = _small_stream(3, seed=11)
+    with S.Server(1 << 30, slots=2, prec=P.F64, tol=1e-14, max_iter=3, restart=3, dirs=DIRS) as srv:
+        for r in reqs:
+            srv.submit(r["spec"], r["angles"])
+        out = srv.drain()
+    assert len(out) == 3
+    for o in out:
+        assert P.STATUS[o.status] == "BEM_E_NOCONV" and o.iters_max <= 3 and np.isfinite(o.far_field).all()

@@ -240,9 +240,13 @@ def workload_kite16384_fp32(n: int = 16384, k1: complex = 30.0) -> Workload:
                     precision="f32")
 
 
-def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0):
-    """Served-path request stream: Poisson arrivals, Fourier-perturbed circles,
-    N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32 angles."""
+def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0, n_range=(512, 8192),
+                   k0_range=(1.0, 50.0), ratio_range=(1.2, 3.0), max_rhs: int = 32):
+    """Served-path request stream: Poisson arrivals at `rate` per second,
+    Fourier-perturbed circles r(t) = 1 + sum_{m=2..6} a_m cos(m t + phi_m) with
+    a_m ~ U(0, 0.08), phi_m ~ U(0, 2 pi), N log-uniform in n_range, k0 ~ U(k0_range),
+    k1 / k0 ~ U(ratio_range) (real), 1..max_rhs incident angles ~ U(0, 2 pi).
+    One SeedSequence child per request, so request i does not depend on n_requests."""
     ss = np.random.SeedSequence(seed)
     rng_t = np.random.default_rng(ss.spawn(1)[0])
     gaps = rng_t.exponential(1.0 / rate, size=n_requests)
@@ -252,10 +256,10 @@ def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0):
         rng = np.random.default_rng(child)
         amps = rng.uniform(0.0, 0.08, size=5)
         phases = rng.uniform(0.0, 2 * np.pi, size=5)
-        n = int(round(math.exp(rng.uniform(math.log(512), math.log(8192)))))
-        k0 = float(rng.uniform(1.0, 50.0))
-        ratio = float(rng.uniform(1.2, 3.0))
-        nrhs = int(rng.integers(1, 33))
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        k0 = float(rng.uniform(*k0_range))
+        ratio = float(rng.uniform(*ratio_range))
+        nrhs = int(rng.integers(1, max_rhs + 1))
         angles = rng.uniform(0.0, 2 * np.pi, size=nrhs)
         spec = single_material(perturbed_circle_nodes(n, amps, phases), k0, k0 * ratio,
                                name=f"req{i}")
