@@ -106,7 +106,7 @@ struct bem_problem {
     // pinned host slots for the asynchronous read-back of the GMRES flags
     int* pinned = nullptr;
     size_t pinned_ints = 0;
-    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    hipEvent_t flag_ev[bemk::FLAG_RING] = {};
     bool lent = false;  // pinned / flag_ev belong to the caller (request server slot)
     // device state recorded by the calls
     char* geom = nullptr;
@@ -629,7 +629,19 @@ bem_status upload_ints(const Solver& c, size_t off, const std::vector<int>& v)
 // classical Gram-Schmidt with one re-orthogonalisation; the true residual is
 // recomputed at the end of each cycle.  Columns with want[r] == 0 are left
 // untouched.  iters[r] counts Arnoldi products.
-bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, double tol, int maxit,
+// Steps the host runs ahead of the GPU's stopping flags: 1 for matrices of
+// 128 MB and more (a product outlasts the host's work for a step), up to
+// FLAG_RING - 1 for small ones.
+int flag_lag(int n, int prec)
+{
+    const double bytes = (double)n * n * (prec == BEM_F32 ? 8.0 : 16.0);
+    if (bytes >= 128e6) return 1;
+    if (bytes >= 32e6) return 2;
+    return bemk::FLAG_RING - 1;
+}
+
+bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, const std::vector<double>& tol,
+                 int maxit,
                  const std::vector<int>& want, std::vector<int>& iters, std::vector<int>& conv,
                  std::vector<double>& rel, std::vector<int>& cycles, bool& nonfinite)
 {
@@ -661,26 +673,35 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     }
     // device-side stopping thresholds and counters
     std::vector<double> thr(nr);
-    for (int r = 0; r < nr; ++r) thr[r] = tol * bnorm[r];
+    for (int r = 0; r < nr; ++r) thr[r] = tol[(size_t)r] * bnorm[r];
     HIP_OK(hipMemcpyAsync(c.at<double>(c.W.thr), thr.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
     HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), iters.data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
-    if (c.p->pinned_ints < (size_t)2 * nr) {
-        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than 2 * nrhs");
+    // The GPU decides per right-hand side when to stop (k_arnoldi_step); the
+    // host reads the flags `lag` steps behind, so the queue never drains.  A
+    // small matrix gets a longer lag (its steps are shorter than the host's
+    // launch work); steps enqueued after every column stopped do nothing but
+    // an unused product.
+    const int lag = flag_lag(n, c.p->prec);
+    const int ring = lag + 1;
+    if (c.p->pinned_ints < (size_t)ring * nr) {
+        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than (lag + 1) * nrhs");
         if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
         c.p->pinned = nullptr;
-        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), 2 * nr * sizeof(int), hipHostMallocDefault));
-        c.p->pinned_ints = 2 * nr;
+        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), (size_t)ring * nr * sizeof(int),
+                             hipHostMallocDefault));
+        c.p->pinned_ints = (size_t)ring * nr;
     }
-    for (auto& e : c.p->flag_ev)
-        if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int k = 0; k < ring; ++k)
+        if (!c.p->flag_ev[k]) {
+            if (c.p->lent) return fail(BEM_E_ARG, "lent flag events fewer than lag + 1");
+            HIP_OK(hipEventCreateWithFlags(&c.p->flag_ev[k], hipEventDisableTiming));
+        }
     std::vector<int> dev_iters(nr);
     while (std::count(alive.begin(), alive.end(), 1) > 0) {
         if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
         HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
         HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
                                         c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
-        // The GPU decides per right-hand side when to stop (k_arnoldi_step);
-        // the host reads the flags one step behind, so the queue never drains.
         for (int j = 0; j < m; ++j) {
             if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
             HIP_OK(bemk::launch_arnoldi(c.V(0), ldv, nr, j, m, n, Wv, ldv, c.at<double2>(c.W.dot_part),
@@ -689,12 +710,12 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
                                         c.at<double2>(c.W.sn), c.at<double2>(c.W.gvec), c.at<double>(c.W.hnorm),
                                         c.at<double>(c.W.resid), c.at<double>(c.W.thr), maxit, c.at<int>(c.W.iters),
                                         c.at<int>(c.W.kdim), c.at<int>(c.W.active), c.s));
-            int* slot = c.p->pinned + (j & 1) * nr;
+            int* slot = c.p->pinned + (size_t)(j % ring) * nr;
             HIP_OK(hipMemcpyAsync(slot, c.at<int>(c.W.active), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
-            HIP_OK(hipEventRecord(c.p->flag_ev[j & 1], c.s));
-            if (j >= 1) {
-                HIP_OK(hipEventSynchronize(c.p->flag_ev[(j - 1) & 1]));
-                const int* prev = c.p->pinned + ((j - 1) & 1) * nr;
+            HIP_OK(hipEventRecord(c.p->flag_ev[j % ring], c.s));
+            if (j >= lag) {
+                HIP_OK(hipEventSynchronize(c.p->flag_ev[(j - lag) % ring]));
+                const int* prev = c.p->pinned + (size_t)((j - lag) % ring) * nr;
                 bool any = false;
                 for (int r = 0; r < nr; ++r) any = any || prev[r];
                 if (!any) break;
@@ -714,7 +735,7 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
             if (!std::isfinite(rel[r])) {
                 nonfinite = true;
                 alive[r] = 0;
-            } else if (rel[r] <= tol) {
+            } else if (rel[r] <= tol[(size_t)r]) {
                 conv[r] = 1;
                 alive[r] = 0;
             } else if (iters[r] >= maxit) {
@@ -750,7 +771,8 @@ bem_status bem_solve(bem_problem* p, int nrhs, const void* B_dev, size_t ldb, co
     std::vector<double> rel(nrhs, 1.0);
     bool nonfinite = false;
     if (p->prec == BEM_F64) {
-        if (bem_status st = gmres(c, B, ldb, X, ldx, opts->tol, opts->max_iter, want, iters, conv, rel, cycles,
+        const std::vector<double> tols((size_t)nrhs, opts->tol);
+        if (bem_status st = gmres(c, B, ldb, X, ldx, tols, opts->max_iter, want, iters, conv, rel, cycles,
                                   nonfinite))
             return st;
     } else {
@@ -787,10 +809,16 @@ bem_status bem_solve(bem_problem* p, int nrhs, const void* B_dev, size_t ldb, co
                 }
             }
             if (!any) break;
+            // inner tolerance: inner_tol, or less if that already takes the
+            // outer residual below half the target
+            std::vector<double> tols((size_t)nrhs, inner_tol);
+            for (int r = 0; r < nrhs; ++r)
+                if (active[r] && rnorm[r] > 0.0)
+                    tols[(size_t)r] = std::max(inner_tol, 0.5 * opts->tol * bnorm[r] / rnorm[r]);
             std::vector<int> it2(nrhs, 0), conv2(nrhs, 0), cyc2(nrhs, 0);
             std::vector<double> rel2(nrhs, 1.0);
             bool nf2 = false;
-            if (bem_status st = gmres(c, Ro, ldv, D, ldv, inner_tol, opts->max_iter, active, it2, conv2, rel2, cyc2,
+            if (bem_status st = gmres(c, Ro, ldv, D, ldv, tols, opts->max_iter, active, it2, conv2, rel2, cyc2,
                                       nf2))
                 return st;
             if (nf2) nonfinite = true;
@@ -837,15 +865,14 @@ bem_status bem_farfield(const bem_problem* p, int nrhs, const void* X_dev, size_
 
 namespace bemk {
 
-// The request server keeps one pinned flag buffer and two events per slot and
+// The request server keeps one pinned flag buffer and FLAG_RING events per slot and
 // lends them to each problem it runs, so that no request allocates or frees
 // pinned memory (hipHostFree may wait for the whole device).
-void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, hipEvent_t e0, hipEvent_t e1)
+void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, const hipEvent_t* ev)
 {
     p->pinned = pinned;
     p->pinned_ints = ints;
-    p->flag_ev[0] = e0;
-    p->flag_ev[1] = e1;
+    for (int k = 0; k < FLAG_RING; ++k) p->flag_ev[k] = ev[k];
     p->lent = true;
 }
 

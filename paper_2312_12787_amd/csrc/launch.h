@@ -10,6 +10,8 @@ namespace bemk {
 // Optional callback around the main kernel of a launcher (phase 0 before the
 // launch, 1 after), used by the library's HIP-event timing.
 enum { KIND_ASSEMBLE = 0, KIND_MATVEC = 1, KIND_RESIDUAL = 2, N_KINDS = 3 };
+// GMRES stopping-flag read-back: ring of pinned slots and events (host lag + 1)
+constexpr int FLAG_RING = 5;
 struct KernelHook {
     void (*fn)(void* ctx, int kind, int phase, hipStream_t s);
     void* ctx;

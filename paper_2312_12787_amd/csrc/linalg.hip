@@ -7,6 +7,9 @@
 // All reductions run in a fixed order, so repeated runs are bitwise equal.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "internal.h"
 #include "launch.h"
 
@@ -15,16 +18,35 @@ namespace bemk {
 namespace {
 
 constexpr int BS = 256;        // threads per block
-constexpr int DOT_BATCH = 8;   // basis vectors reduced together
 
 template <class T>
 __device__ __forceinline__ const T* tab(const char* g, size_t off) { return reinterpret_cast<const T*>(g + off); }
 
+// Move a double between lanes with a DPP pattern (two 32-bit moves); lanes
+// whose row is masked off or whose source is out of range receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane (GFX9 DPP: quad
+// swaps, half-row and row mirrors give each 16-lane row its sum; the row
+// broadcasts of lanes 15 and 31 then collect the four rows into row 3, and
+// lane 63 is read out).
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xf>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xf>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum NV values over the 256 threads of a block; result valid in thread 0.
@@ -159,8 +181,6 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
 // ||w0||^2 / 2).  Every kernel that needs the test re-derives it from the
 // same per-block partial sums in the same order, so all agree bitwise.
 // ---------------------------------------------------------------------------
-constexpr int DOT_ROWS = 2048;               // rows per block of the projection kernel
-constexpr int DOT_RPT = DOT_ROWS / BS;       // rows per thread
 
 __device__ __forceinline__ double sum_parts(const double* __restrict__ p, int r, int nb)
 {
@@ -176,49 +196,65 @@ __device__ __forceinline__ bool needs_second_pass(const double* __restrict__ n0,
     return sum_parts(n1, r, nu) < 0.5 * sum_parts(n0, r, ns);
 }
 
-// Projection coefficients conj(V_i) . W for a batch of DOT_BATCH basis
-// vectors (grid x), one right-hand side (grid y) and one chunk of DOT_ROWS rows
-// (grid z): every thread accumulates DOT_RPT rows, then one block reduction.
+// Projection coefficients conj(V_i) . W for a batch of BATCH basis vectors
+// (grid x), one right-hand side (grid y) and one chunk of rpt * BS rows
+// (grid z): every thread accumulates rpt rows, then one block reduction.
 // part[(r * ns + s) * jc + i]; norm_out (first pass, batch 0) gets the partial
 // of ||W||^2 of the chunk.  With n0 / n1 given this is the second pass and
 // runs only where the test asks for it.
+template <int BATCH>
 __global__ __launch_bounds__(BS) void k_cgs_dots(const double2* __restrict__ V, size_t ldv, int nr, int jc,
-                                                 const double2* __restrict__ W, size_t ldw, int n,
+                                                 const double2* __restrict__ W, size_t ldw, int n, int rpt,
                                                  double2* __restrict__ part, double* __restrict__ norm_out,
                                                  const double* __restrict__ n0, const double* __restrict__ n1, int nu,
                                                  const int* __restrict__ active)
 {
-    __shared__ double lds[4 * 2 * DOT_BATCH];
+    __shared__ double lds[4 * 2 * BATCH];
     const int r = blockIdx.y, sblk = blockIdx.z, ns = gridDim.z;
-    const int i0 = blockIdx.x * DOT_BATCH;
+    const int i0 = blockIdx.x * BATCH;
     if (!active[r]) return;
     if (n0 && !needs_second_pass(n0, ns, n1, nu, r)) return;
-    double acc[2 * DOT_BATCH];
+    double acc[2 * BATCH];
 #pragma unroll
-    for (int b = 0; b < 2 * DOT_BATCH; ++b) acc[b] = 0.0;
+    for (int b = 0; b < 2 * BATCH; ++b) acc[b] = 0.0;
     double nn[1] = {0.0};
     const double2* wr = W + (size_t)r * ldw;
+    const int nb = min(BATCH, jc - i0);
+    const double2* vb = V + ((size_t)i0 * nr + r) * ldv;
+    const size_t vstride = (size_t)nr * ldv;
+    const int q0 = sblk * rpt * BS + threadIdx.x;
+    const int q1 = min(n, (sblk + 1) * rpt * BS);
+    if (nb == BATCH) {
 #pragma unroll 2
-    for (int k = 0; k < DOT_RPT; ++k) {
-        const int q = sblk * DOT_ROWS + k * BS + threadIdx.x;
-        if (q >= n) break;
-        const double2 w = wr[q];
-        nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
+        for (int q = q0; q < q1; q += BS) {
+            const double2 w = wr[q];
+            nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
 #pragma unroll
-        for (int b = 0; b < DOT_BATCH; ++b) {
-            const int i = i0 + b;
-            if (i < jc) {
-                const double2 v = V[((size_t)i * nr + r) * ldv + q];
+            for (int b = 0; b < BATCH; ++b) {
+                const double2 v = vb[b * vstride + q];
                 acc[2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * b]));
                 acc[2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * b + 1]));
             }
         }
+    } else {
+        for (int q = q0; q < q1; q += BS) {
+            const double2 w = wr[q];
+            nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                if (b < nb) {
+                    const double2 v = vb[b * vstride + q];
+                    acc[2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * b]));
+                    acc[2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * b + 1]));
+                }
+            }
+        }
     }
-    block_sum<2 * DOT_BATCH>(acc, lds);
+    block_sum<2 * BATCH>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int b = 0; b < DOT_BATCH; ++b)
-            if (i0 + b < jc) part[((size_t)r * ns + sblk) * jc + i0 + b] = make_double2(acc[2 * b], acc[2 * b + 1]);
+        for (int b = 0; b < BATCH; ++b)
+            if (b < nb) part[((size_t)r * ns + sblk) * jc + i0 + b] = make_double2(acc[2 * b], acc[2 * b + 1]);
     }
     if (norm_out && blockIdx.x == 0) {
         block_sum<1>(nn, lds);
@@ -534,23 +570,56 @@ hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double*
     return hipGetLastError();
 }
 
-int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + DOT_ROWS - 1) / DOT_ROWS); }
+// Shape of the projection kernel: rows per block (a multiple of BS) and basis
+// vectors per block (4, 8 or 16); BEM_DOT_CFG="rows,batch" overrides it (tuning).
+struct DotCfg {
+    int rows, batch;
+};
+
+DotCfg dot_cfg()
+{
+    DotCfg c{512, 4};
+    if (const char* e = getenv("BEM_DOT_CFG")) {
+        int a = 0, b = 0;
+        if (sscanf(e, "%d,%d", &a, &b) == 2 && a >= BS && a <= 16384 && a % BS == 0 && (b == 4 || b == 8 || b == 16))
+            c = {a, b};
+    }
+    return c;
+}
+
+int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().rows - 1) / dot_cfg().rows); }
+
+void launch_dots(const DotCfg& c, dim3 grid, hipStream_t s, const double2* V, size_t ldv, int nr, int jc,
+                 const double2* W, size_t ldw, int n, double2* part, double* norm_out, const double* n0,
+                 const double* n1, int nu, const int* active)
+{
+    const int rpt = c.rows / BS;
+    if (c.batch == 4)
+        hipLaunchKernelGGL(k_cgs_dots<4>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
+                           n1, nu, active);
+    else if (c.batch == 16)
+        hipLaunchKernelGGL(k_cgs_dots<16>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
+                           n1, nu, active);
+    else
+        hipLaunchKernelGGL(k_cgs_dots<8>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
+                           n1, nu, active);
+}
 
 hipError_t launch_arnoldi(double2* V, size_t ldv, int nr, int j, int m, int n, double2* W, size_t ldw,
                           double2* p1, double2* p2, double* n0, double* n1, double* n2, double2* H, double2* cs,
                           double2* sn, double2* gvec, double* hnorm, double* resid, const double* thr, int maxit,
                           int* iters, int* kdim, int* active, hipStream_t s)
 {
-    const int ns = (n + DOT_ROWS - 1) / DOT_ROWS;  // row chunks of the projection kernel
-    const int nu = (n + BS - 1) / BS;              // blocks of the update kernel
+    const DotCfg dc = dot_cfg();
+    const int ns = (n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
+    const int nu = (n + BS - 1) / BS;            // blocks of the update kernel
     const int jc = j + 1;
-    dim3 gd((jc + DOT_BATCH - 1) / DOT_BATCH, nr, ns);
+    dim3 gd((jc + dc.batch - 1) / dc.batch, nr, ns);
     dim3 gu(nu, nr);
-    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, p1, n0, nullptr, nullptr, nu,
-                       active);
+    launch_dots(dc, gd, s, V, ldv, nr, jc, W, ldw, n, p1, n0, nullptr, nullptr, nu, active);
     hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p1, ns, W, ldw, n, n1, nullptr, nullptr,
                        active);
-    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, p2, nullptr, n0, n1, nu, active);
+    launch_dots(dc, gd, s, V, ldv, nr, jc, W, ldw, n, p2, nullptr, n0, n1, nu, active);
     hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p2, ns, W, ldw, n, n2, n0, n1, active);
     hipLaunchKernelGGL(k_arnoldi_step, dim3(nr), dim3(64), 0, s, nr, j, m, ns, nu, p1, p2, n0, n1, n2, H, cs, sn,
                        gvec, hnorm, resid, thr, maxit, iters, kdim, active);

@@ -20,9 +20,10 @@
 #include <vector>
 
 #include "../../include/bem_serve.h"
+#include "launch.h"
 
 namespace bemk {
-void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, hipEvent_t e0, hipEvent_t e1);
+void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, const hipEvent_t* ev);
 void set_last_error(const std::string& msg);
 }
 
@@ -30,7 +31,7 @@ namespace {
 
 constexpr int MAX_SLOTS = 16;
 constexpr int MAX_REQ_RHS = 256;
-constexpr size_t FLAG_INTS = 2 * MAX_REQ_RHS;
+constexpr size_t FLAG_INTS = (size_t)bemk::FLAG_RING * MAX_REQ_RHS;
 
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -104,7 +105,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     int* pinned = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[bemk::FLAG_RING] = {};
     std::thread th;
 };
 
@@ -175,7 +176,7 @@ struct bem_server {
         char* F = X + r->vec;
         const size_t n = (size_t)r->n;
         std::vector<bem_solve_info> info((size_t)r->nrhs);
-        bemk::lend_flag_buffers(r->p, sl.pinned, FLAG_INTS, sl.ev[0], sl.ev[1]);
+        bemk::lend_flag_buffers(r->p, sl.pinned, FLAG_INTS, sl.ev);
         bem_status st = bem_geometry(r->p, g, r->geom, sl.stream);
         if (!st) st = bem_assemble(r->p, (bem_prec)o.prec, A, n, sl.stream);
         if (!st) st = bem_rhs(r->p, r->nrhs, r->angles.data(), B, n, sl.stream);
