@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
+VALU_PEAK_FLOPS = 78.6e12  # FP64 vector; also FP32 vector without packed FP32 (disabled in this build)
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. err vs FP64; assembly FLOP/s, matvec GB/s"
 
 
@@ -45,21 +46,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_sha(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def sources_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def traffic_record(kernel_src, workload):
-    """HBM traffic of the product kernel from the committed rocprofv3 PMC
-    summary of this workload, if it was taken on the current kernel source;
-    else None."""
-    path = os.path.join(ROOT, "profiles", f"matvec_traffic_{workload.split('_')[0]}.json")
+def counter_record(kind, workload):
+    """Committed rocprofv3 PMC summary (profiles/<kind>_<workload tag>.json) if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload.split('_')[0]}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha") != source_sha(kernel_src):
+    if rec.get("source_sha") != sources_sha(rec.get("source_files", [])):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def traffic_record(workload):
+    """HBM bytes per launch of the product kernel (FETCH_SIZE + WRITE_SIZE, each
+    scaled by a plain copy of known size), or None."""
+    rec = counter_record("matvec_traffic", workload)
+    return rec.get("bytes_per_launch") if rec else None
 
 
 def cpu_baseline(workload, gpu_iters, rows_per_case=None):
@@ -143,6 +153,22 @@ def assembly_evals(spec):
         for d in (f.dom_left, f.dom_right):
             sizes[d] = sizes.get(d, 0) + n_el
     return float(spec.quad) * sum(e * (e - 1) for e in sizes.values())
+
+
+def assembly_record(wl, launches, avg_ms, evals):
+    """Assembly rate; FLOP/s from the committed VALU-counter summary when it
+    matches the current kernel sources (FLOPs per assembly averaged over the
+    cases, which the step assembles once each)."""
+    out = {"launches": launches, "avg_ms": avg_ms, "evals": evals,
+           "evals_per_s": evals / (avg_ms * 1e-3) if launches else None}
+    rec = counter_record("assembly_flops", wl.name)
+    if rec and launches and len(rec["cases"]) == len(wl.problems):
+        fl = sum(c["flops_fp64"] + c["flops_fp32"] for c in rec["cases"]) / len(rec["cases"])
+        out.update({"flops_per_assembly": fl, "TFLOP_per_s": fl / (avg_ms * 1e-3) / 1e12,
+                    "frac_of_valu_peak": fl / (avg_ms * 1e-3) / VALU_PEAK_FLOPS,
+                    "valu_peak_TFLOP_per_s": VALU_PEAK_FLOPS / 1e12,
+                    "flops_source": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP64/FP32 x 64 lanes, profiles/assembly_flops_*.json"})
+    return out
 
 
 def max_rel_err(F, Fr):
@@ -273,6 +299,32 @@ def serve_mode(args, P, torch):
     print(json.dumps(out), flush=True)
 
 
+def assemble_mode(args, wl, P, torch, prec):
+    """Only assemblies: every case of the workload --steps times (after
+    --warmup), timed with the library's HIP events (for hardware-counter runs
+    of the assembly kernels)."""
+    out = []
+    for spec in wl.problems:
+        g = P.Problem(spec)
+        g.geometry()
+        A = torch.empty((g.n, g.n), dtype=torch.complex64 if prec == P.F32 else torch.complex128, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            g.assemble(prec, out=A)
+        torch.cuda.synchronize()
+        g.profile(True)
+        g.profile_read(reset=True)
+        for _ in range(args.steps):
+            g.assemble(prec, out=A)
+        pr = g.profile_read(reset=True)
+        g.profile(False)
+        ev = assembly_evals(spec)
+        avg = pr["assemble_ms"] / max(1, pr["assemble_launches"])
+        out.append({"case": str(spec.k), "launches": pr["assemble_launches"], "avg_ms": avg, "evals": ev,
+                    "evals_per_s": ev / (avg * 1e-3)})
+        del A
+    print(json.dumps({"mode": "assemble", "workload": wl.name, "precision": wl.precision, "cases": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,9 +338,10 @@ def main():
     ap.add_argument("--serve-tol", type=float, default=1e-8, help="serve: GMRES / refinement tolerance")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
-                         "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs)")
+                         "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
+                         "assemble: only --steps assemblies of every case")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1 "
@@ -309,6 +362,8 @@ def main():
     prec = P.F32 if mixed else P.F64
     if args.mode == "matvec":
         return matvec_mode(args, wl, P, torch, prec)
+    if args.mode == "assemble":
+        return assemble_mode(args, wl, P, torch, prec)
     dirs = wl.far_dirs
     probs, mats = [], []
     nr = len(wl.angles)
@@ -381,18 +436,17 @@ def main():
     mv_tfs = mv_flops / (mv_avg_ms * 1e-3) / 1e12
     as_avg_ms = as_ms / max(1, as_launch)
     evals = sum(assembly_evals(s) for s in wl.problems) / len(wl.problems)
-    kernel_src = os.path.join(ROOT, "paper_2312_12787_amd", "csrc", "matvec.hip")
     lat_ms = np.array(lat) * 1e3
     if mixed:
         roofline = {"kernel": f"k_matvec_mfma (FP32 MFMA split-K block product, {nr} right-hand sides in one pass "
                               f"over A)", "bound": "mfma", "achieved": mv_tfs, "peak": FP32_MFMA_PEAK_TFS,
                     "unit": "TFLOP/s", "frac": mv_tfs / FP32_MFMA_PEAK_TFS,
-                    "traffic": traffic_record(kernel_src, wl.name)}
+                    "traffic": traffic_record(wl.name)}
     else:
         roofline = {"kernel": f"k_matvec_mfma (FP64 MFMA split-K block product, {nr} right-hand sides)"
                     if nr > 4 else f"k_matvec (FP64 VALU split-K product, {nr} right-hand side(s))",
                     "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(kernel_src, wl.name)}
+                    "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(wl.name)}
     out = {
         "metric": METRIC,
         "value": solves / T,
@@ -413,8 +467,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "unit": f"one case: geometry tables + assembly + {nr} solves + far field"},
         "gmres_iterations_per_rhs": [it / (args.steps * nr) for it in iters],
-        "assembly": {"launches": as_launch, "avg_ms": as_avg_ms, "evals": evals,
-                     "evals_per_s": evals / (as_avg_ms * 1e-3) if as_launch else None},
+        "assembly": assembly_record(wl, as_launch, as_avg_ms, evals),
         "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
                    "share_of_step_time": mv_ms / (T * 1e3)},
         "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},

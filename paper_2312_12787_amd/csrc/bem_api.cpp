@@ -625,10 +625,6 @@ bem_status upload_ints(const Solver& c, size_t off, const std::vector<int>& v)
     return BEM_OK;
 }
 
-// GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi by
-// classical Gram-Schmidt with one re-orthogonalisation; the true residual is
-// recomputed at the end of each cycle.  Columns with want[r] == 0 are left
-// untouched.  iters[r] counts Arnoldi products.
 // Steps the host runs ahead of the GPU's stopping flags: 1 for matrices of
 // 128 MB and more (a product outlasts the host's work for a step), up to
 // FLAG_RING - 1 for small ones.
@@ -639,6 +635,12 @@ int flag_lag(int n, int prec)
     if (bytes >= 32e6) return 2;
     return bemk::FLAG_RING - 1;
 }
+
+// GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi by
+// classical Gram-Schmidt with one re-orthogonalisation; the true residual is
+// recomputed at the end of each cycle with FP64 accumulation.  Columns with
+// want[r] == 0 are left untouched.  iters[r] counts Arnoldi products; tol[r] is the
+// relative tolerance of column r.
 
 bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, const std::vector<double>& tol,
                  int maxit,
@@ -724,6 +726,10 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
                                       c.at<double2>(c.W.y), c.s));
         HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx, c.s));
+        // FP64 accumulation also inside the refinement: with FP32 products the
+        // rounding of the restart residual (about 1e-7 kappa ||b||) can exceed
+        // the inner tolerance of an ill-conditioned problem, which then never
+        // stops
         if (bem_status st = residual(c, B, ldb, X, ldx, R, ldv)) return st;
         HIP_OK(hipMemcpyAsync(dev_iters.data(), c.at<int>(c.W.iters), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
         if (bem_status st = col_norms(c, R, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;

@@ -328,7 +328,8 @@ struct MfmaCfg {
 
 MfmaCfg mfma_cfg(int n, int ng, bool f64)
 {
-    MfmaCfg c = ng == 1 ? MfmaCfg{2, 8, 8, 1} : (f64 ? MfmaCfg{1, 4, 0, 1} : MfmaCfg{2, 4, 0, 1});
+    // defaults measured on gfx950 (n = 32768; 16, 32 and 64 right-hand sides)
+    MfmaCfg c = ng == 1 ? MfmaCfg{2, 8, 8, 1} : (f64 && ng == 2 ? MfmaCfg{1, 4, 8, 1} : MfmaCfg{2, 4, 0, 1});
     if (const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE")) {
         int a = 0, b = 0, d = 0, g = 1;
         const int got = sscanf(e, "%d,%d,%d,%d", &a, &b, &d, &g);
