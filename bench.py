@@ -228,7 +228,7 @@ def serve_mode(args, P, torch):
     solves = sum(len(r["angles"]) for r in reqs)
 
     def closed_loop(prec, tol):
-        with S.Server(arena, slots=args.slots, prec=prec, tol=tol, dirs=dirs) as srv:
+        with S.Server(arena, slots=args.slots, prec=prec, tol=tol, restart=args.serve_restart, dirs=dirs) as srv:
             for r in reqs[:8]:  # warm-up: code objects, host paths
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -251,7 +251,8 @@ def serve_mode(args, P, torch):
     lat = []
     if not args.no_open_loop:
         log("  open loop at the arrival times ...")
-        with S.Server(arena, slots=args.slots, prec=P.F32, tol=args.serve_tol, dirs=dirs) as srv:
+        with S.Server(arena, slots=args.slots, prec=P.F32, tol=args.serve_tol, restart=args.serve_restart,
+                      dirs=dirs) as srv:
             for r in reqs[:8]:
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -284,7 +285,7 @@ def serve_mode(args, P, torch):
         "config": {"workload": f"served stream: {len(reqs)} requests, Poisson 20/s, perturbed circles N 512-8192 "
                                f"log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
                    "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
-                   "tol": args.serve_tol, "restart": 100, "far_field_dirs": len(dirs)},
+                   "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs)},
         "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
                      "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
                      "arena_high_water_GiB": st32["arena_high_water"] / 2**30},
@@ -336,6 +337,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serve: requests in flight")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="serve: device arena in GiB")
     ap.add_argument("--serve-tol", type=float, default=1e-8, help="serve: GMRES / refinement tolerance")
+    ap.add_argument("--serve-restart", type=int, default=300,
+                    help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble"],

@@ -170,7 +170,7 @@ typedef struct {
 } bem_solve_opts;
 
 typedef struct {
-    int iters;          /* matrix-vector products spent on this right-hand side         */
+    int iters;          /* Krylov steps (one product each) summed over restart cycles    */
     int restarts;       /* restart cycles (FP64) or refinement steps (BEM_F32 matrix)     */
     int converged;      /* 1 if the true relative residual reached tol                   */
     double rel_residual;/* final true relative residual ||b - A x|| / ||b||              */
@@ -179,9 +179,11 @@ typedef struct {
 /* Solve A X = B for nrhs right-hand sides (complex128, n x nrhs, ldb >= n) by
  * GMRES(restart) started from X = 0 (Sec. 3.2: the Krylov space of A itself,
  * no preconditioner applied).  The right-hand sides share every matrix pass
- * (block products); their Krylov spaces are independent.  With an FP64
- * matrix the Arnoldi process is classical Gram-Schmidt with one
- * re-orthogonalisation; with an FP32 matrix (bem_assemble(BEM_F32)) the
+ * (block products); their Krylov spaces are independent.  The Arnoldi
+ * process orthogonalises each new vector once and re-orthogonalises it one
+ * step later in the same pass (two passes over the basis per step; each
+ * cycle spends one extra product on the step at which it stops).  With an
+ * FP32 matrix (bem_assemble(BEM_F32)) the
  * inner GMRES runs FP32 products and FP64 Arnoldi, and an outer FP64
  * iterative refinement recomputes r = b - A x with FP64 accumulation until
  * tol.  X_dev is complex128 (ldx >= n) and is overwritten.  info is a host

@@ -104,7 +104,8 @@ struct bem_problem {
     bemk::GlobalIn glob{};
     GeomLayout L{};
     // pinned host slots for the asynchronous read-back of the GMRES flags
-    int* pinned = nullptr;
+    int* pinned = nullptr;      // host address
+    int* pinned_dev = nullptr;  // the same memory as the kernels address it
     size_t pinned_ints = 0;
     hipEvent_t flag_ev[bemk::FLAG_RING] = {};
     bool lent = false;  // pinned / flag_ev belong to the caller (request server slot)
@@ -160,8 +161,8 @@ GeomLayout make_layout(const bem_problem* p)
 
 // Workspace of the solver and products (byte offsets into work_dev).
 struct WorkLayout {
-    size_t V, W, R, Ro, D, X32, W32, mv_part, dot_part, dot_part2, h1, h2, y, H, cs, sn, gvec, norm_part, n0, n1, n2,
-        hnorm, resid, rnorm, bnorm, thr, active, kdim, iters, dirs, total;
+    size_t V, W, R, Ro, D, mv_part, dot_part, dot_part2, upd_part, y, H, Hraw, cs, sn, gvec, sc, tc, scal,
+        norm_part, hnorm, rnorm, bnorm, thr, active, kdim, iters, total;
     int ldv, nblk, anblk;
 };
 
@@ -182,32 +183,28 @@ WorkLayout make_work(int n, int nr, int m)
     W.R = take(vec);
     W.Ro = take(vec);
     W.D = take(vec);
-    W.X32 = take((size_t)W.ldv * nr * sizeof(float2));
-    W.W32 = take((size_t)W.ldv * nr * sizeof(float2));
     W.mv_part = take(bemk::matvec_part_elems(n, nr) * sizeof(double2));
     W.anblk = bemk::arnoldi_blocks(n);
     W.dot_part = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
     W.dot_part2 = take((size_t)nr * W.anblk * (m + 1) * sizeof(double2));
-    W.n0 = take((size_t)nr * W.anblk * sizeof(double));
-    W.n1 = take((size_t)nr * W.anblk * sizeof(double));
-    W.n2 = take((size_t)nr * W.anblk * sizeof(double));
+    W.upd_part = take((size_t)nr * W.anblk * sizeof(double));
     W.thr = take((size_t)nr * sizeof(double));
     W.iters = take((size_t)nr * sizeof(int));
-    W.h1 = take((size_t)nr * 1024 * sizeof(double2));
-    W.h2 = take((size_t)nr * 1024 * sizeof(double2));
     W.y = take((size_t)nr * 1024 * sizeof(double2));
     W.H = take((size_t)nr * (m + 1) * m * sizeof(double2));
+    W.Hraw = take((size_t)nr * (m + 1) * m * sizeof(double2));
     W.cs = take((size_t)nr * m * sizeof(double2));
     W.sn = take((size_t)nr * m * sizeof(double2));
     W.gvec = take((size_t)nr * (m + 1) * sizeof(double2));
+    W.sc = take((size_t)nr * (m + 1) * sizeof(double2));
+    W.tc = take((size_t)nr * (m + 1) * sizeof(double2));
+    W.scal = take((size_t)nr * 2 * sizeof(double2));
     W.norm_part = take((size_t)nr * std::max(W.nblk, 64) * sizeof(double));
     W.hnorm = take((size_t)nr * sizeof(double));
-    W.resid = take((size_t)nr * sizeof(double));
     W.rnorm = take((size_t)nr * sizeof(double));
     W.bnorm = take((size_t)nr * sizeof(double));
     W.active = take((size_t)nr * sizeof(int));
     W.kdim = take((size_t)nr * sizeof(int));
-    W.dirs = take((size_t)bemk::MAX_DIRS * sizeof(double));
     W.total = off;
     return W;
 }
@@ -585,13 +582,8 @@ bem_status apply_A(const Solver& c, const double2* X, size_t ldx, double2* Y, si
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
                                        c.at<double2>(c.W.mv_part), c.s, p->hk()));
     } else {
-        float2* x32 = c.at<float2>(c.W.X32);
-        float2* y32 = c.at<float2>(c.W.W32);
-        HIP_OK(bemk::launch_cast_f64_to_f32(X, ldx, c.n, c.nr, x32, c.W.ldv, c.s));
-        HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, c.n, x32, c.W.ldv, c.nr, y32,
-                                       c.W.ldv, reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s,
-                                       p->hk()));
-        HIP_OK(bemk::launch_cast_f32_to_f64(y32, c.W.ldv, c.n, c.nr, Y, ldy, c.s));
+        HIP_OK(bemk::launch_matvec_f32x64(static_cast<const float2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
+                                          reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk()));
     }
     return BEM_OK;
 }
@@ -636,11 +628,12 @@ int flag_lag(int n, int prec)
     return bemk::FLAG_RING - 1;
 }
 
-// GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi by
-// classical Gram-Schmidt with one re-orthogonalisation; the true residual is
-// recomputed at the end of each cycle with FP64 accumulation.  Columns with
-// want[r] == 0 are left untouched.  iters[r] counts Arnoldi products; tol[r] is the
-// relative tolerance of column r.
+// GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi
+// with delayed re-orthogonalisation (launch_arnoldi: steps 0..m, the last one
+// only completes column m - 1); the true residual is recomputed at the end of
+// each cycle with FP64 accumulation.  Columns with want[r] == 0 are left
+// untouched.  iters[r] counts completed Krylov steps; tol[r] is the relative
+// tolerance of column r.
 
 bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, const std::vector<double>& tol,
                  int maxit,
@@ -678,8 +671,9 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     for (int r = 0; r < nr; ++r) thr[r] = tol[(size_t)r] * bnorm[r];
     HIP_OK(hipMemcpyAsync(c.at<double>(c.W.thr), thr.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
     HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), iters.data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
-    // The GPU decides per right-hand side when to stop (k_arnoldi_step); the
-    // host reads the flags `lag` steps behind, so the queue never drains.  A
+    // The GPU decides per right-hand side when to stop (k_dc_step, which also
+    // writes the decision into a ring of pinned host slots); the host reads
+    // the flags `lag` steps behind, so the queue never drains.  A
     // small matrix gets a longer lag (its steps are shorter than the host's
     // launch work); steps enqueued after every column stopped do nothing but
     // an unused product.
@@ -689,31 +683,54 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than (lag + 1) * nrhs");
         if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
         c.p->pinned = nullptr;
+        c.p->pinned_dev = nullptr;
         HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), (size_t)ring * nr * sizeof(int),
-                             hipHostMallocDefault));
+                             hipHostMallocMapped | hipHostMallocCoherent));
         c.p->pinned_ints = (size_t)ring * nr;
     }
+    if (!c.p->pinned_dev)
+        HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.p->pinned_dev), c.p->pinned, 0));
     for (int k = 0; k < ring; ++k)
         if (!c.p->flag_ev[k]) {
             if (c.p->lent) return fail(BEM_E_ARG, "lent flag events fewer than lag + 1");
             HIP_OK(hipEventCreateWithFlags(&c.p->flag_ev[k], hipEventDisableTiming));
         }
+    bemk::ArnoldiArgs arn{};
+    arn.V = c.V(0);
+    arn.ldv = ldv;
+    arn.nr = nr;
+    arn.m = m;
+    arn.n = n;
+    arn.W = Wv;
+    arn.ldw = ldv;
+    arn.partP = c.at<double2>(c.W.dot_part);
+    arn.partQ = c.at<double2>(c.W.dot_part2);
+    arn.Hraw = c.at<double2>(c.W.Hraw);
+    arn.H = c.at<double2>(c.W.H);
+    arn.cs = c.at<double2>(c.W.cs);
+    arn.sn = c.at<double2>(c.W.sn);
+    arn.gvec = c.at<double2>(c.W.gvec);
+    arn.sc = c.at<double2>(c.W.sc);
+    arn.tc = c.at<double2>(c.W.tc);
+    arn.scal = c.at<double2>(c.W.scal);
+    arn.hnorm = c.at<double>(c.W.hnorm);
+    arn.norm_part = c.at<double>(c.W.upd_part);
+    arn.thr = c.at<double>(c.W.thr);
+    arn.maxit = maxit;
+    arn.iters = c.at<int>(c.W.iters);
+    arn.kdim = c.at<int>(c.W.kdim);
+    arn.active = c.at<int>(c.W.active);
     std::vector<int> dev_iters(nr);
     while (std::count(alive.begin(), alive.end(), 1) > 0) {
         if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
         HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
         HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
                                         c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
-        for (int j = 0; j < m; ++j) {
-            if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
-            HIP_OK(bemk::launch_arnoldi(c.V(0), ldv, nr, j, m, n, Wv, ldv, c.at<double2>(c.W.dot_part),
-                                        c.at<double2>(c.W.dot_part2), c.at<double>(c.W.n0), c.at<double>(c.W.n1),
-                                        c.at<double>(c.W.n2), c.at<double2>(c.W.H), c.at<double2>(c.W.cs),
-                                        c.at<double2>(c.W.sn), c.at<double2>(c.W.gvec), c.at<double>(c.W.hnorm),
-                                        c.at<double>(c.W.resid), c.at<double>(c.W.thr), maxit, c.at<int>(c.W.iters),
-                                        c.at<int>(c.W.kdim), c.at<int>(c.W.active), c.s));
-            int* slot = c.p->pinned + (size_t)(j % ring) * nr;
-            HIP_OK(hipMemcpyAsync(slot, c.at<int>(c.W.active), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
+        for (int j = 0; j <= m; ++j) {
+            if (j < m)
+                if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
+            arn.flags_out = c.p->pinned_dev + (size_t)(j % ring) * nr;
+            HIP_OK(bemk::launch_arnoldi(arn, j, c.s));
             HIP_OK(hipEventRecord(c.p->flag_ev[j % ring], c.s));
             if (j >= lag) {
                 HIP_OK(hipEventSynchronize(c.p->flag_ev[(j - lag) % ring]));
@@ -877,6 +894,7 @@ namespace bemk {
 void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, const hipEvent_t* ev)
 {
     p->pinned = pinned;
+    p->pinned_dev = nullptr;
     p->pinned_ints = ints;
     for (int k = 0; k < FLAG_RING; ++k) p->flag_ev[k] = ev[k];
     p->lent = true;

@@ -44,6 +44,11 @@ size_t matvec_part_elems(int n, int nrhs);
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s,
                              const KernelHook* hook = nullptr);
+// FP32 matrix and products with FP64 vectors: X is rounded to FP32 when packed,
+// Y widened when the split partial sums are added.
+hipError_t launch_matvec_f32x64(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
+                                double2* Y, size_t ldy, float2* partial, hipStream_t s,
+                                const KernelHook* hook = nullptr);
 hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
                              size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr);
 // R = B - A X (FP64)
@@ -58,13 +63,28 @@ hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double
 // GMRES building blocks (basis V[(i * nr + r) * ldv + q], FP64).
 hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double* partial, double* out,
                             hipStream_t s);
-// One Arnoldi step for all running right-hand sides after W = A V_j: CGS with
-// a conditional second pass, Givens update, stopping decision, V_{j+1}.
+// Row chunks of the projection kernel and blocks of the update kernel: the
+// partial-sum buffers hold arnoldi_blocks(n) entries per right-hand side.
 int arnoldi_blocks(int n);
-hipError_t launch_arnoldi(double2* V, size_t ldv, int nr, int j, int m, int n, double2* W, size_t ldw,
-                          double2* p1, double2* p2, double* n0, double* n1, double* n2, double2* H, double2* cs,
-                          double2* sn, double2* gvec, double* hnorm, double* resid, const double* thr, int maxit,
-                          int* iters, int* kdim, int* active, hipStream_t s);
+// One Arnoldi step j (0..m) of the batched GMRES cycle (linalg.hip): delayed
+// re-orthogonalisation, two passes over the basis; W = A V_j for j < m.
+struct ArnoldiArgs {
+    double2* V;
+    size_t ldv;
+    int nr, m, n;
+    double2* W;
+    size_t ldw;
+    double2 *partP, *partQ;        // projection partials [nr][ns][m + 1]
+    double2 *Hraw, *H;             // Hessenberg as produced / rotated, [nr][m][m + 1]
+    double2 *cs, *sn, *gvec;       // Givens rotations, rotated right-hand side
+    double2 *sc, *tc, *scal;       // step coefficients [nr][m + 1], [nr][2]
+    double *hnorm, *norm_part;     // |w| of the last step, its partials [nr][nu]
+    const double* thr;             // absolute stopping thresholds
+    int maxit;
+    int *iters, *kdim, *active;    // counters and flags (device)
+    int* flags_out;                // copy of the stopping flags in pinned host memory (device address)
+};
+hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
                               double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
@@ -73,8 +93,6 @@ hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const dou
                           double2* X, size_t ldx, hipStream_t s);
 hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, size_t ldax, int n, int nr,
                             double2* R, size_t ldr, hipStream_t s);
-hipError_t launch_cast_f64_to_f32(const double2* X, size_t ldx, int n, int nr, float2* Y, size_t ldy, hipStream_t s);
-hipError_t launch_cast_f32_to_f64(const float2* X, size_t ldx, int n, int nr, double2* Y, size_t ldy, hipStream_t s);
 hipError_t launch_add_f64(const double2* D, size_t ldd, int n, int nr, double2* X, size_t ldx, const int* active,
                           hipStream_t s);
 

@@ -176,126 +176,285 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
 
 
 // ---------------------------------------------------------------------------
-// Arnoldi step with device-side control (classical Gram-Schmidt, second pass
-// only where the Daniel-Gragg-Kaufman-Stewart test asks for it: ||w1||^2 <
-// ||w0||^2 / 2).  Every kernel that needs the test re-derives it from the
-// same per-block partial sums in the same order, so all agree bitwise.
+// Arnoldi step with delayed re-orthogonalisation and device-side control.
+// At step j the basis v_0..v_{j-1} is final, the candidate vt = V_j has had one
+// Gram-Schmidt pass and unit norm, and (j < m) wt = A vt.  One projection pass
+// gives s = V_{<j}^H vt, alpha = |vt|^2, t = V_{<j}^H wt, tau = vt^H wt; with
+// V_{<j} orthonormal the rest is exact algebra:
+//   gamma = sqrt(alpha - |s|^2),  v_j = (vt - V_{<j} s) / gamma,
+//   column j-1 of the Hessenberg matrix gains beta s, H[j, j-1] = beta gamma
+//   (beta = |w| of step j-1), which completes it: Givens rotation, residual
+//   estimate and stopping decision for Krylov dimension j;
+//   z = H[0:j+1, 0:j] s,  c = (tau - s^H t) / gamma,
+//   column j: H[i, j] = (t_i - z_i) / gamma (i < j),  H[j, j] = (c - z_j) / gamma,
+//   w = (wt - V_{<j} t - v_j c) / gamma,  beta = |w|,  V_{j+1} = w / beta.
+// Two passes over the basis per step (projection, update) instead of the four
+// of classical Gram-Schmidt with a second pass; the product of the step at
+// which a column stops is not used.  Reductions run in a fixed order.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double sum_parts(const double* __restrict__ p, int r, int nb)
+// Partial projections of the candidate (and of wt when HASW) on V_0..V_j for a
+// batch of BATCH basis vectors (grid x), one right-hand side (grid y) and one
+// chunk of rpt * BS rows (grid z): partP/partQ[(r * ns + chunk) * jc + i].
+template <int BATCH, bool HASW>
+__global__ __launch_bounds__(BS) void k_dc_dots(const double2* __restrict__ V, size_t ldv, int nr, int jc,
+                                                const double2* __restrict__ W, size_t ldw, int n, int rpt,
+                                                double2* __restrict__ partP, double2* __restrict__ partQ,
+                                                const int* __restrict__ active)
 {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += p[r * nb + b];
-    return s;
-}
-
-// n0: partials of ||w0||^2 (ns per right-hand side), n1: of ||w1||^2 (nu each)
-__device__ __forceinline__ bool needs_second_pass(const double* __restrict__ n0, int ns,
-                                                  const double* __restrict__ n1, int nu, int r)
-{
-    return sum_parts(n1, r, nu) < 0.5 * sum_parts(n0, r, ns);
-}
-
-// Projection coefficients conj(V_i) . W for a batch of BATCH basis vectors
-// (grid x), one right-hand side (grid y) and one chunk of rpt * BS rows
-// (grid z): every thread accumulates rpt rows, then one block reduction.
-// part[(r * ns + s) * jc + i]; norm_out (first pass, batch 0) gets the partial
-// of ||W||^2 of the chunk.  With n0 / n1 given this is the second pass and
-// runs only where the test asks for it.
-template <int BATCH>
-__global__ __launch_bounds__(BS) void k_cgs_dots(const double2* __restrict__ V, size_t ldv, int nr, int jc,
-                                                 const double2* __restrict__ W, size_t ldw, int n, int rpt,
-                                                 double2* __restrict__ part, double* __restrict__ norm_out,
-                                                 const double* __restrict__ n0, const double* __restrict__ n1, int nu,
-                                                 const int* __restrict__ active)
-{
-    __shared__ double lds[4 * 2 * BATCH];
-    const int r = blockIdx.y, sblk = blockIdx.z, ns = gridDim.z;
+    constexpr int NV = (HASW ? 4 : 2) * BATCH;
+    __shared__ double lds[4 * NV];
+    const int r = blockIdx.y, chunk = blockIdx.z, ns = gridDim.z;
     const int i0 = blockIdx.x * BATCH;
     if (!active[r]) return;
-    if (n0 && !needs_second_pass(n0, ns, n1, nu, r)) return;
-    double acc[2 * BATCH];
+    double acc[NV];
 #pragma unroll
-    for (int b = 0; b < 2 * BATCH; ++b) acc[b] = 0.0;
-    double nn[1] = {0.0};
-    const double2* wr = W + (size_t)r * ldw;
-    const int nb = min(BATCH, jc - i0);
-    const double2* vb = V + ((size_t)i0 * nr + r) * ldv;
+    for (int b = 0; b < NV; ++b) acc[b] = 0.0;
     const size_t vstride = (size_t)nr * ldv;
-    const int q0 = sblk * rpt * BS + threadIdx.x;
-    const int q1 = min(n, (sblk + 1) * rpt * BS);
-    if (nb == BATCH) {
-#pragma unroll 2
-        for (int q = q0; q < q1; q += BS) {
-            const double2 w = wr[q];
-            nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
+    const double2* vb = V + ((size_t)i0 * nr + r) * ldv;
+    const double2* vt = V + ((size_t)(jc - 1) * nr + r) * ldv;
+    const double2* wr = HASW ? W + (size_t)r * ldw : nullptr;
+    const int nb = min(BATCH, jc - i0);
+    const int q0 = chunk * rpt * BS + threadIdx.x;
+    const int q1 = min(n, (chunk + 1) * rpt * BS);
+    for (int q = q0; q < q1; q += BS) {
+        const double2 a = vt[q];
+        double2 w = make_double2(0.0, 0.0);
+        if (HASW) w = wr[q];
 #pragma unroll
-            for (int b = 0; b < BATCH; ++b) {
+        for (int b = 0; b < BATCH; ++b) {
+            if (b < nb) {
                 const double2 v = vb[b * vstride + q];
-                acc[2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * b]));
-                acc[2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * b + 1]));
-            }
-        }
-    } else {
-        for (int q = q0; q < q1; q += BS) {
-            const double2 w = wr[q];
-            nn[0] = fma(w.x, w.x, fma(w.y, w.y, nn[0]));
-#pragma unroll
-            for (int b = 0; b < BATCH; ++b) {
-                if (b < nb) {
-                    const double2 v = vb[b * vstride + q];
-                    acc[2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * b]));
-                    acc[2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * b + 1]));
+                acc[2 * b] = fma(v.x, a.x, fma(v.y, a.y, acc[2 * b]));
+                acc[2 * b + 1] = fma(v.x, a.y, fma(-v.y, a.x, acc[2 * b + 1]));
+                if (HASW) {
+                    acc[2 * BATCH + 2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * BATCH + 2 * b]));
+                    acc[2 * BATCH + 2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * BATCH + 2 * b + 1]));
                 }
             }
         }
     }
-    block_sum<2 * BATCH>(acc, lds);
+    block_sum<NV>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int b = 0; b < BATCH; ++b)
-            if (b < nb) part[((size_t)r * ns + sblk) * jc + i0 + b] = make_double2(acc[2 * b], acc[2 * b + 1]);
-    }
-    if (norm_out && blockIdx.x == 0) {
-        block_sum<1>(nn, lds);
-        if (threadIdx.x == 0) norm_out[r * ns + sblk] = nn[0];
+        for (int b = 0; b < BATCH; ++b) {
+            if (b < nb) {
+                const size_t o = ((size_t)r * ns + chunk) * jc + i0 + b;
+                partP[o] = make_double2(acc[2 * b], acc[2 * b + 1]);
+                if (HASW) partQ[o] = make_double2(acc[2 * BATCH + 2 * b], acc[2 * BATCH + 2 * b + 1]);
+            }
+        }
     }
 }
 
-// W -= sum_i h_i V_i with h_i summed from the ns dot partials inside the
-// block; norm_out gets the partials (one per block of BS rows) of the new ||W||^2.
-__global__ __launch_bounds__(BS) void k_cgs_update(const double2* __restrict__ V, size_t ldv, int nr, int jc,
-                                                   const double2* __restrict__ part, int ns, double2* __restrict__ W,
-                                                   size_t ldw, int n, double* __restrict__ norm_out,
-                                                   const double* __restrict__ n0, const double* __restrict__ n1,
-                                                   const int* __restrict__ active)
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b)
 {
-    __shared__ double2 h[1024];
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// The small work of step j for one right-hand side (one wave): sum the
+// projection partials into S = [s, alpha] and T = [t, tau] (kept for the update
+// kernel), complete column j-1 (Givens, residual, decision), form column j and
+// the update coefficients scal = {(gamma, 0), c}.  Hraw holds the Hessenberg
+// matrix as produced, H its rotated (triangular) form for the back-solve.
+__global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, const double2* __restrict__ partP,
+                                                const double2* __restrict__ partQ, double2* __restrict__ Hraw,
+                                                double2* __restrict__ H, double2* __restrict__ cs,
+                                                double2* __restrict__ sn, double2* __restrict__ gvec,
+                                                const double* __restrict__ hnorm, double2* __restrict__ sc,
+                                                double2* __restrict__ tc, double2* __restrict__ scal,
+                                                const double* __restrict__ thr, int maxit, int* __restrict__ iters,
+                                                int* __restrict__ kdim, int* __restrict__ active,
+                                                int* __restrict__ flags_out)
+{
+    __shared__ double2 col[1024 + 1];
+    __shared__ double2 lc[1024], ls[1024];
+    __shared__ int still_s;
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (!active[r]) {
+        if (flags_out && lane == 0) flags_out[r] = 0;
+        return;
+    }
+    const int jc = j + 1;
+    const bool hasw = partQ != nullptr;
+    double2* S = sc + (size_t)r * (m + 1);
+    double2* T = tc + (size_t)r * (m + 1);
+    for (int i = lane; i < jc; i += 64) {
+        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+        for (int b = 0; b < ns; ++b) {
+            const size_t o = ((size_t)r * ns + b) * jc + i;
+            const double2 p = partP[o];
+            pr += p.x;
+            pi += p.y;
+            if (hasw) {
+                const double2 t = partQ[o];
+                qr += t.x;
+                qi += t.y;
+            }
+        }
+        S[i] = make_double2(pr, pi);
+        if (hasw) T[i] = make_double2(qr, qi);
+    }
+    __syncthreads();
+    const double beta = j >= 1 ? hnorm[r] : 1.0;
+    const bool brk = !(beta > 0.0);  // previous step ended the Krylov space
+    double ss = 0.0, str = 0.0, sti = 0.0;
+    for (int i = lane; i < j; i += 64) {
+        const double2 a = brk ? make_double2(0.0, 0.0) : S[i];
+        ss = fma(a.x, a.x, fma(a.y, a.y, ss));
+        if (hasw) {
+            const double2 t = T[i];
+            str = fma(a.x, t.x, fma(a.y, t.y, str));
+            sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
+        }
+    }
+    ss = wave_sum(ss);
+    str = wave_sum(str);
+    sti = wave_sum(sti);
+    const double alpha = S[j].x;
+    const double gamma = brk ? 0.0 : sqrt(fmax(alpha - ss, 0.0));
+    int still = 1;
+    if (j >= 1) {
+        // complete column j - 1
+        double2* Hc = Hraw + (size_t)r * (m + 1) * m + (size_t)(j - 1) * (m + 1);
+        for (int i = lane; i < j; i += 64) {
+            double2 h = Hc[i];
+            if (!brk) {
+                const double2 a = S[i];
+                h.x = fma(beta, a.x, h.x);
+                h.y = fma(beta, a.y, h.y);
+            }
+            Hc[i] = h;
+            col[i] = h;
+        }
+        for (int i = lane; i < j - 1; i += 64) {
+            lc[i] = cs[(size_t)r * m + i];
+            ls[i] = sn[(size_t)r * m + i];
+        }
+        if (lane == 0) {
+            const double2 sub = make_double2(brk ? 0.0 : beta * gamma, 0.0);
+            Hc[j] = sub;
+            col[j] = sub;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            const int c0 = j - 1;
+            for (int i = 0; i < c0; ++i) {
+                const double2 hi = col[i], hn = col[i + 1];
+                const double2 ci = lc[i], si = ls[i];
+                col[i] = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
+                                      ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
+                col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
+                                          -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
+            }
+            const double2 a = col[c0], b = col[c0 + 1];
+            const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+            const double rho = hypot(na, nb);
+            double2 cj, sj;
+            if (rho == 0.0) {
+                cj = make_double2(1.0, 0.0);
+                sj = make_double2(0.0, 0.0);
+            } else if (na == 0.0) {
+                cj = make_double2(0.0, 0.0);
+                sj = make_double2(b.x / nb, -b.y / nb);
+            } else {
+                cj = make_double2(na / rho, 0.0);
+                const double ux = a.x / na, uy = a.y / na;
+                sj = make_double2((ux * b.x + uy * b.y) / rho, (uy * b.x - ux * b.y) / rho);
+            }
+            cs[(size_t)r * m + c0] = cj;
+            sn[(size_t)r * m + c0] = sj;
+            col[c0] = make_double2(cj.x * a.x + sj.x * b.x - sj.y * b.y, cj.x * a.y + sj.x * b.y + sj.y * b.x);
+            col[c0 + 1] = make_double2(0.0, 0.0);
+            double2* gv = gvec + (size_t)r * (m + 1);
+            const double2 gj = gv[c0];
+            const double2 gn = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
+            gv[c0 + 1] = gn;
+            gv[c0] = make_double2(cj.x * gj.x, cj.x * gj.y);
+            const double res = hypot(gn.x, gn.y);
+            const int it = iters[r] + 1;
+            iters[r] = it;
+            kdim[r] = j;
+            // stop on convergence, a spent budget, the end of the Krylov space or a non-finite value
+            still = (res > thr[r]) && it < maxit && (gamma > 0.0) && !brk;
+            if (!still) active[r] = 0;
+            still_s = still;
+        }
+        __syncthreads();
+        still = still_s;
+        double2* Rc = H + (size_t)r * (m + 1) * m + (size_t)(j - 1) * (m + 1);
+        for (int i = lane; i <= j; i += 64) Rc[i] = col[i];
+    } else if (!(gamma > 0.0)) {
+        still = 0;
+        if (lane == 0) active[r] = 0;
+    }
+    if (j == m) still = 0;  // end of the cycle
+    if (flags_out && lane == 0) flags_out[r] = still;
+    if (!still) return;
+    // column j and the update coefficients
+    const double2 tau = T[j];
+    const double ig = 1.0 / gamma;
+    const double2 c = make_double2((tau.x - str) * ig, (tau.y - sti) * ig);
+    const double2* Hr = Hraw + (size_t)r * (m + 1) * m;
+    double2* Hj = Hraw + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
+    for (int i = lane; i <= j; i += 64) {
+        // z_i = sum_l H[i, l] s_l over the Hessenberg band l >= i - 1
+        double zr = 0.0, zi = 0.0;
+        for (int l = max(i - 1, 0); l < j; ++l) {
+            const double2 h = Hr[(size_t)l * (m + 1) + i];
+            const double2 a = S[l];
+            zr += h.x * a.x - h.y * a.y;
+            zi += h.x * a.y + h.y * a.x;
+        }
+        const double2 base = i < j ? T[i] : c;
+        Hj[i] = make_double2((base.x - zr) * ig, (base.y - zi) * ig);
+    }
+    if (lane == 0) {
+        scal[(size_t)r * 2] = make_double2(gamma, 0.0);
+        scal[(size_t)r * 2 + 1] = c;
+    }
+}
+
+// One pass over V_0..V_{j-1}: v_j = (vt - V s) / gamma (in place of the
+// candidate) and w = (wt - V t - v_j c) / gamma; norm_out gets the partial of
+// |w|^2 of each block.
+__global__ __launch_bounds__(BS) void k_dc_update(double2* __restrict__ V, size_t ldv, int nr, int j, int m,
+                                                  const double2* __restrict__ sc, const double2* __restrict__ tc,
+                                                  const double2* __restrict__ scal, double2* __restrict__ W,
+                                                  size_t ldw, int n, double* __restrict__ norm_out,
+                                                  const int* __restrict__ active)
+{
+    __shared__ double2 sl[1024], tl[1024];
     __shared__ double lds[4];
     const int r = blockIdx.y;
     const int nu = gridDim.x;
     if (!active[r]) return;
-    if (n0 && !needs_second_pass(n0, ns, n1, nu, r)) return;
-    for (int i = threadIdx.x; i < jc; i += BS) {
-        double sr = 0.0, si = 0.0;
-        for (int b = 0; b < ns; ++b) {
-            const double2 v = part[((size_t)r * ns + b) * jc + i];
-            sr += v.x;
-            si += v.y;
-        }
-        h[i] = make_double2(sr, si);
+    for (int i = threadIdx.x; i < j; i += BS) {
+        sl[i] = sc[(size_t)r * (m + 1) + i];
+        tl[i] = tc[(size_t)r * (m + 1) + i];
     }
     __syncthreads();
+    const double ig = 1.0 / scal[(size_t)r * 2].x;
+    const double2 c = scal[(size_t)r * 2 + 1];
     double nn[1] = {0.0};
     const int q = blockIdx.x * BS + threadIdx.x;
     if (q < n) {
+        double2* vj = V + ((size_t)j * nr + r) * ldv;
+        double2 v = vj[q];
         double2 w = W[(size_t)r * ldw + q];
-        for (int i = 0; i < jc; ++i) {
-            const double2 c = h[i];
-            const double2 v = V[((size_t)i * nr + r) * ldv + q];
-            w.x -= c.x * v.x - c.y * v.y;
-            w.y -= c.x * v.y + c.y * v.x;
+        for (int i = 0; i < j; ++i) {
+            const double2 b = V[((size_t)i * nr + r) * ldv + q];
+            const double2 a = sl[i], t = tl[i];
+            v.x -= a.x * b.x - a.y * b.y;
+            v.y -= a.x * b.y + a.y * b.x;
+            w.x -= t.x * b.x - t.y * b.y;
+            w.y -= t.x * b.y + t.y * b.x;
         }
+        v = make_double2(v.x * ig, v.y * ig);
+        const double2 vc = cmul2(v, c);
+        w = make_double2((w.x - vc.x) * ig, (w.y - vc.y) * ig);
+        vj[q] = v;
         W[(size_t)r * ldw + q] = w;
         nn[0] = fma(w.x, w.x, w.y * w.y);
     }
@@ -303,109 +462,28 @@ __global__ __launch_bounds__(BS) void k_cgs_update(const double2* __restrict__ V
     if (threadIdx.x == 0) norm_out[r * nu + blockIdx.x] = nn[0];
 }
 
-// Column j of H from the two passes, ||w||, Givens update, residual estimate,
-// and the stopping decision of this right-hand side (residual estimate below
-// thr[r], or the product budget spent): one wave per right-hand side.
-__global__ __launch_bounds__(64) void k_arnoldi_step(int nr, int j, int m, int ns, int nu, const double2* __restrict__ p1,
-                                                     const double2* __restrict__ p2, const double* __restrict__ n0,
-                                                     const double* __restrict__ n1, const double* __restrict__ n2,
-                                                     double2* __restrict__ H, double2* __restrict__ cs,
-                                                     double2* __restrict__ sn, double2* __restrict__ gvec,
-                                                     double* __restrict__ hnorm, double* __restrict__ resid,
-                                                     const double* __restrict__ thr, int maxit,
-                                                     int* __restrict__ iters, int* __restrict__ kdim,
-                                                     int* __restrict__ active)
+// beta = |w| from the update partials (every block sums them in the same
+// order), V_{j+1} = w / beta (0 if beta = 0: the Krylov space ended).
+__global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, size_t ldw, int n,
+                                                const double* __restrict__ norm_part, int nu,
+                                                double2* __restrict__ V, size_t ldv, double* __restrict__ hnorm,
+                                                const int* __restrict__ active)
 {
-    __shared__ double2 col[1024 + 1];
-    __shared__ double2 lc[1024], ls[1024];
-    __shared__ int two;
-    const int r = blockIdx.x;
-    if (!active[r]) return;
-    const int lane = threadIdx.x;
-    const int jc = j + 1;
-    if (lane == 0) two = needs_second_pass(n0, ns, n1, nu, r) ? 1 : 0;
-    __syncthreads();
-    for (int i = lane; i < jc; i += 64) {
-        double sr = 0.0, si = 0.0;
-        for (int b = 0; b < ns; ++b) {
-            const double2 v = p1[((size_t)r * ns + b) * jc + i];
-            sr += v.x;
-            si += v.y;
-        }
-        if (two) {
-            double tr = 0.0, ti = 0.0;
-            for (int b = 0; b < ns; ++b) {
-                const double2 v = p2[((size_t)r * ns + b) * jc + i];
-                tr += v.x;
-                ti += v.y;
-            }
-            sr += tr;
-            si += ti;
-        }
-        col[i] = make_double2(sr, si);
-    }
-    for (int i = lane; i < j; i += 64) {
-        lc[i] = cs[(size_t)r * m + i];
-        ls[i] = sn[(size_t)r * m + i];
-    }
-    __syncthreads();
-    if (lane == 0) {
-        const double nv = sqrt(sum_parts(two ? n2 : n1, r, nu));
-        hnorm[r] = nv;
-        col[j + 1] = make_double2(nv, 0.0);
-        for (int i = 0; i < j; ++i) {
-            const double2 hi = col[i], hn = col[i + 1];
-            const double2 ci = lc[i], si = ls[i];
-            col[i] = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
-                                  ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
-            col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
-                                      -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
-        }
-        const double2 a = col[j], b = col[j + 1];
-        const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-        const double rho = hypot(na, nb);
-        double2 cj, sj;
-        if (rho == 0.0) {
-            cj = make_double2(1.0, 0.0);
-            sj = make_double2(0.0, 0.0);
-        } else if (na == 0.0) {
-            cj = make_double2(0.0, 0.0);
-            sj = make_double2(b.x / nb, -b.y / nb);
-        } else {
-            cj = make_double2(na / rho, 0.0);
-            const double ux = a.x / na, uy = a.y / na;
-            sj = make_double2((ux * b.x + uy * b.y) / rho, (uy * b.x - ux * b.y) / rho);
-        }
-        cs[(size_t)r * m + j] = cj;
-        sn[(size_t)r * m + j] = sj;
-        col[j] = make_double2(cj.x * a.x + sj.x * b.x - sj.y * b.y, cj.x * a.y + sj.x * b.y + sj.y * b.x);
-        col[j + 1] = make_double2(0.0, 0.0);
-        double2* gv = gvec + (size_t)r * (m + 1);
-        const double2 gj = gv[j];
-        const double2 gn = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
-        gv[j + 1] = gn;
-        gv[j] = make_double2(cj.x * gj.x, cj.x * gj.y);
-        const double res = hypot(gn.x, gn.y);
-        resid[r] = res;
-        const int it = iters[r] + 1;
-        iters[r] = it;
-        kdim[r] = jc;
-        // stop on convergence, a spent budget, a breakdown (||w|| = 0) or a non-finite value
-        if (!(res > thr[r]) || it >= maxit || !(nv > 0.0)) active[r] = 0;
-    }
-    __syncthreads();
-    double2* Hc = H + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
-    for (int i = lane; i <= j + 1; i += 64) Hc[i] = col[i];
-}
-
-// V_{j+1} = W / ||W|| for the right-hand sides still running
-__global__ void k_next_basis(const double2* __restrict__ W, size_t ldw, int n, const double* __restrict__ hnorm,
-                             double2* __restrict__ V, size_t ldv, const int* __restrict__ active)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double bsh;
     const int r = blockIdx.y;
-    if (q >= n || !active[r]) return;
-    const double inv = 1.0 / hnorm[r];
+    if (!active[r]) return;
+    if (threadIdx.x < 64) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nu; b += 64) v += norm_part[r * nu + b];
+        v = wave_sum(v);
+        if (threadIdx.x == 0) bsh = sqrt(v);
+    }
+    __syncthreads();
+    const double beta = bsh;
+    if (blockIdx.x == 0 && threadIdx.x == 0) hnorm[r] = beta;
+    const int q = blockIdx.x * BS + threadIdx.x;
+    if (q >= n) return;
+    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const double2 w = W[(size_t)r * ldw + q];
     V[(size_t)r * ldv + q] = make_double2(w.x * inv, w.y * inv);
 }
@@ -454,24 +532,6 @@ __global__ void k_axpby_res(const double2* __restrict__ B, size_t ldb, const dou
     if (q >= n) return;
     const double2 b = B[(size_t)r * ldb + q], a = AX[(size_t)r * ldax + q];
     R[(size_t)r * ldr + q] = make_double2(b.x - a.x, b.y - a.y);
-}
-
-__global__ void k_cast_64_32(const double2* __restrict__ X, size_t ldx, int n, float2* __restrict__ Y, size_t ldy)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (q >= n) return;
-    const double2 v = X[(size_t)r * ldx + q];
-    Y[(size_t)r * ldy + q] = make_float2((float)v.x, (float)v.y);
-}
-
-__global__ void k_cast_32_64(const float2* __restrict__ X, size_t ldx, int n, double2* __restrict__ Y, size_t ldy)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (q >= n) return;
-    const float2 v = X[(size_t)r * ldx + q];
-    Y[(size_t)r * ldy + q] = make_double2((double)v.x, (double)v.y);
 }
 
 __global__ void k_add_64(const double2* __restrict__ D, size_t ldd, int n, double2* __restrict__ X, size_t ldx,
@@ -589,42 +649,45 @@ DotCfg dot_cfg()
 
 int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().rows - 1) / dot_cfg().rows); }
 
-void launch_dots(const DotCfg& c, dim3 grid, hipStream_t s, const double2* V, size_t ldv, int nr, int jc,
-                 const double2* W, size_t ldw, int n, double2* part, double* norm_out, const double* n0,
-                 const double* n1, int nu, const int* active)
+template <bool HASW>
+void launch_dc_dots(const DotCfg& c, dim3 grid, hipStream_t s, const double2* V, size_t ldv, int nr, int jc,
+                    const double2* W, size_t ldw, int n, double2* partP, double2* partQ, const int* active)
 {
     const int rpt = c.rows / BS;
     if (c.batch == 4)
-        hipLaunchKernelGGL(k_cgs_dots<4>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
-                           n1, nu, active);
+        hipLaunchKernelGGL((k_dc_dots<4, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP, partQ,
+                           active);
     else if (c.batch == 16)
-        hipLaunchKernelGGL(k_cgs_dots<16>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
-                           n1, nu, active);
+        hipLaunchKernelGGL((k_dc_dots<16, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
+                           partQ, active);
     else
-        hipLaunchKernelGGL(k_cgs_dots<8>, grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, part, norm_out, n0,
-                           n1, nu, active);
+        hipLaunchKernelGGL((k_dc_dots<8, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP, partQ,
+                           active);
 }
 
-hipError_t launch_arnoldi(double2* V, size_t ldv, int nr, int j, int m, int n, double2* W, size_t ldw,
-                          double2* p1, double2* p2, double* n0, double* n1, double* n2, double2* H, double2* cs,
-                          double2* sn, double2* gvec, double* hnorm, double* resid, const double* thr, int maxit,
-                          int* iters, int* kdim, int* active, hipStream_t s)
+hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
 {
     const DotCfg dc = dot_cfg();
+    const int n = a.n, nr = a.nr, m = a.m;
     const int ns = (n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
     const int nu = (n + BS - 1) / BS;            // blocks of the update kernel
     const int jc = j + 1;
+    const bool last = j == m;
     dim3 gd((jc + dc.batch - 1) / dc.batch, nr, ns);
     dim3 gu(nu, nr);
-    launch_dots(dc, gd, s, V, ldv, nr, jc, W, ldw, n, p1, n0, nullptr, nullptr, nu, active);
-    hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p1, ns, W, ldw, n, n1, nullptr, nullptr,
-                       active);
-    launch_dots(dc, gd, s, V, ldv, nr, jc, W, ldw, n, p2, nullptr, n0, n1, nu, active);
-    hipLaunchKernelGGL(k_cgs_update, gu, dim3(BS), 0, s, V, ldv, nr, jc, p2, ns, W, ldw, n, n2, n0, n1, active);
-    hipLaunchKernelGGL(k_arnoldi_step, dim3(nr), dim3(64), 0, s, nr, j, m, ns, nu, p1, p2, n0, n1, n2, H, cs, sn,
-                       gvec, hnorm, resid, thr, maxit, iters, kdim, active);
-    hipLaunchKernelGGL(k_next_basis, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, W, ldw, n, hnorm,
-                       V + (size_t)jc * nr * ldv, ldv, active);
+    if (last)
+        launch_dc_dots<false>(dc, gd, s, a.V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
+    else
+        launch_dc_dots<true>(dc, gd, s, a.V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
+    hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(64), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
+                       a.H, a.cs, a.sn, a.gvec, a.hnorm, a.sc, a.tc, a.scal, a.thr, a.maxit, a.iters, a.kdim, a.active,
+                       a.flags_out);
+    if (!last) {
+        hipLaunchKernelGGL(k_dc_update, gu, dim3(BS), 0, s, a.V, a.ldv, nr, j, m, a.sc, a.tc, a.scal, a.W, a.ldw, n,
+                           a.norm_part, a.active);
+        hipLaunchKernelGGL(k_dc_next, gu, dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
+                           a.V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active);
+    }
     return hipGetLastError();
 }
 
@@ -655,18 +718,6 @@ hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, siz
                             double2* R, size_t ldr, hipStream_t s)
 {
     hipLaunchKernelGGL(k_axpby_res, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, B, ldb, AX, ldax, n, R, ldr);
-    return hipGetLastError();
-}
-
-hipError_t launch_cast_f64_to_f32(const double2* X, size_t ldx, int n, int nr, float2* Y, size_t ldy, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cast_64_32, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, X, ldx, n, Y, ldy);
-    return hipGetLastError();
-}
-
-hipError_t launch_cast_f32_to_f64(const float2* X, size_t ldx, int n, int nr, double2* Y, size_t ldy, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cast_32_64, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, X, ldx, n, Y, ldy);
     return hipGetLastError();
 }
 

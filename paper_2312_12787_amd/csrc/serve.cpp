@@ -276,7 +276,7 @@ bem_status bem_server_create(const bem_server_opts* opts, bem_server** out)
     for (Slot& sl : s->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), FLAG_INTS * sizeof(int),
-                                               hipHostMallocDefault);
+                                               hipHostMallocMapped | hipHostMallocCoherent);
         for (auto& ev : sl.ev)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     }
