@@ -216,8 +216,9 @@ def serve_mode(args, P, torch):
     """Served stream: requests with Poisson arrivals at 20/s, perturbed circles
     with N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32
     angles.  Capacity: every request submitted at once (closed loop), solves/s
-    = right-hand sides / wall time, for the mixed server and the FP64 server;
-    accuracy: far field of every request, mixed against FP64.  Latency: the
+    = right-hand sides / wall time, for the mixed server (BEM_MIXED) and the
+    FP64 server; accuracy: far field of every request, mixed against FP64, and
+    both against FP64 solved to 1e-12 on every 10th request.  Latency: the
     arrivals replayed in real time (open loop) on the mixed server, p50/p99 of
     completion minus arrival."""
     import workloads as W
@@ -234,24 +235,36 @@ def serve_mode(args, P, torch):
             srv.drain()
             t0 = time.perf_counter()
             ids = {srv.submit(r["spec"], r["angles"]): i for i, r in enumerate(reqs)}
-            out = srv.drain()
+            out = []
+            while len(out) < len(reqs):
+                out.extend(srv.poll(wait_ms=1000))
+                if len(out) // 250 != (len(out) - 1) // 250 or len(out) == len(reqs):
+                    log(f"    {len(out)} / {len(reqs)} done, {time.perf_counter() - t0:.1f} s")
             T = time.perf_counter() - t0
             st = srv.stats()
         res = {ids[o.id]: o for o in out}
         return T, res, st
 
+    def ff_err(a, b):
+        return float(np.max(np.linalg.norm(a.far_field - b.far_field, axis=1) / np.linalg.norm(b.far_field, axis=1)))
+
     log(f"serve: {len(reqs)} requests, {solves} solves, closed loop, mixed ...")
-    T32, r32, st32 = closed_loop(P.F32, args.serve_tol)
+    T32, r32, st32 = closed_loop(P.MIXED, args.serve_tol)
     log(f"  {T32:.1f} s; FP64 ...")
     T64, r64, _ = closed_loop(P.F64, args.serve_tol)
-    log(f"  {T64:.1f} s")
+    log(f"  {T64:.1f} s; FP64 reference to 1e-12 on every 10th request ...")
+    sample = list(range(0, len(reqs), 10))
+    with S.Server(arena, slots=args.slots, prec=P.F64, tol=1e-12, restart=args.serve_restart, dirs=dirs) as srv:
+        ids = {srv.submit(reqs[i]["spec"], reqs[i]["angles"]): i for i in sample}
+        ref = {ids[o.id]: o for o in srv.drain()}
     bad = [i for i in range(len(reqs)) if r32[i].status != 0 or r64[i].status != 0]
-    err = max(float(np.max(np.linalg.norm(r32[i].far_field - r64[i].far_field, axis=1) /
-                           np.linalg.norm(r64[i].far_field, axis=1))) for i in range(len(reqs)))
+    err = max(ff_err(r32[i], r64[i]) for i in range(len(reqs)))
+    err32 = [ff_err(r32[i], ref[i]) for i in sample]
+    err64 = [ff_err(r64[i], ref[i]) for i in sample]
     lat = []
     if not args.no_open_loop:
         log("  open loop at the arrival times ...")
-        with S.Server(arena, slots=args.slots, prec=P.F32, tol=args.serve_tol, restart=args.serve_restart,
+        with S.Server(arena, slots=args.slots, prec=P.MIXED, tol=args.serve_tol, restart=args.serve_restart,
                       dirs=dirs) as srv:
             for r in reqs[:8]:
                 srv.submit(r["spec"], r["angles"])
@@ -264,7 +277,10 @@ def serve_mode(args, P, torch):
                     time.sleep(dt)
                 late = (time.perf_counter() - t0) - r["arrival"]
                 lag[srv.submit(r["spec"], r["angles"])] = late
-                lat.extend(srv.poll(0))
+                got = srv.poll(0)
+                lat.extend(got)
+                if got and len(lat) // 250 != (len(lat) - len(got)) // 250:
+                    log(f"    {len(lat)} / {len(reqs)} done, {time.perf_counter() - t0:.1f} s")
             lat.extend(srv.drain())
         # latency = completion - arrival: the server's own submit-to-done time
         # plus how late the replay submitted the request
@@ -289,7 +305,14 @@ def serve_mode(args, P, torch):
         "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
                      "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
                      "arena_high_water_GiB": st32["arena_high_water"] / 2**30},
-        "accuracy": {"far_field_rel_err_mixed_vs_fp64_max": err, "failed_requests": bad},
+        "accuracy": {"far_field_rel_err_mixed_vs_fp64_max": err,
+                     "vs_fp64_1e-12_sample": {"requests": len(sample), "mixed_max": max(err32),
+                                              "mixed_p50": float(np.median(err32)), "fp64_path_max": max(err64),
+                                              "fp64_path_p50": float(np.median(err64))},
+                     "measure": "max over right-hand sides of the relative 2-norm far-field error at 360 directions",
+                     "failed_requests": bad},
+        "precision": {"mixed": "BEM_MIXED: FP64 matrix and its FP32 copy from one assembly; FP32 products, "
+                               "FP64 Arnoldi, refinement residuals with the FP64 matrix", "fp64": "BEM_F64"},
         "gmres_iterations_max_per_request": {"p50": float(np.median([r32[i].iters_max for i in r32])),
                                              "max": int(max(r32[i].iters_max for i in r32))},
         "roofline": None,

@@ -65,7 +65,20 @@ typedef enum {
     BEM_E_NONFINITE = 7  /* NaN or Inf met in a residual                           */
 } bem_status;
 
-typedef enum { BEM_F64 = 0, BEM_F32 = 1 } bem_prec;
+/* Matrix precision.
+ *   BEM_F64    complex128 matrix; FP64 products.
+ *   BEM_F32    complex64 matrix (FP32 assembly with FP64 distances, phases,
+ *              small-argument series and self terms); FP32 products, FP64
+ *              Arnoldi, refinement residuals with the FP32 matrix (FP64
+ *              accumulation): converges to the solution of the FP32 matrix.
+ *   BEM_MIXED  the complex128 matrix followed, at byte offset
+ *              256-aligned(16 n lda), by its complex64 rounding (same lda),
+ *              both written by one assembly pass; FP32 products on the copy,
+ *              refinement residuals with the FP64 matrix: converges to the
+ *              solution of the FP64 matrix (iterative refinement with the
+ *              residual in FP64), for problems whose condition number would
+ *              amplify FP32 matrix rounding beyond the target.            */
+typedef enum { BEM_F64 = 0, BEM_F32 = 1, BEM_MIXED = 2 } bem_prec;
 
 /* Formulation presets.
  *   BEM_CALDERON       eq. (calderon_bieb) with beta = -alpha for one inclusion,
@@ -142,7 +155,8 @@ bem_status bem_geometry_update(bem_problem *p, hipStream_t stream);
 /* Assemble the n x n system matrix (eqs. (stmp)-(ddtmp), (fundamental_sol),
  * the block systems of Secs. 3-6) into A_dev with leading dimension lda >= n,
  * in precision prec (BEM_F64: complex128; BEM_F32: complex64 entries, with
- * self terms computed in FP64 and rounded).  Requires bem_geometry.  The
+ * self terms computed in FP64 and rounded; BEM_MIXED: complex128 and its
+ * complex64 rounding, layout under bem_prec).  Requires bem_geometry.  The
  * problem records A_dev, lda and prec for bem_matvec / bem_solve.           */
 bem_status bem_assemble(bem_problem *p, int prec, void *A_dev, size_t lda, hipStream_t stream);
 
@@ -154,8 +168,9 @@ bem_status bem_rhs(const bem_problem *p, int nang, const double *angles, void *B
                    hipStream_t stream);
 
 /* Y = A X for nrhs columns (the dense products of GMRES, Sec. 3.2).  X and Y
- * have the precision of the assembled matrix (complex128 for BEM_F64,
- * complex64 for BEM_F32), leading dimensions ldx, ldy >= n.  work_dev holds
+ * have the precision of the assembled matrix (complex128 for BEM_F64 and
+ * BEM_MIXED, whose FP64 matrix is used; complex64 for BEM_F32), leading
+ * dimensions ldx, ldy >= n.  work_dev holds
  * split-K partial sums (bem_sizes with this nrhs).                          */
 bem_status bem_matvec(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev,
                       size_t ldy, void *work_dev, size_t work_bytes, hipStream_t stream);
@@ -164,14 +179,14 @@ typedef struct {
     int restart;        /* GMRES restart length m (>= 1)                                  */
     int max_iter;       /* cap on matrix-vector products per right-hand side            */
     double tol;         /* stop when ||b - A x|| <= tol ||b|| (true residual, FP64)      */
-    double inner_tol;   /* BEM_F32 matrix only: relative tolerance of each inner solve;
+    double inner_tol;   /* BEM_F32 / BEM_MIXED only: relative tolerance of each inner solve;
                            0 selects 1e-5                                               */
-    int max_refine;     /* BEM_F32 matrix only: cap on FP64 refinement steps; 0 -> 20    */
+    int max_refine;     /* BEM_F32 / BEM_MIXED only: cap on FP64 refinement steps; 0 -> 20 */
 } bem_solve_opts;
 
 typedef struct {
     int iters;          /* Krylov steps (one product each) summed over restart cycles    */
-    int restarts;       /* restart cycles (FP64) or refinement steps (BEM_F32 matrix)     */
+    int restarts;       /* restart cycles (FP64) or refinement steps (BEM_F32, BEM_MIXED) */
     int converged;      /* 1 if the true relative residual reached tol                   */
     double rel_residual;/* final true relative residual ||b - A x|| / ||b||              */
 } bem_solve_info;
@@ -182,11 +197,11 @@ typedef struct {
  * (block products); their Krylov spaces are independent.  The Arnoldi
  * process orthogonalises each new vector once and re-orthogonalises it one
  * step later in the same pass (two passes over the basis per step; each
- * cycle spends one extra product on the step at which it stops).  With an
- * FP32 matrix (bem_assemble(BEM_F32)) the
- * inner GMRES runs FP32 products and FP64 Arnoldi, and an outer FP64
- * iterative refinement recomputes r = b - A x with FP64 accumulation until
- * tol.  X_dev is complex128 (ldx >= n) and is overwritten.  info is a host
+ * cycle spends one extra product on the step at which it stops).  With a
+ * BEM_F32 or BEM_MIXED matrix the inner GMRES runs FP32 products and FP64
+ * Arnoldi, and an outer FP64 iterative refinement recomputes r = b - A x
+ * with FP64 accumulation (FP32 matrix for BEM_F32, FP64 matrix for
+ * BEM_MIXED) until tol.  X_dev is complex128 (ldx >= n) and is overwritten.  info is a host
  * array [nrhs].  Returns BEM_E_NOCONV if any column missed tol.            */
 bem_status bem_solve(bem_problem *p, int nrhs, const void *B_dev, size_t ldb, const bem_solve_opts *opts,
                      void *X_dev, size_t ldx, void *work_dev, size_t work_bytes, bem_solve_info *info,

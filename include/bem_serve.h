@@ -7,8 +7,9 @@
  * Each request runs the whole path of bem.h (geometry tables, assembly of the
  * Calderon-ordered Burton-Miller matrix, plane-wave right-hand sides of
  * Sec. 7, restarted GMRES, far field) in the precision the server was created
- * with: BEM_F64, or BEM_F32 for the FP32 matrix and products inside FP64
- * residual refinement (bem_solve).
+ * with (bem_prec): BEM_F64; BEM_F32 (FP32 matrix and products inside FP64
+ * residual refinement); BEM_MIXED (FP32 products, refinement residuals with
+ * the FP64 matrix).
  *
  * Scheduling:
  *   - the server owns `slots` worker threads, each with its own non-blocking
@@ -69,7 +70,7 @@ typedef struct {
 
 /* Validate the options, copy the directions, create the slot streams and
  * threads.  BEM_E_ARG: slots outside 1..16, a null or unaligned arena, ndir < 1,
- * prec not BEM_F64/BEM_F32, restart < 1.  BEM_E_DEVICE: stream or thread set-up
+ * prec not a bem_prec, restart < 1.  BEM_E_DEVICE: stream or thread set-up
  * failed.                                                                    */
 bem_status bem_server_create(const bem_server_opts *opts, bem_server **out);
 

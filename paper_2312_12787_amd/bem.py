@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BEM_LIB_PATH") or os.path.join(_HERE, "libbem_hip.so")
 
-F64, F32 = 0, 1
+F64, F32, MIXED = 0, 1, 2
 CALDERON, CALDERON_BETA1, CONVENTIONAL, CALDERON_ORIG = 0, 1, 2, 3
 STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4: "BEM_E_DEVICE",
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
@@ -218,9 +218,21 @@ class Problem:
         return self
 
     def assemble(self, prec: int = F64, out=None, lda: Optional[int] = None, stream=None):
+        """Assemble into `out` (allocated if None) and return the matrix tensor.
+        MIXED: `out` is a uint8 buffer of sizes(MIXED)[1] bytes holding the
+        FP64 matrix and its FP32 copy; the FP64 part is returned."""
         import torch
         if self.geom is None:
             self.geometry(stream)
+        if prec == MIXED:
+            _, mb, _ = self.sizes(MIXED)
+            if out is None:
+                out = torch.empty(mb, dtype=torch.uint8, device=self.device)
+            assert out.dtype == torch.uint8 and out.numel() >= mb and out.is_contiguous()
+            _check(lib().bem_assemble(self._h, prec, C.c_void_p(out.data_ptr()), self.n, _stream(stream)))
+            self.A = out
+            self.prec = prec
+            return out[:16 * self.n * self.n].view(torch.complex128).view(self.n, self.n)
         lda = lda or self.n
         dt = torch.complex128 if prec == F64 else torch.complex64
         if out is None:
@@ -239,8 +251,16 @@ class Problem:
                              C.c_void_p(B.data_ptr()), self.n, _stream(stream)))
         return B
 
+    def mixed_f32(self):
+        """The FP32 copy of a MIXED matrix, as a (n, n) complex64 view."""
+        import torch
+        assert self.prec == MIXED
+        off = (16 * self.n * self.n + 255) // 256 * 256
+        return self.A[off:off + 8 * self.n * self.n].view(torch.complex64).view(self.n, self.n)
+
     def matvec(self, X, stream=None):
-        """Y = A X for X of shape (nrhs, n) in the matrix precision."""
+        """Y = A X for X of shape (nrhs, n) in the matrix precision (complex128
+        for MIXED: its FP64 matrix)."""
         import torch
         X = X.contiguous()
         nrhs = X.shape[0]

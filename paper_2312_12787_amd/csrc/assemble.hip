@@ -291,7 +291,8 @@ template <int Q, bool CPLX, bool BM>
 __device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, const GaussRec* __restrict__ gq,
                                               const WaveConst& W, const DomConst& Dm, int sg, int i,
                                               const ElemRec& Ei, int j0, int cnt, int q_rt, cd selfS,
-                                              double2* __restrict__ A, size_t lda, size_t row, int N)
+                                              double2* __restrict__ A, size_t lda, float2* __restrict__ A32,
+                                              size_t lda32, size_t row, int N)
 {
     const int q = Q > 0 ? Q : q_rt;
     const cd k = {Dm.k[0], Dm.k[1]};
@@ -376,14 +377,22 @@ __device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, co
         }
         A[row + (size_t)j * lda] = make_double2(au.re, au.im);
         A[row + (size_t)(N + j) * lda] = make_double2(aw.re, aw.im);
+        if (A32) {
+            A32[row + (size_t)j * lda32] = make_float2((float)au.re, (float)au.im);
+            A32[row + (size_t)(N + j) * lda32] = make_float2((float)aw.re, (float)aw.im);
+        }
     }
 }
 
+// A: the FP64 matrix; A32 (optional): its entries rounded to FP32, written in
+// the same pass (the mixed path's inner products use it, its refinement
+// residuals the FP64 matrix).
 template <int Q, bool CPLX, bool BM>
 __global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f64(const char* __restrict__ g, GeomLayout L,
                                                                                 int N, int n_if, int q_rt,
                                                                                 const int* __restrict__ tiles, int side,
-                                                                                double2* __restrict__ A, size_t lda)
+                                                                                double2* __restrict__ A, size_t lda,
+                                                                                float2* __restrict__ A32, size_t lda32)
 {
     const Tile rt = tab<Tile>(g, L.rtiles)[tiles[blockIdx.x]];
     const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
@@ -399,6 +408,10 @@ __global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f64(c
             const int j = cc.start + jj;
             A[row + (size_t)j * lda] = make_double2(0.0, 0.0);
             A[row + (size_t)(N + j) * lda] = make_double2(0.0, 0.0);
+            if (A32) {
+                A32[row + (size_t)j * lda32] = make_float2(0.0f, 0.0f);
+                A32[row + (size_t)(N + j) * lda32] = make_float2(0.0f, 0.0f);
+            }
         }
         return;
     }
@@ -412,7 +425,8 @@ __global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f64(c
         const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
         selfS = {sv.x, sv.y};
     }
-    assemble_side<Q, CPLX, BM>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+    assemble_side<Q, CPLX, BM>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, A32, lda32, row,
+                               N);
 }
 
 
@@ -633,7 +647,8 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
 // over the row tiles of that variant; lists[v] / counts[v] are device / host.
 template <class T2, bool F64, int Q>
 void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                     const int* const* lists, const int* counts, T2* A, size_t lda, hipStream_t s)
+                     const int* const* lists, const int* counts, T2* A, size_t lda, float2* A32, size_t lda32,
+                     hipStream_t s)
 {
     for (int v = 0; v < ASM_VARIANTS; ++v) {
         if (counts[v] == 0) continue;
@@ -643,7 +658,7 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
     if (cplx == C_ && bm == B_) {                                                                               \
         if constexpr (F64)                                                                                      \
             hipLaunchKernelGGL((k_assemble_f64<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
-                               side, reinterpret_cast<double2*>(A), lda);                                        \
+                               side, reinterpret_cast<double2*>(A), lda, A32, lda32);                            \
         else                                                                                                    \
             hipLaunchKernelGGL((k_assemble_f32<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
                                side, reinterpret_cast<float2*>(A), lda);                                         \
@@ -657,14 +672,15 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
 }
 
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, double2* A, size_t lda, hipStream_t s)
+                               const int* const* lists, const int* counts, double2* A, size_t lda, float2* A32,
+                               size_t lda32, hipStream_t s)
 {
     if (q == 8)
-        launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
     else if (q == 10)
-        launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
     else
-        launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
     return hipGetLastError();
 }
 
@@ -672,11 +688,11 @@ hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_
                                const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s)
 {
     if (q == 8)
-        launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
     else if (q == 10)
-        launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
     else
-        launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, s);
+        launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
     return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ bem_status hip_fail(hipError_t e, const char* where)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// BEM_MIXED matrix buffer: the FP64 matrix, then its FP32 copy (same lda).
+size_t mixed_offset(size_t n, size_t lda) { return align256(lda * n * sizeof(double2)); }
+
 }  // namespace
 
 // HIP-event timing of the main kernels (bem_profile_enable / bem_profile_read).
@@ -111,7 +114,8 @@ struct bem_problem {
     bool lent = false;  // pinned / flag_ev belong to the caller (request server slot)
     // device state recorded by the calls
     char* geom = nullptr;
-    void* A = nullptr;
+    void* A = nullptr;      // FP64 or FP32 matrix (BEM_MIXED: the FP64 one)
+    void* A32 = nullptr;    // BEM_MIXED: the FP32 copy (leading dimension lda)
     size_t lda = 0;
     int prec = -1;
 };
@@ -442,12 +446,16 @@ bem_status bem_sizes(const bem_problem* p, int prec, int nrhs, int restart, size
                      size_t* matrix_bytes, size_t* work_bytes)
 {
     if (bem_status s = check_problem(p)) return s;
-    if (prec != BEM_F64 && prec != BEM_F32) return fail(BEM_E_ARG, "prec must be BEM_F64 or BEM_F32");
+    if (prec != BEM_F64 && prec != BEM_F32 && prec != BEM_MIXED)
+        return fail(BEM_E_ARG, "prec must be BEM_F64, BEM_F32 or BEM_MIXED");
     if (nrhs < 1) return fail(BEM_E_ARG, "nrhs must be >= 1");
     if (restart < 1 || restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
     const size_t n = 2 * (size_t)p->N;
     if (geom_bytes) *geom_bytes = p->L.total;
-    if (matrix_bytes) *matrix_bytes = n * n * (prec == BEM_F64 ? sizeof(double2) : sizeof(float2));
+    if (matrix_bytes)
+        *matrix_bytes = prec == BEM_F64 ? n * n * sizeof(double2)
+                        : prec == BEM_F32 ? n * n * sizeof(float2)
+                                          : mixed_offset(n, n) + n * n * sizeof(float2);
     if (work_bytes) *work_bytes = make_work((int)n, nrhs, restart).total;
     return BEM_OK;
 }
@@ -498,7 +506,8 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
 {
     if (bem_status s = check_problem(p)) return s;
     if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_assemble");
-    if (prec != BEM_F64 && prec != BEM_F32) return fail(BEM_E_ARG, "prec must be BEM_F64 or BEM_F32");
+    if (prec != BEM_F64 && prec != BEM_F32 && prec != BEM_MIXED)
+        return fail(BEM_E_ARG, "prec must be BEM_F64, BEM_F32 or BEM_MIXED");
     const size_t n = 2 * (size_t)p->N;
     if (!A_dev) return fail(BEM_E_ARG, "null matrix");
     if (lda < n) return fail(BEM_E_ARG, "lda < n");
@@ -508,14 +517,17 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
     for (int v = 0; v < bemk::ASM_VARIANTS; ++v)
         lists[v] = reinterpret_cast<const int*>(p->geom + p->L.vtiles) + p->voff[v];
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
-    if (prec == BEM_F64)
-        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
-                                         static_cast<double2*>(A_dev), lda, stream));
-    else
+    float2* A32 = prec == BEM_MIXED ? reinterpret_cast<float2*>(static_cast<char*>(A_dev) + mixed_offset(n, lda))
+                                    : nullptr;
+    if (prec == BEM_F32)
         HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
                                          static_cast<float2*>(A_dev), lda, stream));
+    else
+        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
+                                         static_cast<double2*>(A_dev), lda, A32, lda, stream));
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 1, stream);
     p->A = A_dev;
+    p->A32 = A32;
     p->lda = lda;
     p->prec = prec;
     return BEM_OK;
@@ -544,7 +556,7 @@ bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t 
     const size_t need = bemk::matvec_part_elems(n, nrhs) * sizeof(double2);
     if (work_bytes < need) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
     char* w = static_cast<char*>(work_dev);
-    if (p->prec == BEM_F64)
+    if (p->prec != BEM_F32)
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n,
                                        static_cast<const double2*>(X_dev), ldx, nrhs, static_cast<double2*>(Y_dev),
                                        ldy, reinterpret_cast<double2*>(w), stream, p->hk()));
@@ -582,18 +594,21 @@ bem_status apply_A(const Solver& c, const double2* X, size_t ldx, double2* Y, si
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
                                        c.at<double2>(c.W.mv_part), c.s, p->hk()));
     } else {
-        HIP_OK(bemk::launch_matvec_f32x64(static_cast<const float2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
+        // FP32 products: the FP32 matrix, or the FP32 copy of a BEM_MIXED one
+        const float2* A32 = static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A);
+        HIP_OK(bemk::launch_matvec_f32x64(A32, p->lda, c.n, X, ldx, c.nr, Y, ldy,
                                           reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk()));
     }
     return BEM_OK;
 }
 
-// R = B - A X with FP64 accumulation (an FP32 matrix is widened on load).
+// R = B - A X with FP64 accumulation: the FP64 matrix (BEM_F64, BEM_MIXED) or
+// the FP32 one widened on load (BEM_F32).
 bem_status residual(const Solver& c, const double2* B, size_t ldb, const double2* X, size_t ldx, double2* R,
                     size_t ldr)
 {
     const bem_problem* p = c.p;
-    if (p->prec == BEM_F64)
+    if (p->prec != BEM_F32)
         HIP_OK(bemk::launch_residual_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, B, ldb, R, ldr,
                                          c.at<double2>(c.W.mv_part), c.s, p->hk()));
     else
@@ -622,7 +637,7 @@ bem_status upload_ints(const Solver& c, size_t off, const std::vector<int>& v)
 // FLAG_RING - 1 for small ones.
 int flag_lag(int n, int prec)
 {
-    const double bytes = (double)n * n * (prec == BEM_F32 ? 8.0 : 16.0);
+    const double bytes = (double)n * n * (prec == BEM_F64 ? 16.0 : 8.0);
     if (bytes >= 128e6) return 1;
     if (bytes >= 32e6) return 2;
     return bemk::FLAG_RING - 1;

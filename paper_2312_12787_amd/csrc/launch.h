@@ -26,7 +26,8 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
 // (device) holds the row-tile ids of variant v, counts[v] (host) their number.
 constexpr int ASM_VARIANTS = 8;
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, double2* A, size_t lda, hipStream_t s);
+                               const int* const* lists, const int* counts, double2* A, size_t lda, float2* A32,
+                               size_t lda32, hipStream_t s);
 hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                                const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s);
 

@@ -261,7 +261,7 @@ bem_status bem_server_create(const bem_server_opts* opts, bem_server** out)
     if (!o.arena_dev || (reinterpret_cast<uintptr_t>(o.arena_dev) & 255) || o.arena_bytes < 256)
         return sfail(BEM_E_ARG, "arena null, unaligned or empty");
     if (o.ndir < 1 || o.ndir > 4096 || !o.dirs) return sfail(BEM_E_ARG, "ndir outside 1..4096 or no directions");
-    if (o.prec != BEM_F64 && o.prec != BEM_F32) return sfail(BEM_E_ARG, "unknown precision");
+    if (o.prec != BEM_F64 && o.prec != BEM_F32 && o.prec != BEM_MIXED) return sfail(BEM_E_ARG, "unknown precision");
     if (o.solve.restart < 1 || o.solve.max_iter < 1 || !(o.solve.tol > 0.0))
         return sfail(BEM_E_ARG, "bad solve options");
     auto* s = new bem_server();

@@ -127,3 +127,39 @@ def test_precision_path_full_size_kite16384(k1):
     scale = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
     print("  oracle-row residual / rms(b)", (np.abs(res) / scale).max(), flush=True)
     assert (np.abs(res) / scale).max() < 1e-9
+
+
+def test_mixed_matrix_is_the_fp64_matrix_and_its_rounding():
+    """BEM_MIXED writes the FP64 matrix (bit-identical to BEM_F64) and its
+    entries rounded to FP32 (bit-identical to rounding the FP64 matrix) in one
+    assembly pass."""
+    P = _gpu()
+    for spec in (W.kite(301, 6.0, 9.0 + 0.2j), W.concentric(70, 33, [2.0, 2.5, 3.5 + 0.2j])):
+        g = P.Problem(spec)
+        A64 = g.assemble(P.F64).clone()
+        Am = g.assemble(P.MIXED)
+        assert torch.equal(Am, A64)
+        assert torch.equal(g.mixed_f32(), A64.to(torch.complex64))
+
+
+def test_mixed_refinement_reaches_the_fp64_solution():
+    """Refinement with FP64-matrix residuals converges to the FP64 solution
+    (oracle LU) to the solve tolerance; with FP32-matrix residuals the FP32
+    rounding of the matrix stays in the answer."""
+    P = _gpu()
+    spec = W.kite(400, 20.0, 30.0)
+    ang = W.equispaced_angles(8)
+    po = O.Problem(spec)
+    Xo = np.linalg.solve(po.assemble(), po.rhs(ang))
+    errs = {}
+    for name in ("F32", "MIXED"):
+        g = P.Problem(spec)
+        g.assemble(getattr(P, name))
+        X, info = g.solve(g.rhs(ang), restart=100, tol=1e-11, inner_tol=1e-5)
+        assert info.converged.all()
+        Xg = X.cpu().numpy().T
+        errs[name] = max(rel_err(Xg[:, r], Xo[:, r]) for r in range(len(ang)))
+        print(name, "iters", info.iters.max(), "refinement steps", info.restarts.max(), "solution error", errs[name],
+              flush=True)
+    assert errs["MIXED"] < 1e-9
+    assert errs["F32"] > 1e-8 and errs["F32"] < 1e-6

@@ -40,7 +40,7 @@ def _rel(a, b):
 DIRS = W.equispaced_angles(72)
 
 
-@pytest.mark.parametrize("prec", ["F32", "F64"])
+@pytest.mark.parametrize("prec", ["MIXED", "F32", "F64"])
 def test_each_result_is_the_same_alone_and_in_the_mix(prec):
     P, S = _gpu()
     pr = getattr(P, prec)
@@ -74,7 +74,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(prec):
 def test_served_results_match_the_oracle():
     P, S = _gpu()
     reqs = _small_stream(4, seed=5)
-    with S.Server(1 << 30, slots=3, prec=P.F32, tol=1e-8, dirs=DIRS) as srv:
+    with S.Server(1 << 30, slots=3, prec=P.MIXED, tol=1e-8, dirs=DIRS) as srv:
         ids = {srv.submit(r["spec"], r["angles"]): i for i, r in enumerate(reqs)}
         out = srv.drain()
     for res in out:
