@@ -101,6 +101,13 @@ int or_gmres(int n, const double *A, const double *b, int m, double tol, int max
 int or_farfield(const or_problem *p, int nrhs, const double *X, int ndir, const double *dirs,
                 double *F);
 
+/* Near field (Sec. 7.1) at npts points xy (2 per point) lying in domains
+ * dom[npts], for solutions X (2N x nrhs col-major): U (npts x nrhs col-major,
+ * complex).  angles[nrhs] (or NULL: scattered field only) adds the incident
+ * plane wave at host-medium points.  Returns 1 for a domain out of range.  */
+int or_nearfield(const or_problem *p, int nrhs, const double *X, const double *angles, int npts,
+                 const double *xy, const int *dom, double *U);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,7 @@ def lib():
         L.or_gmres.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int, _dp,
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.or_farfield.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, _dp, _dp]
+        L.or_nearfield.argtypes = [C.c_void_p, C.c_int, _dp, C.c_void_p, C.c_int, _dp, _ip, _dp]
         _lib = L
     return _lib
 
@@ -158,6 +159,22 @@ class Problem:
         lib().or_farfield(self._h, X.shape[1], X.reshape(-1, order="F").view(np.float64), len(dirs), dirs,
                           F.reshape(-1, order="F").view(np.float64))
         return F
+
+    def nearfield(self, X: np.ndarray, points, dom, angles=None) -> np.ndarray:
+        """Field at points (npts, 2) of domains dom (npts,) for solutions X
+        (2N, nrhs): total field at host-medium points when angles are given,
+        else the scattered field; returns (npts, nrhs)."""
+        X = np.asfortranarray(np.asarray(X, dtype=np.complex128).reshape(self.n, -1))
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+        dm = np.ascontiguousarray(dom, dtype=np.int32)
+        ang = None if angles is None else np.ascontiguousarray(angles, dtype=np.float64)
+        U = np.zeros((len(pts), X.shape[1]), dtype=np.complex128, order="F")
+        st = lib().or_nearfield(self._h, X.shape[1], X.reshape(-1, order="F").view(np.float64),
+                                None if ang is None else ang.ctypes.data_as(C.c_void_p), len(pts), pts.reshape(-1), dm,
+                                U.reshape(-1, order="F").view(np.float64))
+        if st:
+            raise ValueError(lib().or_last_error().decode())
+        return U
 
 
 def matvec(A: np.ndarray, x: np.ndarray) -> np.ndarray:

@@ -7,7 +7,8 @@ tau = k1 / (eps k0) = k0 / k1 for eps = (k1/k0)^2:
     a_n = -c_n [J_n'(x0) J_n(x1) - tau J_n(x0) J_n'(x1)]
               / [H_n'(x0) J_n(x1) - tau H_n(x0) J_n'(x1)],
 and the far field of the scattered part with u_sc ~ e^{i k0 r}/sqrt(r) F:
-    F(theta) = sqrt(2/(pi k0)) e^{-i pi/4} sum_n a_n (-i)^n e^{i n theta}.
+    F(theta) = sqrt(2/(pi k0)) e^{-i pi/4} sum_n a_n (-i)^n e^{i n theta};
+inside, b_n = (c_n J_n(x0) + a_n H_n(x0)) / J_n(x1) (continuity of u).
 """
 import numpy as np
 import scipy.special as sp
@@ -31,6 +32,32 @@ def mie_farfield(k0, k1, R, theta_inc, dirs, nmax=30):
     dirs = np.asarray(dirs, dtype=np.float64)
     F = (a[None, :] * ((-1j) ** ns)[None, :] * np.exp(1j * np.outer(dirs, ns))).sum(axis=1)
     return np.sqrt(2.0 / (np.pi * k0)) * np.exp(-1j * np.pi / 4) * F
+
+
+def mie_nearfield(k0, k1, R, theta_inc, points, nmax=50):
+    """Total field of eq. (2dom_anal) at points (npts, 2): u_in + sum a_n H_n(k0 r) e^{in theta}
+    outside the circle of radius R, sum b_n J_n(k1 r) e^{in theta} inside."""
+    ns, a, b = mie_coefficients(k0, k1, R, theta_inc, nmax)
+    pts = np.asarray(points, dtype=np.float64)
+    r = np.hypot(pts[:, 0], pts[:, 1])
+    th = np.arctan2(pts[:, 1], pts[:, 0])
+    e = np.exp(1j * np.outer(th, ns))
+    out = np.exp(1j * k0 * (np.cos(theta_inc) * pts[:, 0] + np.sin(theta_inc) * pts[:, 1])) \
+        + (a[None, :] * sp.hankel1(ns[None, :], k0 * r[:, None]) * e).sum(axis=1)
+    inn = (b[None, :] * sp.jv(ns[None, :], k1 * r[:, None]) * e).sum(axis=1)
+    return np.where(r >= R, out, inn)
+
+
+def paper_grid(m=101, half=2.99):
+    """The m x m field points equally spaced in [-half, half]^2 (Sec. 7.1: 101 x 101 in [-2.99, 2.99]^2)."""
+    t = np.linspace(-half, half, m)
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def real_part_error(num, ana):
+    """Relative l2 error between the real parts (Sec. 7.1)."""
+    return float(np.sqrt(np.sum(np.real(num - ana) ** 2) / np.sum(np.real(ana) ** 2)))
 
 
 def rel_err(a, b):
