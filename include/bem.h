@@ -218,6 +218,24 @@ bem_status bem_farfield(const bem_problem *p, int nrhs, const void *X_dev, size_
                         const double *dirs, void *F_dev, size_t ldf, void *work_dev, size_t work_bytes,
                         hipStream_t stream);
 
+/* Field at points off the boundary (Sec. 7.1 evaluates the total field at
+ * field points): for a point x of domain d, Green's representation formula
+ * of that domain with the solution's boundary data,
+ *   u(x) = [d = 0] u_in(x) + sum_m sigma_dm sum_j (eps_d S_j(x) w_j - D_j(x) u_j),
+ * S_j, D_j the single- and double-layer integrals of G_d over element j and
+ * sigma_dm = +1 where interface m's normal leaves d.  Points at least two
+ * element lengths from an element use its Gauss rule; closer ones integrate
+ * the Laplace parts of the kernels exactly and the smooth remainder by Gauss.
+ * X_dev: nrhs solutions (complex128, ldx >= n).  angles: host [nrhs], the
+ * incident angles (adds u_in at host-medium points), or NULL for the
+ * scattered field only.  xy_dev: device [2 npts] coordinates; dom_dev: device
+ * [npts] domain of each point, chosen by the caller (points with an id outside
+ * [0, n_dom) are skipped and their U entries left untouched).  U_dev:
+ * complex128 npts x nrhs, point fastest, ldu >= npts.  Requires bem_geometry. */
+bem_status bem_nearfield(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, const double *angles,
+                         int npts, const double *xy_dev, const int *dom_dev, void *U_dev, size_t ldu,
+                         hipStream_t stream);
+
 /* Kernel timing for measurement.  While enabled, the library records HIP
  * events on the caller's stream immediately before and after the main kernel
  * of every assembly (the fused block-assembly kernel), every dense product

@@ -25,8 +25,8 @@ CALDERON, CALDERON_BETA1, CONVENTIONAL, CALDERON_ORIG = 0, 1, 2, 3
 STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4: "BEM_E_DEVICE",
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
 EXPORTS = ["bem_create", "bem_destroy", "bem_n_elements", "bem_order", "bem_sizes", "bem_geometry",
-           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield", "bem_profile_enable",
-           "bem_profile_read", "bem_last_error"]
+           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield", "bem_nearfield",
+           "bem_profile_enable", "bem_profile_read", "bem_last_error"]
 
 
 class BemError(RuntimeError):
@@ -85,11 +85,12 @@ def lib():
         L.bem_solve.argtypes = [vp, C.c_int, vp, sz, C.POINTER(bem_solve_opts), vp, sz, vp, sz,
                                 C.POINTER(bem_solve_info), vp]
         L.bem_farfield.argtypes = [vp, C.c_int, vp, sz, C.c_int, C.POINTER(C.c_double), vp, sz, vp, sz, vp]
+        L.bem_nearfield.argtypes = [vp, C.c_int, vp, sz, C.POINTER(C.c_double), C.c_int, vp, vp, vp, sz, vp]
         L.bem_profile_enable.argtypes = [vp, C.c_int]
         L.bem_profile_read.argtypes = [vp, C.POINTER(bem_profile), C.c_int]
         L.bem_last_error.restype = C.c_char_p
         for f in ["bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve",
-                  "bem_farfield", "bem_profile_enable", "bem_profile_read"]:
+                  "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -310,3 +311,25 @@ class Problem:
                                   d.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(F.data_ptr()), len(d),
                                   None, 0, _stream(stream)))
         return F
+
+    def nearfield(self, X, points, dom, angles: Optional[Sequence[float]] = None, stream=None):
+        """Field at points (npts, 2) in domains dom (npts,) for solutions X of
+        shape (nrhs, n): the total field at host-medium points when the
+        incident angles are given, else the scattered field.  Returns a
+        complex128 tensor of shape (nrhs, npts)."""
+        import torch
+        X = X.contiguous()
+        pts = torch.as_tensor(points, dtype=torch.float64, device=self.device).reshape(-1, 2).contiguous()
+        dm = torch.as_tensor(dom, dtype=torch.int32, device=self.device).reshape(-1).contiguous()
+        npts = pts.shape[0]
+        assert dm.numel() == npts
+        U = torch.zeros((X.shape[0], max(npts, 1)), dtype=torch.complex128, device=self.device)
+        ang = None
+        if angles is not None:
+            ang = np.ascontiguousarray(angles, dtype=np.float64)
+            assert len(ang) == X.shape[0]
+        _check(lib().bem_nearfield(self._h, X.shape[0], C.c_void_p(X.data_ptr()), X.shape[1],
+                                   ang.ctypes.data_as(C.POINTER(C.c_double)) if ang is not None else None, npts,
+                                   C.c_void_p(pts.data_ptr()), C.c_void_p(dm.data_ptr()), C.c_void_p(U.data_ptr()),
+                                   U.shape[1], _stream(stream)))
+        return U[:, :npts]

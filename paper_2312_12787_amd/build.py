@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbem_hip.so")
-SOURCES = ["assemble.hip", "linalg.hip", "matvec.hip", "bem_api.cpp", "serve.cpp"]
+SOURCES = ["assemble.hip", "linalg.hip", "matvec.hip", "nearfield.hip", "bem_api.cpp", "serve.cpp"]
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -899,6 +899,24 @@ bem_status bem_farfield(const bem_problem* p, int nrhs, const void* X_dev, size_
     return BEM_OK;
 }
 
+bem_status bem_nearfield(const bem_problem* p, int nrhs, const void* X_dev, size_t ldx, const double* angles,
+                         int npts, const double* xy_dev, const int* dom_dev, void* U_dev, size_t ldu,
+                         hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->geom) return fail(BEM_E_STATE, "bem_geometry must run before bem_nearfield");
+    if (nrhs < 1 || npts < 0 || !X_dev || (npts > 0 && (!xy_dev || !dom_dev || !U_dev)))
+        return fail(BEM_E_ARG, "bad near-field arguments");
+    if (ldx < 2 * (size_t)p->N || ldu < (size_t)npts) return fail(BEM_E_ARG, "leading dimension too small");
+    if (npts == 0) return BEM_OK;
+    std::vector<int> cplx((size_t)p->n_dom);
+    for (int d = 0; d < p->n_dom; ++d) cplx[(size_t)d] = p->k[(size_t)d].imag() != 0.0;
+    HIP_OK(bemk::launch_nearfield(p->geom, p->L, p->n_if, p->n_dom, p->N, p->quad, cplx.data(),
+                                  static_cast<const double2*>(X_dev), ldx, nrhs, angles, xy_dev, dom_dev, npts,
+                                  static_cast<double2*>(U_dev), ldu, stream));
+    return BEM_OK;
+}
+
 }  // extern "C"
 
 namespace bemk {

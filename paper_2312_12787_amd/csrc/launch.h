@@ -97,6 +97,15 @@ hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, siz
 hipError_t launch_add_f64(const double2* D, size_t ldd, int n, int nr, double2* X, size_t ldx, const int* active,
                           hipStream_t s);
 
+// Field at points (nearfield.hip): right-hand sides in groups of NF_RB, their
+// angles by value; dom_cplx[d] (host) = domain d has a complex wavenumber.
+constexpr int NF_RB = 8;
+struct NearAngles {
+    double v[NF_RB];
+};
+hipError_t launch_nearfield(const char* g, const GeomLayout& L, int n_if, int n_dom, int N, int q, const int* dom_cplx,
+                            const double2* X, size_t ldx, int nrhs, const double* angles, const double* xy,
+                            const int* dom, int npts, double2* U, size_t ldu, hipStream_t s);
 hipError_t launch_farfield(const char* g, const GeomLayout& L, int N, int n_if, int n_dom, const double2* X,
                            size_t ldx, int nrhs, const double* dirs, int ndir, double2* F, size_t ldf,
                            hipStream_t s);

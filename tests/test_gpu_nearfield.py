@@ -1,0 +1,124 @@
+"""Near field on the GPU (Sec. 7.1: the total field at field points).
+
+* The evaluation alone, GPU against the oracle for the same boundary data, at
+  grid points and at points 1e-6 .. 0.3 element lengths from the boundary on
+  both sides (disk; three-sector disk with junctions and a lossy sector).
+* The paper's accuracy measure on its 101 x 101 grid against the Mie series
+  (eq. (2dom_anal)) with the whole GPU path, falling like N^-1.
+* The incident wave is added exactly at host-medium points.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import mie_nearfield, paper_grid, real_part_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+K0, K1 = 5.0, 5.0 * np.sqrt(2.0)
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2312_12787_amd as P
+    return P
+
+
+def _close_points(po, rng, count, dom_of):
+    """Points at distances 1e-6 .. 0.3 h on both sides of random elements."""
+    el = po.elements()  # ax ay bx by cx cy tx ty h
+    pts, doms = [], []
+    for _ in range(count):
+        j = rng.integers(len(el))
+        ax, ay, _, _, _, _, tx, ty, h = el[j]
+        along = rng.uniform(-0.05, 1.05)
+        dist = 10.0 ** rng.uniform(-6, np.log10(0.3))
+        side = rng.choice([-1.0, 1.0])
+        x = ax + along * h * tx + side * dist * h * (-ty)
+        y = ay + along * h * ty + side * dist * h * tx
+        pts.append([x, y])
+        doms.append(dom_of(x, y))
+    return np.array(pts), np.array(doms, dtype=np.int32)
+
+
+def _disk_dom(x, y):
+    return 1 if np.hypot(x, y) < 1.0 else 0
+
+
+def _sector_dom(x, y):
+    if np.hypot(x, y) >= 1.0:
+        return 0
+    th = np.degrees(np.arctan2(y, x))
+    for s, a in enumerate((90.0, 210.0, 330.0)):
+        if (th - a) % 360.0 < 120.0:
+            return s + 1
+    return 1
+
+
+@pytest.mark.parametrize("case", ["disk", "sectors"])
+def test_nearfield_matches_oracle(case):
+    P = _gpu()
+    if case == "disk":
+        spec, dom_of = W.disk(64, K0, K1), _disk_dom
+    else:
+        spec, dom_of = W.sectors([10.0, 12.0, 18.0, 9.0 + 0.5j], h=1 / 12), _sector_dom
+    po = O.Problem(spec)
+    ang = [0.0, 1.3]
+    X = np.linalg.solve(po.assemble(), po.rhs(ang))
+    rng = np.random.default_rng(4)
+    # shifted off the radial interfaces and the central junction (on an
+    # interface the representation formula jumps and has no value)
+    grid = paper_grid(9) + np.array([0.0123, -0.0071])
+    gdom = np.array([dom_of(x, y) for x, y in grid], dtype=np.int32)
+    cpts, cdom = _close_points(po, rng, 120, dom_of)
+    pts = np.concatenate([grid, cpts])
+    dom = np.concatenate([gdom, cdom])
+    Uo = po.nearfield(X, pts, dom, angles=ang)
+    g = P.Problem(spec)
+    g.geometry()
+    U = g.nearfield(torch.as_tensor(X.T.copy(), device="cuda"), pts, dom, angles=ang).cpu().numpy().T
+    scale = np.abs(Uo).max()
+    ef = np.abs(U[:len(grid)] - Uo[:len(grid)]).max() / scale
+    ec = np.abs(U[len(grid):] - Uo[len(grid):]).max() / scale
+    print(case, "elements", spec.n_elements, "grid error", ef, "close-point error", ec, flush=True)
+    assert ef < 1e-11 and ec < 1e-9
+
+
+def test_paper_nearfield_error_falls_like_one_over_n():
+    """Sec. 7.1 (Fig. 3 measure): relative l2 error of the real part of the
+    total field on the 101 x 101 grid of [-2.99, 2.99]^2, unit disk as an
+    inscribed N-gon, omega = 5, eps2 = 2, the whole GPU path (assembly,
+    GMRES, near field) against the Mie series truncated at |n| <= 50."""
+    P = _gpu()
+    pts = paper_grid(101)
+    dom = (np.hypot(pts[:, 0], pts[:, 1]) < 1.0).astype(np.int32)
+    ua = mie_nearfield(K0, K1, 1.0, 0.0, pts, nmax=50)
+    errs = []
+    for n in (256, 512, 1024):
+        g = P.Problem(W.disk(n, K0, K1))
+        g.assemble(P.F64)
+        X, info = g.solve(g.rhs([0.0]), restart=100, tol=1e-10)
+        assert info.converged.all()
+        U = g.nearfield(X, pts, dom, angles=[0.0]).cpu().numpy()[0]
+        errs.append(real_part_error(U, ua))
+        print("N", n, "iterations", int(info.iters[0]), "near-field error", errs[-1], flush=True)
+    for a, b in zip(errs, errs[1:]):
+        assert 1.6 < a / b < 2.6
+    assert errs[-1] < 2e-3
+
+
+def test_incident_wave_is_added_at_host_points_only():
+    P = _gpu()
+    g = P.Problem(W.kite(200, 4.0, 6.0 + 0.1j))
+    g.assemble(P.F64)
+    ang = [0.4, 2.0, 3.3]
+    X, _ = g.solve(g.rhs(ang), restart=60, tol=1e-10)
+    pts = np.array([[2.5, 0.3], [-2.0, 1.9], [0.0, 0.0], [-0.5, 0.2]])
+    dom = np.array([0, 0, 1, 1], dtype=np.int32)
+    Ut = g.nearfield(X, pts, dom, angles=ang).cpu().numpy()
+    Us = g.nearfield(X, pts, dom).cpu().numpy()
+    uin = np.exp(1j * 4.0 * (np.cos(ang)[:, None] * pts[None, :, 0] + np.sin(ang)[:, None] * pts[None, :, 1]))
+    assert np.abs(Ut[:, :2] - Us[:, :2] - uin[:, :2]).max() < 1e-14
+    assert np.array_equal(Ut[:, 2:], Us[:, 2:])
