@@ -34,6 +34,41 @@ def mie_farfield(k0, k1, R, theta_inc, dirs, nmax=30):
     return np.sqrt(2.0 / (np.pi * k0)) * np.exp(-1j * np.pi / 4) * F
 
 
+def layered_mie_coefficients(k, radii, theta_inc, nmax=40):
+    """Concentric cylinders (Sec. 7.2): k = [k0, k_shell, k_core], radii =
+    [R_outer, R_inner]; eps_d = (k_d/k0)^2.  Per order n the four unknowns
+    [a_n, b_n, d_n, e_n] of
+        host  : c_n J_n(k0 r) + a_n H_n(k0 r),
+        shell : b_n J_n(k1 r) + d_n H_n(k1 r),
+        core  : e_n J_n(k2 r),
+    from continuity of u and of (1/eps) du/dr at both radii."""
+    k0, k1, k2 = (complex(v) for v in k)
+    R1, R2 = radii
+    e1, e2 = (k1 / k0) ** 2, (k2 / k0) ** 2
+    ns = np.arange(-nmax, nmax + 1)
+    out = np.zeros((len(ns), 4), dtype=np.complex128)
+    for i, n in enumerate(ns):
+        c = (1j ** n) * np.exp(-1j * n * theta_inc)
+        J, Jp, H, Hp = sp.jv, sp.jvp, sp.hankel1, sp.h1vp
+        M = np.array([
+            [H(n, k0 * R1), -J(n, k1 * R1), -H(n, k1 * R1), 0.0],
+            [k0 * Hp(n, k0 * R1), -(k1 / e1) * Jp(n, k1 * R1), -(k1 / e1) * Hp(n, k1 * R1), 0.0],
+            [0.0, J(n, k1 * R2), H(n, k1 * R2), -J(n, k2 * R2)],
+            [0.0, (k1 / e1) * Jp(n, k1 * R2), (k1 / e1) * Hp(n, k1 * R2), -(k2 / e2) * Jp(n, k2 * R2)]],
+            dtype=np.complex128)
+        rhs = np.array([-c * J(n, k0 * R1), -c * k0 * Jp(n, k0 * R1), 0.0, 0.0], dtype=np.complex128)
+        out[i] = np.linalg.solve(M, rhs)
+    return ns, out
+
+
+def layered_mie_farfield(k, radii, theta_inc, dirs, nmax=40):
+    ns, co = layered_mie_coefficients(k, radii, theta_inc, nmax)
+    k0 = float(np.real(k[0]))
+    dirs = np.asarray(dirs, dtype=np.float64)
+    F = (co[None, :, 0] * ((-1j) ** ns)[None, :] * np.exp(1j * np.outer(dirs, ns))).sum(axis=1)
+    return np.sqrt(2.0 / (np.pi * k0)) * np.exp(-1j * np.pi / 4) * F
+
+
 def mie_nearfield(k0, k1, R, theta_inc, points, nmax=50):
     """Total field of eq. (2dom_anal) at points (npts, 2): u_in + sum a_n H_n(k0 r) e^{in theta}
     outside the circle of radius R, sum b_n J_n(k1 r) e^{in theta} inside."""

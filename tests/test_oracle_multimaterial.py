@@ -75,3 +75,25 @@ def test_sectors_geometry_and_junctions():
     for f in W.sectors([1.0, 2.0, 3.0, 4.0], h=1 / 20).interfaces:
         d = np.hypot(*np.diff(f.xy, axis=0).T)
         assert np.max(np.maximum(d[1:] / d[:-1], d[:-1] / d[1:])) < 1.5 + 1e-6
+
+
+def test_concentric_disks_converge_to_the_layered_cylinder_series():
+    """Sec. 7.2 geometry (radii 2 and 1, eps = 1, 2, 3 at omega = 1.5): the far
+    field of every formulation converges to the concentric-cylinder series
+    (solved per order from the transmission conditions at both radii) like
+    N^-1, and the formulations agree with each other to O(h)."""
+    from closed_forms import layered_mie_farfield
+    w = 1.5
+    k = [w, w * np.sqrt(2.0), w * np.sqrt(3.0)]
+    dirs = W.equispaced_angles(36)
+    Fa = layered_mie_farfield(k, [2.0, 1.0], 0.0, dirs)
+    for form in (W.CALDERON, W.CALDERON_ORIG, W.CONVENTIONAL):
+        errs = []
+        for n in (40, 80, 160):
+            po = O.Problem(W.concentric(2 * n, n, k, form=form))
+            X = np.linalg.solve(po.assemble(), po.rhs([0.0]))
+            errs.append(rel_err(po.farfield(X, dirs)[:, 0], Fa))
+        print("form", form, "far-field error vs layered series", errs)
+        assert errs[-1] < 8e-3
+        for a, b in zip(errs, errs[1:]):
+            assert 1.6 < a / b < 2.6
