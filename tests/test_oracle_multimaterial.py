@@ -97,3 +97,21 @@ def test_concentric_disks_converge_to_the_layered_cylinder_series():
         assert errs[-1] < 8e-3
         for a, b in zip(errs, errs[1:]):
             assert 1.6 < a / b < 2.6
+
+
+def test_split_disk_geometry_and_equal_halves():
+    """Disk split by a vertical diameter (junction example of Sec. 7.2): with
+    both halves of the same material it is the one-disk problem again
+    (far field against the Mie series, O(h))."""
+    k0, k1 = 2.0, 3.0
+    spec = W.split_disk(200, [k0, k1, k1])
+    assert spec.n_elements == 200
+    el = O.Problem(spec).elements()
+    assert np.allclose(np.hypot(el[:150, 4], el[:150, 5]), 1.0, atol=1e-3)  # arc midpoints
+    assert np.allclose(el[150:, 4], 0.0)                                     # diameter midpoints
+    dirs = W.equispaced_angles(24)
+    po = O.Problem(spec)
+    X = np.linalg.solve(po.assemble(), po.rhs([0.3]))
+    err = rel_err(po.farfield(X, dirs)[:, 0], mie_farfield(k0, k1, 1.0, 0.3, dirs))
+    print("split disk with equal halves: far-field error vs Mie", err)
+    assert err < 1e-2

@@ -191,6 +191,27 @@ def sectors(k: Sequence[complex], h: float = 1.0 / 800, graded: bool = True, ang
     return ProblemSpec(k=[complex(v) for v in k], interfaces=ifs, quad=quad, form=form, name="sectors")
 
 
+def split_disk(n: int, k: Sequence[complex], quad: int = 8, form: int = CALDERON) -> ProblemSpec:
+    """Unit disk split by its vertical diameter (Sec. 7.2, junction example:
+    two triple points at (0, +-1)): left half = domain 1, right half =
+    domain 2.  3n/8 elements on each half circle (counter-clockwise, normal
+    into the disk) and n/4 on the diameter (upwards, normal into the left
+    half)."""
+    n_arc = max(1, int(round(3 * n / 8)))
+    n_line = max(1, n - 2 * n_arc)
+    def arc(a0, a1):
+        t = np.linspace(a0, a1, n_arc + 1)
+        return np.stack([np.cos(t), np.sin(t)], axis=1)
+    left = arc(0.5 * np.pi, 1.5 * np.pi)
+    right = arc(1.5 * np.pi, 2.5 * np.pi)
+    for xy in (left, right):  # exact junction coordinates
+        xy[0] = [0.0, np.sign(xy[0, 1])]
+        xy[-1] = [0.0, np.sign(xy[-1, 1])]
+    line = np.stack([np.zeros(n_line + 1), np.linspace(-1.0, 1.0, n_line + 1)], axis=1)
+    ifs = [Interface(left, False, 1, 0), Interface(right, False, 2, 0), Interface(line, False, 1, 2)]
+    return ProblemSpec(k=[complex(v) for v in k], interfaces=ifs, quad=quad, form=form, name=f"split_disk{n}")
+
+
 def equispaced_angles(n: int) -> np.ndarray:
     return 2.0 * np.pi * np.arange(n) / n
 
