@@ -20,7 +20,7 @@ materials: conventional (eq. (3dom_conv_bie)), original (eq.
 (3dom_calderon_bie0)) and modified (eq. (3dom_calderon_bie)).  GMRES from
 x0 = 0 to a relative residual of 1e-8, incident angle 0, without restart up to
 1000 Krylov vectors (the library's largest restart length; a longer run
-restarts), FP64.
+restarts), at most 5000 steps (more: reported as None), FP64.
 
 Usage: python sweeps.py [--exp NAME ...] [--quick]   (one JSON line per experiment)
 """
@@ -39,8 +39,9 @@ SINGLE_FORMS = {"conventional": 2, "calderon_beta1": 1, "calderon_beta_minus_alp
 MULTI_FORMS = {"conventional": 2, "calderon_orig": 3, "calderon_mod": 0}
 
 
-def iterations(spec, tol=1e-8, max_iter=20000):
-    """GMRES iterations of one FP64 solve on the GPU (incident angle 0)."""
+def iterations(spec, tol=1e-8, max_iter=5000):
+    """GMRES iterations of one FP64 solve on the GPU (incident angle 0); a
+    solve still above tol after max_iter steps is reported as None."""
     import paper_2312_12787_amd as P
     g = P.Problem(spec)
     g.assemble(P.F64)
@@ -58,6 +59,7 @@ def _sweep(name, values, make, forms, label):
             it, ok = iterations(make(v, form))
             row[fname] = it if ok else None
         rows.append(row)
+        print(f"{name}: {row}", file=sys.stderr, flush=True)
     return {"experiment": name, "parameter": label, "rows": rows, "seconds": time.perf_counter() - t0}
 
 

@@ -1,0 +1,72 @@
+"""The paper's iteration studies (Sec. 7) on short sweeps of the GPU path:
+the qualitative claims the paper draws from its figures.
+
+* Single material (omega = 5, eps2 = 2): the conventional Burton-Miller count
+  grows with N, the Calderon forms stay flat, beta = -alpha needs no more
+  iterations than beta = 1 (Sec. 7.1, iterations vs N).
+* Against omega (N = 600): both Calderon forms beat the conventional one at
+  every frequency, beta = -alpha "almost always" beats beta = 1.
+* Concentric disks: the modified form converges no slower than the original
+  and both stay flat in N; the conventional one grows (Sec. 7.2).
+* Disk split by a diameter (two triple points): modified < original <
+  conventional (Sec. 7.2).
+GMRES without restart up to 1000 vectors, tolerance 1e-8, angle 0 (Sec. 7);
+a solve that has not converged after 5000 steps counts as unbounded.
+"""
+import math
+
+import pytest
+
+import sweeps
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _col(res, key):
+    return [math.inf if r[key] is None else r[key] for r in res["rows"]]
+
+
+def test_single_material_iterations_against_n():
+    _gpu()
+    res = sweeps.single_N(Ns=(100, 200, 400, 800))
+    print(res, flush=True)
+    conv, b1, ba = _col(res, "conventional"), _col(res, "calderon_beta1"), _col(res, "calderon_beta_minus_alpha")
+    assert math.isfinite(max(conv + b1 + ba))
+    assert conv[-1] > 1.3 * conv[0]
+    assert max(ba) <= 1.3 * min(ba) and max(b1) <= 1.3 * min(b1)
+    assert all(a <= b for a, b in zip(ba, b1))
+    assert ba[-1] < conv[-1]
+
+
+def test_single_material_iterations_against_omega():
+    _gpu()
+    res = sweeps.single_omega(omegas=(1.0, 3.0, 5.0, 7.0, 9.0))
+    print(res, flush=True)
+    conv, b1, ba = _col(res, "conventional"), _col(res, "calderon_beta1"), _col(res, "calderon_beta_minus_alpha")
+    assert all(a < c and b < c for a, b, c in zip(ba, b1, conv))
+    assert sum(a <= b for a, b in zip(ba, b1)) >= 4
+
+
+def test_concentric_iterations_against_n():
+    _gpu()
+    res = sweeps.conc_N(Ns=(150, 300, 600))
+    print(res, flush=True)
+    conv, orig, mod = _col(res, "conventional"), _col(res, "calderon_orig"), _col(res, "calderon_mod")
+    assert all(m <= o for m, o in zip(mod, orig))
+    assert max(mod) <= 1.3 * min(mod) and max(orig) <= 1.3 * min(orig)
+    assert conv[-1] > conv[0] and mod[-1] < conv[-1]
+
+
+def test_junction_disk_ordering():
+    _gpu()
+    res = sweeps.split_omega(omegas=(2.0, 5.0), N=1066)
+    print(res, flush=True)
+    conv, orig, mod = _col(res, "conventional"), _col(res, "calderon_orig"), _col(res, "calderon_mod")
+    assert all(m < o < c for m, o, c in zip(mod, orig, conv))
+    assert math.isfinite(max(orig))
