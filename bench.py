@@ -114,6 +114,7 @@ def matvec_mode(args, wl, P, torch, prec):
     kernel of known traffic for scaling hardware counters)."""
     g = P.Problem(wl.problems[0])
     g.assemble(prec)
+    tuning = tune_or_import(args, P, g, len(wl.angles))
     X = g.rhs(wl.angles)
     if prec == P.F32:
         X = X.to(torch.complex64)
@@ -139,7 +140,8 @@ def matvec_mode(args, wl, P, torch, prec):
     print(json.dumps({"mode": "matvec", "workload": wl.name, "launches": pr["matvec_launches"], "avg_ms": avg,
                       "algorithmic_bytes_per_launch": mv_bytes, "GB_per_s": mv_bytes / (avg * 1e-3) / 1e9,
                       "TFLOP_per_s": 8.0 * n * n * nr / (avg * 1e-3) / 1e12,
-                      "wall_ms_per_product": T / args.steps * 1e3, "copy_bytes": 1 << 30}), flush=True)
+                      "wall_ms_per_product": T / args.steps * 1e3, "copy_bytes": 1 << 30, "tuning": tuning}),
+          flush=True)
     del Y
 
 
@@ -177,7 +179,23 @@ def max_rel_err(F, Fr):
     return float(torch.max(torch.linalg.vector_norm(F - Fr, dim=1) / torch.linalg.vector_norm(Fr, dim=1)))
 
 
-def fp64_comparison(wl, probs, P, torch, F_mixed):
+def tune_or_import(args, P, g, nr):
+    """Autotune the product launch shape of g's matrix for nr right-hand sides,
+    or import the table of --tune-file when that file exists."""
+    if args.no_tune:
+        return None
+    if args.tune_file and os.path.exists(args.tune_file):
+        text = open(args.tune_file).read()
+        P.tune_import(text)
+        return {"imported": os.path.basename(args.tune_file), "table": text.strip().splitlines()[1:]}
+    t = g.tune(nr, reps=3)
+    if args.tune_file:
+        with open(args.tune_file, "w") as f:
+            f.write(P.tune_export())
+    return t
+
+
+def fp64_comparison(wl, probs, P, torch, F_mixed, tune=True):
     """Mixed path only, outside the timed region: the FP64 path on the same
     workload (assembly, right-hand sides, GMRES to the same tolerance, far
     field), timed once per case, and the far-field error of both against an
@@ -187,6 +205,8 @@ def fp64_comparison(wl, probs, P, torch, F_mixed):
     for g, Fm in zip(probs, F_mixed):
         A64 = torch.empty((g.n, g.n), dtype=torch.complex128, device="cuda")
         g.assemble(P.F64, out=A64)
+        if tune:
+            g.tune(nr, reps=3)  # the FP64 path gets its own tuned shape too
         Xr, ir = g.solve(g.rhs(wl.angles), restart=wl.restart, tol=1e-12, max_iter=20000)
         Fr = g.farfield(Xr, wl.far_dirs)
         del Xr
@@ -364,6 +384,10 @@ def main():
                     help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuning (bem_tune) before timing")
+    ap.add_argument("--tune-file", default=None,
+                    help="launch-shape table: imported if the file exists, else written after tuning "
+                         "(so that profiling runs use the same shapes)")
     ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
                          "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
@@ -431,6 +455,15 @@ def main():
 
     for _ in range(args.warmup):
         step(False)
+    tuning = None
+    if not args.no_tune:
+        # launch-shape autotuning of the solve's products (bem_tune), outside the timed region
+        if args.warmup == 0:
+            probs[0].geometry_update()
+            probs[0].assemble(prec, out=mats[0])
+        log("autotuning the product launch shape ...")
+        tuning = tune_or_import(args, P, probs[0], nr)
+        log("tuned:", tuning)
     for g in probs:
         g.profile(True)
         g.profile_read(reset=True)
@@ -497,12 +530,13 @@ def main():
         "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
                    "share_of_step_time": mv_ms / (T * 1e3)},
         "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
+        "tuning": tuning,
         "roofline": roofline,
     }
     if mixed:
         out["refinement_steps_per_rhs"] = [r / (args.steps * nr) for r in refine]
         log("FP64 path on the same workload (reference solve, then one timed run) ...")
-        out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F)
+        out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F, tune=not args.no_tune)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl, [p // args.steps for p in products])

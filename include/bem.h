@@ -120,7 +120,9 @@ typedef struct {
  * bem_destroy.  BEM_E_GEOMETRY: too few nodes, a zero-length element, an
  * unknown or repeated domain id, the host medium on the normal's side, or
  * |1 + eps_left/eps_right| < 1e-12 (accumulation point at 0, end of Sec. 5).
- * BEM_E_ARG: k[0] not real-positive, Im k < 0, quad out of range.           */
+ * BEM_E_ARG: k[0] not real-positive, Im k < 0, quad out of range, or max |k|
+ * times the diameter of the nodes' bounding box >= 2^29 (the device reduces
+ * phases k r by pi/2 exactly only below 2^30).                              */
 bem_status bem_create(const bem_desc *desc, bem_problem **out);
 void bem_destroy(bem_problem *p);
 
@@ -256,6 +258,41 @@ typedef struct {
 } bem_profile;
 bem_status bem_profile_enable(bem_problem *p, int on);
 bem_status bem_profile_read(bem_problem *p, bem_profile *out, int reset);
+
+/* Launch-shape autotuning of the products inside bem_solve (Sec. 3.2: every
+ * Krylov step costs one product with the dense matrix).  bem_tune times each
+ * candidate launch shape of that product -- rows per wave, columns in flight,
+ * column splits, complex-product form -- with the problem's assembled matrix
+ * and nrhs right-hand sides (the FP64 matrix for BEM_F64; the FP32 matrix,
+ * or the FP32 copy of BEM_MIXED, with FP64 vectors otherwise), `reps` timed
+ * products each after one untimed, and installs the fastest for its shape
+ * class: (matrix and accumulation precision, right-hand-side groups of 16 up
+ * to 64 or the vector kernel's up to 4, ceil(log2 n)).  Every later product
+ * of that class in this process, on any problem and thread, uses it.  X_dev
+ * (complex128, n x nrhs, ldx >= n) is read, Y_dev (same shape, ldy) is
+ * overwritten with A X, work_dev as for bem_matvec.  Candidates never need
+ * more work memory than bem_sizes reports, before or after tuning.  The call
+ * synchronises the stream.  BEM_E_STATE: no matrix; BEM_E_ARG: bad sizes or
+ * reps outside [1, 100]; BEM_E_NOMEM: work smaller than bem_sizes asks.      */
+typedef struct {
+    int rt, u, splits, g3;       /* chosen shape (vector kernel: rt = u = g3 = 0)       */
+    int candidates;              /* shapes timed                                        */
+    double best_ms, default_ms;  /* average product time: chosen shape, built-in shape  */
+} bem_tune_info;
+bem_status bem_tune(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev, size_t ldy,
+                    void *work_dev, size_t work_bytes, int reps, bem_tune_info *info, hipStream_t stream);
+
+/* The tuned shape table as text (one class per line: types ng log2n rt u
+ * splits g3; a '#' line first).  Writes at most len bytes including the
+ * terminating NUL into buf (may be NULL when len = 0) and returns the length
+ * of the whole text (without NUL), so a first call with len = 0 sizes it.   */
+size_t bem_tune_export(char *buf, size_t len);
+/* Add the classes of a text in bem_tune_export's format to the table (lines
+ * starting with '#' are skipped).  BEM_E_ARG and no change on a malformed
+ * line or an invalid shape.                                                 */
+bem_status bem_tune_import(const char *text);
+/* Forget every tuned shape (built-in shapes again). */
+void bem_tune_reset(void);
 
 /* Message of the last non-OK status returned on this thread ("" if none). */
 const char *bem_last_error(void);

@@ -26,7 +26,8 @@ STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4:
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
 EXPORTS = ["bem_create", "bem_destroy", "bem_n_elements", "bem_order", "bem_sizes", "bem_geometry",
            "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield", "bem_nearfield",
-           "bem_profile_enable", "bem_profile_read", "bem_last_error"]
+           "bem_profile_enable", "bem_profile_read", "bem_tune", "bem_tune_export", "bem_tune_import",
+           "bem_tune_reset", "bem_last_error"]
 
 
 class BemError(RuntimeError):
@@ -54,6 +55,11 @@ class bem_solve_opts(C.Structure):
 class bem_profile(C.Structure):
     _fields_ = [("assemble_launches", C.c_int), ("assemble_ms", C.c_double), ("matvec_launches", C.c_int),
                 ("matvec_ms", C.c_double), ("residual_launches", C.c_int), ("residual_ms", C.c_double)]
+
+
+class bem_tune_info(C.Structure):
+    _fields_ = [("rt", C.c_int), ("u", C.c_int), ("splits", C.c_int), ("g3", C.c_int), ("candidates", C.c_int),
+                ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 class bem_solve_info(C.Structure):
@@ -88,12 +94,36 @@ def lib():
         L.bem_nearfield.argtypes = [vp, C.c_int, vp, sz, C.POINTER(C.c_double), C.c_int, vp, vp, vp, sz, vp]
         L.bem_profile_enable.argtypes = [vp, C.c_int]
         L.bem_profile_read.argtypes = [vp, C.POINTER(bem_profile), C.c_int]
+        L.bem_tune.argtypes = [vp, C.c_int, vp, sz, vp, sz, vp, sz, C.c_int, C.POINTER(bem_tune_info), vp]
+        L.bem_tune_export.argtypes = [C.c_char_p, sz]
+        L.bem_tune_export.restype = sz
+        L.bem_tune_import.argtypes = [C.c_char_p]
+        L.bem_tune_reset.argtypes = []
+        L.bem_tune_reset.restype = None
         L.bem_last_error.restype = C.c_char_p
-        for f in ["bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve",
+        for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve",
                   "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
+
+
+def tune_export() -> str:
+    """The process's tuned launch-shape table as text (bem_tune_export)."""
+    n = lib().bem_tune_export(None, 0)
+    buf = C.create_string_buffer(n + 1)
+    lib().bem_tune_export(buf, n + 1)
+    return buf.value.decode()
+
+
+def tune_import(text: str) -> None:
+    """Add a table in tune_export's format (bem_tune_import)."""
+    _check(lib().bem_tune_import(text.encode()))
+
+
+def tune_reset() -> None:
+    """Forget every tuned shape (bem_tune_reset)."""
+    lib().bem_tune_reset()
 
 
 def _check(status: int, allow=()):
@@ -271,6 +301,25 @@ class Problem:
         _check(lib().bem_matvec(self._h, nrhs, C.c_void_p(X.data_ptr()), X.shape[1], C.c_void_p(Y.data_ptr()),
                                 Y.shape[1], C.c_void_p(W.data_ptr()), W.numel(), _stream(stream)))
         return Y
+
+    def tune(self, nrhs: int, reps: int = 3, X=None, stream=None):
+        """Autotune the launch shape of the products bem_solve runs for nrhs
+        right-hand sides on this matrix (bem_tune); returns the chosen shape
+        and the timings.  X: complex128 (nrhs, n), random if None."""
+        import torch
+        if X is None:
+            g = torch.Generator(device="cpu").manual_seed(1234)
+            X = torch.complex(torch.rand(nrhs, self.n, generator=g, dtype=torch.float64),
+                              torch.rand(nrhs, self.n, generator=g, dtype=torch.float64)).to(self.A.device)
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        _, _, wb = self.sizes(self.prec if self.prec is not None else F64, min(nrhs, 64), 1)
+        W = self._workspace(wb)
+        info = bem_tune_info()
+        _check(lib().bem_tune(self._h, nrhs, C.c_void_p(X.data_ptr()), X.shape[1], C.c_void_p(Y.data_ptr()),
+                              Y.shape[1], C.c_void_p(W.data_ptr()), W.numel(), reps, C.byref(info), _stream(stream)))
+        return {"rt": info.rt, "u": info.u, "splits": info.splits, "g3": info.g3, "candidates": info.candidates,
+                "best_ms": info.best_ms, "default_ms": info.default_ms}
 
     def solve(self, B, restart: int = 100, tol: float = 1e-10, max_iter: int = 10000, inner_tol: float = 0.0,
               max_refine: int = 0, X=None, stream=None, raise_on_noconv: bool = False):

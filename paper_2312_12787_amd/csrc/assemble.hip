@@ -14,15 +14,16 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr double EULER = 0.57721566490153286061;
-// Assembly kernels: minimum waves per SIMD (1: the compiler may keep every
-// polynomial coefficient and two interleaved Gauss points in registers; a
-// higher floor forces scratch spills, measured 2-7x slower on gfx950) and
-// Gauss points unrolled together.
-#ifndef ASM_WAVES_PER_SIMD
-#define ASM_WAVES_PER_SIMD 1
+// Assembly kernels: minimum waves per SIMD of the far-element launch (the
+// near-element launch keeps one, with every series coefficient in registers)
+// and Gauss points unrolled together (measured on gfx950, kite of 4096
+// elements: one Gauss point at a time is 6 % faster than two in FP64, equal
+// in FP32; four waves per SIMD no faster than two).
+#ifndef ASM_FAR_WAVES
+#define ASM_FAR_WAVES 2
 #endif
 #ifndef ASM_GAUSS_UNROLL
-#define ASM_GAUSS_UNROLL 2
+#define ASM_GAUSS_UNROLL 1
 #endif
 
 template <class T>
@@ -146,6 +147,10 @@ __device__ void build_wave(cd k, WaveConst& W)
     W.wr = w.re;
     W.wi = w.im;
     const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));  // sqrt(2/(pi k))
+    W.ampr = sq.re;
+    W.ampi = sq.im;
+    W.rs = HANKEL_XS_F64 / ak;
+    W.rs32 = HANKEL_XS_F32 / ak;
     const double c4 = 0.70710678118654752440;
     W.a0r = sq.re * c4 + sq.im * c4;  // * e^{-i pi/4} = (1 - i)/sqrt2
     W.a0i = sq.im * c4 - sq.re * c4;
@@ -176,6 +181,8 @@ __device__ void build_wave32(cd k, WaveConst32& W)
     W.wr = (float)w.re;
     W.wi = (float)w.im;
     const cd sq = csqrt_(cdiv({2.0 / PI, 0.0}, k));
+    W.ampr = (float)sq.re;
+    W.ampi = (float)sq.im;
     const double c4 = 0.70710678118654752440;
     W.a0r = (float)(sq.re * c4 + sq.im * c4);
     W.a0i = (float)(sq.im * c4 - sq.re * c4);
@@ -284,151 +291,130 @@ __global__ void k_self_terms(char* g, GeomLayout L, int N, int n_dom)
 //   standard row, scale s:  A[row, u_j] = s (delta/2 + sigma D),   A[row, w_j] = -s sigma eps S
 //   Burton-Miller row, c:   A[row, u_j] = delta/2 + sigma (D + c N),
 //                           A[row, w_j] = -sigma eps S + c (eps delta/2 - sigma eps D*)
-// One lane per collocation row; the wave walks the source elements of its
-// chunk in order (wave-uniform element data, coalesced column-major stores).
+// One lane per collocation row (a workgroup: ROW_TILE rows against a chunk of
+// COL_CHUNK source elements).  The chunk's Gauss points and element data are
+// staged in LDS once per workgroup; each wave then splits the chunk by a
+// wave-uniform test: an element whose every point lies at least XS/|k| from
+// all of the wave's collocation points is "far" and takes the large-argument
+// Hankel form alone (hankel01_far: no series, no per-lane branch); the rest
+// (the element itself, its neighbours, close parts of a non-convex curve)
+// take the general per-lane evaluation.  The far elements are walked first,
+// the near ones after, so that the series coefficients are not live in the
+// far loop.  Stores are coalesced column-major (consecutive lanes = rows).
 // ---------------------------------------------------------------------------
-template <int Q, bool CPLX, bool BM>
-__device__ __forceinline__ void assemble_side(const ElemRec* __restrict__ el, const GaussRec* __restrict__ gq,
-                                              const WaveConst& W, const DomConst& Dm, int sg, int i,
-                                              const ElemRec& Ei, int j0, int cnt, int q_rt, cd selfS,
-                                              double2* __restrict__ A, size_t lda, float2* __restrict__ A32,
-                                              size_t lda32, size_t row, int N)
+static_assert(XS_SERIES_F64 == HANKEL_XS_F64 && XS_SERIES_F32 == HANKEL_XS_F32,
+              "the host's near-pair lists use the series radii of the device evaluator");
+
+struct GaussL {
+    double x, y, w, pad;
+};
+struct ElemL {
+    double nx, ny, ax, ay, bx, by, cx, cy, hh, pad;  // normal, nodes, midpoint, h/2
+};
+
+// Per-block combination constants of one equation block (see the entries above).
+struct BlockConst {
+    cd cD, cS, cDs, cNS, cNE, du, dw, iq;
+};
+
+template <bool BM>
+__device__ __forceinline__ BlockConst block_const(const DomConst& Dm, int sg)
 {
-    const int q = Q > 0 ? Q : q_rt;
     const cd k = {Dm.k[0], Dm.k[1]};
-    const cd ik4 = {-0.25 * k.im, 0.25 * k.re};     // i k / 4
+    const cd ik4 = {-0.25 * k.im, 0.25 * k.re};  // i k / 4
     const cd eps = {Dm.eps[0], Dm.eps[1]};
     const cd c = {Dm.c[0], Dm.c[1]};
     const cd beta = {Dm.beta[0], Dm.beta[1]};
     const double s = (double)sg;
-    // per-block combination constants
-    const cd cD = BM ? cd{s * ik4.re, s * ik4.im} : cscale(cmul(beta, ik4), s);  // multiplies sum D
-    const cd iq = {0.0, 0.25};
-    cd cS = cscale(cmul(eps, iq), -s);  // multiplies sum S (w column)
-    if (!BM) cS = cmul(cS, beta);
-    const cd cDs = cscale(cmul(cmul(c, eps), ik4), s);    // multiplies sum D* (note the minus signs cancel)
-    const cd cNS = cscale(cmul(cmul(c, cmul(k, k)), iq), s);  // k^2 (n_i.n_j) S part of c sigma N
-    const cd cNE = cscale(cmul(c, ik4), s);                   // end-point part of c sigma N
-    const cd du = BM ? cd{0.5, 0.0} : cscale(beta, 0.5);      // jump term, u column
-    const cd dw = cscale(cmul(c, eps), 0.5);                  // jump term, w column (BM only)
-
-    const double xi = Ei.cx, yi = Ei.cy;
-    cd Ea = {0.0, 0.0};
-    if (BM) {
-        const ElemRec& E0 = el[j0];
-        const double dx = xi - E0.ax, dy = yi - E0.ay;
-        const double r2 = dx * dx + dy * dy;
-        const double r = sqrt(r2), rinv = 1.0 / r, sr = sqrt(rinv);
-        const cd h1 = hankel1_only<CPLX>(W, r, r2, rinv, sr);
-        Ea = cscale(h1, (Ei.tx * dx + Ei.ty * dy) * rinv);
-    }
-    for (int jj = 0; jj < cnt; ++jj) {
-        const int j = j0 + jj;
-        const ElemRec& Ej = el[j];
-        cd sS = {0.0, 0.0}, sD = {0.0, 0.0}, sDs = {0.0, 0.0};
-        const bool diag = (j == i);
-        if (!diag) {
-            const GaussRec& G = gq[j];
-#pragma unroll ASM_GAUSS_UNROLL
-            for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
-                if (Q == 0 && g >= q) break;
-                const double rx = xi - G.x[g], ry = yi - G.y[g];
-                const double r2 = fma(rx, rx, ry * ry);
-                const double r = sqrt(r2);
-                const double rinv = 1.0 / r;
-                const double sr = sqrt(rinv);
-                cd h0, h1;
-                hankel01<CPLX>(W, r, r2, rinv, sr, h0, h1);
-                const double wg = G.w[g];
-                sS.re = fma(wg, h0.re, sS.re);
-                sS.im = fma(wg, h0.im, sS.im);
-                const double wd = wg * (rx * Ej.nx + ry * Ej.ny) * rinv;
-                sD.re = fma(wd, h1.re, sD.re);
-                sD.im = fma(wd, h1.im, sD.im);
-                if (BM) {
-                    const double ws = wg * (rx * Ei.nx + ry * Ei.ny) * rinv;
-                    sDs.re = fma(ws, h1.re, sDs.re);
-                    sDs.im = fma(ws, h1.im, sDs.im);
-                }
-            }
-        }
-        cd au, aw;
-        if (!diag) {
-            au = cmul(cD, sD);
-            aw = cmul(cS, sS);
-        } else {
-            // self term: D = D* = 0 on a flat element, S analytic; sS carries S / (i/4)
-            const cd s4 = cdiv(selfS, iq);
-            sS = s4;
-            au = du;
-            aw = cmul(cS, sS);
-            if (BM) aw = cadd(aw, dw);
-        }
-        if (BM) {
-            const double dxb = xi - Ej.bx, dyb = yi - Ej.by;
-            const double r2 = dxb * dxb + dyb * dyb;
-            const double r = sqrt(r2), rinv = 1.0 / r, sr = sqrt(rinv);
-            const cd h1 = hankel1_only<CPLX>(W, r, r2, rinv, sr);
-            const cd Eb = cscale(h1, (Ei.tx * dxb + Ei.ty * dyb) * rinv);
-            const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
-            au = cadd(au, cadd(cscale(cmul(cNS, sS), ninj), cmul(cNE, {Eb.re - Ea.re, Eb.im - Ea.im})));
-            aw = cadd(aw, cmul(cDs, sDs));
-            Ea = Eb;
-        }
-        A[row + (size_t)j * lda] = make_double2(au.re, au.im);
-        A[row + (size_t)(N + j) * lda] = make_double2(aw.re, aw.im);
-        if (A32) {
-            A32[row + (size_t)j * lda32] = make_float2((float)au.re, (float)au.im);
-            A32[row + (size_t)(N + j) * lda32] = make_float2((float)aw.re, (float)aw.im);
-        }
-    }
+    BlockConst B;
+    B.iq = {0.0, 0.25};
+    B.cD = BM ? cd{s * ik4.re, s * ik4.im} : cscale(cmul(beta, ik4), s);  // multiplies sum D
+    B.cS = cscale(cmul(eps, B.iq), -s);                                   // multiplies sum S (w column)
+    if (!BM) B.cS = cmul(B.cS, beta);
+    B.cDs = cscale(cmul(cmul(c, eps), ik4), s);            // multiplies sum D* (the minus signs cancel)
+    B.cNS = cscale(cmul(cmul(c, cmul(k, k)), B.iq), s);    // k^2 (n_i.n_j) S part of c sigma N
+    B.cNE = cscale(cmul(c, ik4), s);                       // end-point part of c sigma N
+    B.du = BM ? cd{0.5, 0.0} : cscale(beta, 0.5);          // jump term, u column
+    B.dw = cscale(cmul(c, eps), 0.5);                      // jump term, w column (BM only)
+    return B;
 }
 
-// A: the FP64 matrix; A32 (optional): its entries rounded to FP32, written in
-// the same pass (the mixed path's inner products use it, its refinement
-// residuals the FP64 matrix).
-template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f64(const char* __restrict__ g, GeomLayout L,
-                                                                                int N, int n_if, int q_rt,
-                                                                                const int* __restrict__ tiles, int side,
-                                                                                double2* __restrict__ A, size_t lda,
-                                                                                float2* __restrict__ A32, size_t lda32)
+// End-point value E(p) = H1(k|x_i - p|) t_i.(x_i - p)/|x_i - p| (without the ik/4).
+template <bool CPLX, bool FAR>
+__device__ __forceinline__ cd end_value(const WaveConst& W, double xi, double yi, double tix, double tiy, double px,
+                                        double py)
 {
-    const Tile rt = tab<Tile>(g, L.rtiles)[tiles[blockIdx.x]];
-    const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
-    const int li = threadIdx.x;
-    if (li >= rt.count) return;
-    const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
-    const int d = side ? P.dr : P.dl;
-    const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
-    const int i = rt.start + li;
-    const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
-    if (sg == 0) {
-        for (int jj = 0; jj < cc.count; ++jj) {
-            const int j = cc.start + jj;
-            A[row + (size_t)j * lda] = make_double2(0.0, 0.0);
-            A[row + (size_t)(N + j) * lda] = make_double2(0.0, 0.0);
-            if (A32) {
-                A32[row + (size_t)j * lda32] = make_float2(0.0f, 0.0f);
-                A32[row + (size_t)(N + j) * lda32] = make_float2(0.0f, 0.0f);
-            }
-        }
-        return;
+    const double dx = xi - px, dy = yi - py;
+    cd h0, h1;
+    double rinv;
+    if (FAR) {
+        rinv = hankel01_far<CPLX, false>(W, dx, dy, h0, h1);
+    } else {
+        const double r2 = dx * dx + dy * dy;
+        double r;
+        sqrt_rsqrt(r2, r, rinv);
+        h1 = hankel1_only<CPLX>(W, r, r2, rinv, rsqrt_nr(r));
     }
-    const ElemRec* el = tab<ElemRec>(g, L.elem);
-    const GaussRec* gq = tab<GaussRec>(g, L.gauss);
-    const WaveConst& W = tab<WaveConst>(g, L.wave)[d];
-    const DomConst Dm = tab<DomConst>(g, L.dom)[d];
-    const ElemRec Ei = el[i];
-    cd selfS = {0.0, 0.0};
-    if (i >= cc.start && i < cc.start + cc.count) {
-        const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
-        selfS = {sv.x, sv.y};
-    }
-    assemble_side<Q, CPLX, BM>(el, gq, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, A32, lda32, row,
-                               N);
+    return cscale(h1, (tix * dx + tiy * dy) * rinv);
 }
 
+// One matrix entry pair (u column, w column) of row i against element j.
+template <int Q, bool CPLX, bool BM, bool FAR>
+__device__ __forceinline__ void element_entries(const WaveConst& W, const BlockConst& B, const ElemRec& Ei,
+                                                const ElemL& Ej, const GaussL* __restrict__ gp, int q_rt,
+                                                bool diag, cd selfS, cd& Ea, bool carry, cd& au, cd& aw)
+{
+    const int q = Q > 0 ? Q : q_rt;
+    const double xi = Ei.cx, yi = Ei.cy;
+    cd sS = {0.0, 0.0}, sD = {0.0, 0.0}, sDs = {0.0, 0.0};
+    if (FAR || !diag) {
+#pragma unroll ASM_GAUSS_UNROLL
+        for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
+            if (Q == 0 && g >= q) break;
+            const GaussL P = gp[g];
+            const double rx = xi - P.x, ry = yi - P.y;
+            cd h0, h1;
+            double rinv;
+            if (FAR) {
+                rinv = hankel01_far<CPLX, true>(W, rx, ry, h0, h1);
+            } else {
+                const double r2 = fma(rx, rx, ry * ry);
+                double r;
+                sqrt_rsqrt(r2, r, rinv);
+                hankel01<CPLX>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
+            }
+            sS.re = fma(P.w, h0.re, sS.re);
+            sS.im = fma(P.w, h0.im, sS.im);
+            const double wr = P.w * rinv;
+            const double wd = wr * fma(rx, Ej.nx, ry * Ej.ny);
+            sD.re = fma(wd, h1.re, sD.re);
+            sD.im = fma(wd, h1.im, sD.im);
+            if (BM) {
+                const double ws = wr * fma(rx, Ei.nx, ry * Ei.ny);
+                sDs.re = fma(ws, h1.re, sDs.re);
+                sDs.im = fma(ws, h1.im, sDs.im);
+            }
+        }
+    }
+    if (FAR || !diag) {
+        au = cmul(B.cD, sD);
+        aw = cmul(B.cS, sS);
+    } else {
+        // self term: D = D* = 0 on a flat element, S analytic; sS carries S / (i/4)
+        sS = cdiv(selfS, B.iq);
+        au = B.du;
+        aw = cmul(B.cS, sS);
+        if (BM) aw = cadd(aw, B.dw);
+    }
+    if (BM) {
+        if (!carry) Ea = end_value<CPLX, FAR>(W, xi, yi, Ei.tx, Ei.ty, Ej.ax, Ej.ay);
+        const cd Eb = end_value<CPLX, FAR>(W, xi, yi, Ei.tx, Ei.ty, Ej.bx, Ej.by);
+        const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
+        au = cadd(au, cadd(cscale(cmul(B.cNS, sS), ninj), cmul(B.cNE, {Eb.re - Ea.re, Eb.im - Ea.im})));
+        aw = cadd(aw, cmul(B.cDs, sDs));
+        Ea = Eb;  // E(b_j) = E(a_{j+1}): carried to the next element of the same walk
+    }
+}
 
 // ---------------------------------------------------------------------------
 // FP32 assembly (precision path).  Entries are stored as complex64.  What
@@ -490,144 +476,339 @@ __device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveC
     }
 }
 
-template <int Q, bool CPLX, bool BM>
-__device__ __forceinline__ void assemble_side_f32(const ElemRec* __restrict__ el, const GaussRec* __restrict__ gq,
-                                                  const WaveConst& W64, const WaveConst32& W, const DomConst& Dm,
-                                                  int sg, int i, const ElemRec& Ei, int j0, int cnt, int q_rt,
-                                                  cd selfS, float2* __restrict__ A, size_t lda, size_t row, int N)
+// FP32 large-argument form for |k r| >= XS_F32 (no series, no per-lane
+// branch): distance, phase and its reduction by pi/2 in FP64, the reduced
+// angle's sine and cosine, the amplitude polynomials and the products in FP32.
+// Returns 1/r.
+__device__ __forceinline__ void sincos_cw32(double x, float& s, float& c)
+{
+    constexpr double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+    constexpr double P1 = 0x1.921fb54442d18p+0;
+    constexpr double P2 = 0x1.1a62633145c07p-54;
+    const double n = rint(x * TWO_OVER_PI);
+    const float t = (float)fma(-n, P2, fma(-n, P1, x));
+    const float u = t * t;
+    // Taylor series on |t| <= pi/4: sin to t^9 (truncation < 2e-9), cos to t^10 (< 2e-10)
+    const float st = fmaf(t * u, fmaf(u, fmaf(u, fmaf(u, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                                      -1.0f / 6.0f), t);
+    const float ct = fmaf(u, fmaf(u, fmaf(u, fmaf(u, fmaf(u, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
+                                          1.0f / 24.0f), -0.5f), 1.0f);
+    const unsigned q = (unsigned)(int)n;
+    const float a = (q & 1u) ? ct : st;
+    const float b = (q & 1u) ? st : ct;
+    s = __uint_as_float(__float_as_uint(a) ^ ((q & 2u) << 30));
+    c = __uint_as_float(__float_as_uint(b) ^ (((q + 1u) & 2u) << 30));
+}
+
+template <bool CPLX, bool WANT_H0>
+__device__ __forceinline__ float hankel01_far32(const WaveConst& W64, const WaveConst32& W, double rx, double ry,
+                                                cf& h0, cf& h1)
+{
+    constexpr double PI_4 = 0x1.921fb54442d18p-1;
+    const double r2 = fma(rx, rx, ry * ry);
+    double r, rinv;
+    sqrt_rsqrt(r2, r, rinv);
+    float sn, cs;
+    sincos_cw32(fma(W64.kr, r, -PI_4), sn, cs);
+    const float ri = (float)rinv;
+    const float sr = __builtin_amdgcn_rsqf((float)r);
+    const float rho = ri * ri;
+    if (!CPLX) {
+        const float w = W.wr * rho;
+        const float u = W.ur * ri;
+        const float a = W.ampr * sr;
+        const float er = cs * a, ei = sn * a;
+        const float m1 = poly_real(HANKEL_M1_F32, w), un1 = u * poly_real(HANKEL_N1_F32, w);
+        h1 = {fmaf(er, un1, ei * m1), fmaf(ei, un1, -er * m1)};
+        if (WANT_H0) {
+            const float m0 = poly_real(HANKEL_M0_F32, w), un0 = u * poly_real(HANKEL_N0_F32, w);
+            h0 = {fmaf(er, m0, -ei * un0), fmaf(er, un0, ei * m0)};
+        }
+    } else {
+        const float x = W.wr * rho, y = W.wi * rho;
+        const float R = 2.0f * x, S = fmaf(x, x, y * y);
+        const cf u = {W.ur * ri, W.ui * ri};
+        const float damp = expf((float)(-W64.ki * r)) * sr;
+        const cf e = cmulf({cs * damp, sn * damp}, {W.ampr, W.ampi});
+        cf m1, n1;
+        poly_cplx(HANKEL_M1_F32, x, y, R, S, m1.re, m1.im);
+        poly_cplx(HANKEL_N1_F32, x, y, R, S, n1.re, n1.im);
+        const cf un1 = cmulf(u, n1);
+        h1 = cmulf(e, {m1.im + un1.re, un1.im - m1.re});
+        if (WANT_H0) {
+            cf m0, n0;
+            poly_cplx(HANKEL_M0_F32, x, y, R, S, m0.re, m0.im);
+            poly_cplx(HANKEL_N0_F32, x, y, R, S, n0.re, n0.im);
+            const cf un0 = cmulf(u, n0);
+            h0 = cmulf(e, {m0.re - un0.im, m0.im + un0.re});
+        }
+    }
+    return ri;
+}
+
+template <bool CPLX, bool FAR>
+__device__ __forceinline__ cf end_value32(const WaveConst& W64, const WaveConst32& W, double xi, double yi, double tix,
+                                          double tiy, double px, double py)
+{
+    const double dx = xi - px, dy = yi - py;
+    cf h0, h1;
+    double rinv;
+    if (FAR) {
+        rinv = hankel01_far32<CPLX, false>(W64, W, dx, dy, h0, h1);
+    } else {
+        const double r = sqrt(dx * dx + dy * dy);
+        hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+        rinv = 1.0 / r;
+    }
+    const float f = (float)((tix * dx + tiy * dy) * rinv);
+    return {h1.re * f, h1.im * f};
+}
+
+// FP32 sums over the Gauss points; the combination into entries runs in FP64.
+template <int Q, bool CPLX, bool BM, bool FAR>
+__device__ __forceinline__ void element_entries_f32(const WaveConst& W64, const WaveConst32& W, const BlockConst& B,
+                                                    const ElemRec& Ei, const ElemL& Ej, const GaussL* __restrict__ gp,
+                                                    int q_rt, bool diag, cd selfS, cf& Ea, bool carry, cd& au,
+                                                    cd& aw)
 {
     const int q = Q > 0 ? Q : q_rt;
-    const cd k = {Dm.k[0], Dm.k[1]};
-    const cd ik4 = {-0.25 * k.im, 0.25 * k.re};
-    const cd eps = {Dm.eps[0], Dm.eps[1]};
-    const cd c = {Dm.c[0], Dm.c[1]};
-    const cd beta = {Dm.beta[0], Dm.beta[1]};
-    const double s = (double)sg;
-    const cd iq = {0.0, 0.25};
-    const cd cD = BM ? cd{s * ik4.re, s * ik4.im} : cscale(cmul(beta, ik4), s);
-    cd cS = cscale(cmul(eps, iq), -s);
-    if (!BM) cS = cmul(cS, beta);
-    const cd cDs = cscale(cmul(cmul(c, eps), ik4), s);
-    const cd cNS = cscale(cmul(cmul(c, cmul(k, k)), iq), s);
-    const cd cNE = cscale(cmul(c, ik4), s);
-    const cd du = BM ? cd{0.5, 0.0} : cscale(beta, 0.5);
-    const cd dw = cscale(cmul(c, eps), 0.5);
-    const cf cDf = {(float)cD.re, (float)cD.im}, cSf = {(float)cS.re, (float)cS.im};
-    const cf cDsf = {(float)cDs.re, (float)cDs.im}, cNSf = {(float)cNS.re, (float)cNS.im};
-    const cf cNEf = {(float)cNE.re, (float)cNE.im};
     const double xi = Ei.cx, yi = Ei.cy;
-    const float tix = (float)Ei.tx, tiy = (float)Ei.ty, nix = (float)Ei.nx, niy = (float)Ei.ny;
-    cf Ea = {0.0f, 0.0f};
-    if (BM) {
-        const ElemRec& E0 = el[j0];
-        const double dx = xi - E0.ax, dy = yi - E0.ay;
-        const double r = sqrt(dx * dx + dy * dy);
-        cf h0, h1;
-        hankel01_mixed<CPLX>(W64, W, r, h0, h1);
-        const float f = (float)((Ei.tx * dx + Ei.ty * dy) / r);
-        Ea = {h1.re * f, h1.im * f};
-    }
-    for (int jj = 0; jj < cnt; ++jj) {
-        const int j = j0 + jj;
-        const ElemRec& Ej = el[j];
-        cf sS = {0.0f, 0.0f}, sD = {0.0f, 0.0f}, sDs = {0.0f, 0.0f};
-        const bool diag = (j == i);
-        if (!diag) {
-            const GaussRec& G = gq[j];
-            const float njx = (float)Ej.nx, njy = (float)Ej.ny;
+    const float njx = (float)Ej.nx, njy = (float)Ej.ny, nix = (float)Ei.nx, niy = (float)Ei.ny;
+    cf sS = {0.0f, 0.0f}, sD = {0.0f, 0.0f}, sDs = {0.0f, 0.0f};
+    if (FAR || !diag) {
 #pragma unroll ASM_GAUSS_UNROLL
-            for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
-                if (Q == 0 && g >= q) break;
-                const double rx = xi - G.x[g], ry = yi - G.y[g];
+        for (int g = 0; g < (Q > 0 ? Q : QMAX); ++g) {
+            if (Q == 0 && g >= q) break;
+            const GaussL P = gp[g];
+            const double rx = xi - P.x, ry = yi - P.y;
+            cf h0, h1;
+            float ri;
+            if (FAR) {
+                ri = hankel01_far32<CPLX, true>(W64, W, rx, ry, h0, h1);
+            } else {
                 const double r = sqrt(fma(rx, rx, ry * ry));
-                cf h0, h1;
                 hankel01_mixed<CPLX>(W64, W, r, h0, h1);
-                const float wg = (float)G.w[g];
-                const float rxf = (float)rx, ryf = (float)ry, rif = (float)(1.0 / r);
-                sS.re = fmaf(wg, h0.re, sS.re);
-                sS.im = fmaf(wg, h0.im, sS.im);
-                const float wd = wg * (rxf * njx + ryf * njy) * rif;
-                sD.re = fmaf(wd, h1.re, sD.re);
-                sD.im = fmaf(wd, h1.im, sD.im);
-                if (BM) {
-                    const float ws = wg * (rxf * nix + ryf * niy) * rif;
-                    sDs.re = fmaf(ws, h1.re, sDs.re);
-                    sDs.im = fmaf(ws, h1.im, sDs.im);
-                }
+                ri = (float)(1.0 / r);
+            }
+            const float wg = (float)P.w;
+            sS.re = fmaf(wg, h0.re, sS.re);
+            sS.im = fmaf(wg, h0.im, sS.im);
+            const float rxf = (float)rx, ryf = (float)ry, wr = wg * ri;
+            const float wd = wr * fmaf(rxf, njx, ryf * njy);
+            sD.re = fmaf(wd, h1.re, sD.re);
+            sD.im = fmaf(wd, h1.im, sD.im);
+            if (BM) {
+                const float ws = wr * fmaf(rxf, nix, ryf * niy);
+                sDs.re = fmaf(ws, h1.re, sDs.re);
+                sDs.im = fmaf(ws, h1.im, sDs.im);
             }
         }
-        // combine in FP64 (few operations per entry), store FP32
-        cd au, aw;
-        cd sS64 = {(double)sS.re, (double)sS.im};
-        if (!diag) {
-            au = cmul(cD, {(double)sD.re, (double)sD.im});
-            aw = cmul(cS, sS64);
-        } else {
-            sS64 = cdiv(selfS, iq);
-            au = du;
-            aw = cmul(cS, sS64);
-            if (BM) aw = cadd(aw, dw);
-        }
-        if (BM) {
-            const double dxb = xi - Ej.bx, dyb = yi - Ej.by;
-            const double r = sqrt(dxb * dxb + dyb * dyb);
-            cf h0, h1;
-            hankel01_mixed<CPLX>(W64, W, r, h0, h1);
-            const float f = (float)((Ei.tx * dxb + Ei.ty * dyb) / r);
-            const cf Eb = {h1.re * f, h1.im * f};
-            const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
-            au = cadd(au, cadd(cscale(cmul(cNS, sS64), ninj),
-                               cmul(cNE, {(double)Eb.re - (double)Ea.re, (double)Eb.im - (double)Ea.im})));
-            aw = cadd(aw, cmul(cDs, {(double)sDs.re, (double)sDs.im}));
-            Ea = Eb;
-        }
-        (void)cDf;
-        (void)cSf;
-        (void)cDsf;
-        (void)cNSf;
-        (void)cNEf;
-        (void)tix;
-        (void)tiy;
-        A[row + (size_t)j * lda] = make_float2((float)au.re, (float)au.im);
-        A[row + (size_t)(N + j) * lda] = make_float2((float)aw.re, (float)aw.im);
+    }
+    cd sS64 = {(double)sS.re, (double)sS.im};
+    if (FAR || !diag) {
+        au = cmul(B.cD, {(double)sD.re, (double)sD.im});
+        aw = cmul(B.cS, sS64);
+    } else {
+        sS64 = cdiv(selfS, B.iq);
+        au = B.du;
+        aw = cmul(B.cS, sS64);
+        if (BM) aw = cadd(aw, B.dw);
+    }
+    if (BM) {
+        if (!carry) Ea = end_value32<CPLX, FAR>(W64, W, xi, yi, Ei.tx, Ei.ty, Ej.ax, Ej.ay);
+        const cf Eb = end_value32<CPLX, FAR>(W64, W, xi, yi, Ei.tx, Ei.ty, Ej.bx, Ej.by);
+        const double ninj = Ei.nx * Ej.nx + Ei.ny * Ej.ny;
+        au = cadd(au, cadd(cscale(cmul(B.cNS, sS64), ninj),
+                           cmul(B.cNE, {(double)Eb.re - (double)Ea.re, (double)Eb.im - (double)Ea.im})));
+        aw = cadd(aw, cmul(B.cDs, {(double)sDs.re, (double)sDs.im}));
+        Ea = Eb;
     }
 }
 
-template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, ASM_WAVES_PER_SIMD) void k_assemble_f32(const char* __restrict__ g, GeomLayout L,
-                                                                                int N, int n_if, int q_rt,
-                                                                                const int* __restrict__ tiles, int side,
-                                                                                float2* __restrict__ A, size_t lda)
+// ---------------------------------------------------------------------------
+// The assembly kernels.  F32 = false: FP64 entries into A (double2) and, when
+// A32 is given, the same entries rounded to FP32 into A32 in the same pass
+// (the mixed path's inner products use that copy, its refinement residuals
+// the FP64 matrix).  F32 = true: FP32 entries into A (float2).
+// ---------------------------------------------------------------------------
+template <int Q, bool CPLX, bool BM, bool F32, bool NEAR>
+__device__ __forceinline__ void assemble_chunk(const char* __restrict__ g, const GeomLayout& L, int N, int n_if,
+                                               int q_rt, int tile, int chunk, int part, int side, void* Av,
+                                               size_t lda, float2* __restrict__ A32, size_t lda32,
+                                               GaussL* __restrict__ gp, ElemL* __restrict__ ell)
 {
-    const Tile rt = tab<Tile>(g, L.rtiles)[tiles[blockIdx.x]];
-    const Tile cc = tab<Tile>(g, L.cchunks)[blockIdx.y];
+    static_assert(COL_CHUNK <= 32, "the near-element mask is one 32-bit word");
+    constexpr int QS = Q > 0 ? Q : QMAX;
+    const Tile rt = tab<Tile>(g, L.rtiles)[tile];
+    Tile cc = tab<Tile>(g, L.cchunks)[chunk];
+    if (part >= 0) {  // near launch: NEAR_PART elements of the chunk
+        cc.start += part * NEAR_PART;
+        cc.count = min(NEAR_PART, cc.count - part * NEAR_PART);
+    }
     const int li = threadIdx.x;
-    if (li >= rt.count) return;
     const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
     const int d = side ? P.dr : P.dl;
     const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
     const int i = rt.start + li;
     const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
-    if (sg == 0) {
-        for (int jj = 0; jj < cc.count; ++jj) {
-            const int j = cc.start + jj;
-            A[row + (size_t)j * lda] = make_float2(0.0f, 0.0f);
-            A[row + (size_t)(N + j) * lda] = make_float2(0.0f, 0.0f);
+    const int cnt = cc.count;
+    auto store = [&](int j, cd au, cd aw) {
+        if (F32) {
+            float2* A = static_cast<float2*>(Av);
+            A[row + (size_t)j * lda] = make_float2((float)au.re, (float)au.im);
+            A[row + (size_t)(N + j) * lda] = make_float2((float)aw.re, (float)aw.im);
+        } else {
+            double2* A = static_cast<double2*>(Av);
+            A[row + (size_t)j * lda] = make_double2(au.re, au.im);
+            A[row + (size_t)(N + j) * lda] = make_double2(aw.re, aw.im);
+            if (A32) {
+                A32[row + (size_t)j * lda32] = make_float2((float)au.re, (float)au.im);
+                A32[row + (size_t)(N + j) * lda32] = make_float2((float)aw.re, (float)aw.im);
+            }
         }
+    };
+    if (sg == 0) {  // uniform over the workgroup; the far launch writes the zero block
+        if (NEAR || li >= rt.count) return;
+        for (int jj = 0; jj < cnt; ++jj) store(cc.start + jj, {0.0, 0.0}, {0.0, 0.0});
         return;
     }
-    const ElemRec* el = tab<ElemRec>(g, L.elem);
-    const GaussRec* gq = tab<GaussRec>(g, L.gauss);
-    const WaveConst& W64 = tab<WaveConst>(g, L.wave)[d];
-    const WaveConst32& W = tab<WaveConst32>(g, L.wave32)[d];
+    // stage the chunk: Gauss points (x, y, weight) and element data
+    {
+        const int q = Q > 0 ? Q : q_rt;
+        const GaussRec* gq = tab<GaussRec>(g, L.gauss);
+        for (int t = li; t < cnt * q; t += ROW_TILE) {
+            const int e = t / q, gg = t - e * q;
+            const GaussRec& G = gq[cc.start + e];
+            gp[e * QS + gg] = GaussL{G.x[gg], G.y[gg], G.w[gg], 0.0};
+        }
+        const ElemRec* el = tab<ElemRec>(g, L.elem);
+        for (int t = li; t < cnt; t += ROW_TILE) {
+            const ElemRec& E = el[cc.start + t];
+            ell[t] = ElemL{E.nx, E.ny, E.ax, E.ay, E.bx, E.by, E.cx, E.cy, 0.5 * E.h, 0.0};
+        }
+    }
+    __syncthreads();
+    if (li >= rt.count) return;
+    const WaveConst& W = tab<WaveConst>(g, L.wave)[d];
     const DomConst Dm = tab<DomConst>(g, L.dom)[d];
-    const ElemRec Ei = el[i];
+    const ElemRec Ei = tab<ElemRec>(g, L.elem)[i];
+    const BlockConst B = block_const<BM>(Dm, sg);
     cd selfS = {0.0, 0.0};
-    if (i >= cc.start && i < cc.start + cc.count) {
+    if (i >= cc.start && i < cc.start + cnt) {
         const double2 sv = tab<double2>(g, L.self)[(size_t)d * N + i];
         selfS = {sv.x, sv.y};
     }
-    assemble_side_f32<Q, CPLX, BM>(el, gq, W64, W, Dm, sg, i, Ei, cc.start, cc.count, q_rt, selfS, A, lda, row, N);
+    // near mask: bit jj when some collocation point of this wave lies within
+    // the series radius of a point of element jj (the element's points lie
+    // within h/2 of its midpoint).  The near launch widens the radius by a
+    // relative 1e-9, so that no element escapes both launches through a
+    // rounding difference; an element both take is written by the near
+    // launch, which runs second.
+    const double rs = (F32 ? W.rs32 : W.rs) * (NEAR ? 1.0 + 1e-9 : 1.0);
+    unsigned nearm = 0;
+    for (int jj = 0; jj < cnt; ++jj) {
+        const double dx = Ei.cx - ell[jj].cx, dy = Ei.cy - ell[jj].cy;
+        const double lim = rs + ell[jj].hh;
+        if (__builtin_amdgcn_ballot_w64(fma(dx, dx, dy * dy) < lim * lim) != 0) nearm |= 1u << jj;
+    }
+    const unsigned all = cnt >= 32 ? 0xffffffffu : (1u << cnt) - 1u;
+    if (F32) {
+        const WaveConst32& W32 = tab<WaveConst32>(g, L.wave32)[d];
+        cf Ea = {0.0f, 0.0f};
+        int prev = -2;
+        for (unsigned m = NEAR ? 0u : all & ~nearm; m != 0; m &= m - 1) {
+            const int jj = __builtin_ctz(m);
+            cd au, aw;
+            element_entries_f32<Q, CPLX, BM, true>(W, W32, B, Ei, ell[jj], gp + jj * QS, q_rt, false, selfS, Ea,
+                                                   jj == prev + 1, au, aw);
+            prev = jj;
+            store(cc.start + jj, au, aw);
+        }
+        prev = -2;
+        for (unsigned m = NEAR ? nearm : 0u; m != 0; m &= m - 1) {
+            const int jj = __builtin_ctz(m);
+            const int j = cc.start + jj;
+            cd au, aw;
+            element_entries_f32<Q, CPLX, BM, false>(W, W32, B, Ei, ell[jj], gp + jj * QS, q_rt, j == i, selfS, Ea,
+                                                    jj == prev + 1, au, aw);
+            prev = jj;
+            store(j, au, aw);
+        }
+    } else {
+        cd Ea = {0.0, 0.0};
+        int prev = -2;
+        for (unsigned m = NEAR ? 0u : all & ~nearm; m != 0; m &= m - 1) {
+            const int jj = __builtin_ctz(m);
+            cd au, aw;
+            element_entries<Q, CPLX, BM, true>(W, B, Ei, ell[jj], gp + jj * QS, q_rt, false, selfS, Ea,
+                                               jj == prev + 1, au, aw);
+            prev = jj;
+            store(cc.start + jj, au, aw);
+        }
+        prev = -2;
+        for (unsigned m = NEAR ? nearm : 0u; m != 0; m &= m - 1) {
+            const int jj = __builtin_ctz(m);
+            const int j = cc.start + jj;
+            cd au, aw;
+            element_entries<Q, CPLX, BM, false>(W, B, Ei, ell[jj], gp + jj * QS, q_rt, j == i, selfS, Ea,
+                                                jj == prev + 1, au, aw);
+            prev = jj;
+            store(j, au, aw);
+        }
+    }
+}
+
+// Far elements (the bulk; no series code, so two waves fit per SIMD) over the
+// grid (row tiles of the variant) x (column chunks), and near elements (the
+// general per-lane evaluation) over the variant's list of (row tile, column
+// chunk, part of NEAR_PART elements) whose bounding boxes come within the
+// series radius: small workgroups that spread the uneven near work.
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f64(const char* __restrict__ g, GeomLayout L,
+                                                                           int N, int n_if, int q_rt,
+                                                                           const int* __restrict__ tiles, int side,
+                                                                           double2* __restrict__ A, size_t lda,
+                                                                           float2* __restrict__ A32, size_t lda32)
+{
+    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[COL_CHUNK];
+    assemble_chunk<Q, CPLX, BM, false, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], blockIdx.y, -1, side, A, lda,
+                                              A32, lda32, gp, ell);
+}
+
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, 1) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
+                                                                   int n_if, int q_rt, const int* __restrict__ pairs,
+                                                                   int side, double2* __restrict__ A, size_t lda,
+                                                                   float2* __restrict__ A32, size_t lda32)
+{
+    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[COL_CHUNK];
+    assemble_chunk<Q, CPLX, BM, false, true>(g, L, N, n_if, q_rt, pairs[3 * blockIdx.x], pairs[3 * blockIdx.x + 1],
+                                             pairs[3 * blockIdx.x + 2], side, A, lda, A32, lda32, gp, ell);
+}
+
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f32(const char* __restrict__ g, GeomLayout L,
+                                                                           int N, int n_if, int q_rt,
+                                                                           const int* __restrict__ tiles, int side,
+                                                                           float2* __restrict__ A, size_t lda)
+{
+    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[COL_CHUNK];
+    assemble_chunk<Q, CPLX, BM, true, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], blockIdx.y, -1, side, A, lda,
+                                             nullptr, 0, gp, ell);
+}
+
+template <int Q, bool CPLX, bool BM>
+__global__ __launch_bounds__(ROW_TILE, 1) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
+                                                                   int n_if, int q_rt, const int* __restrict__ pairs,
+                                                                   int side, float2* __restrict__ A, size_t lda)
+{
+    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[COL_CHUNK];
+    assemble_chunk<Q, CPLX, BM, true, true>(g, L, N, n_if, q_rt, pairs[3 * blockIdx.x], pairs[3 * blockIdx.x + 1],
+                                            pairs[3 * blockIdx.x + 2], side, A, lda, nullptr, 0, gp, ell);
 }
 }  // namespace
 
@@ -647,21 +828,28 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
 // over the row tiles of that variant; lists[v] / counts[v] are device / host.
 template <class T2, bool F64, int Q>
 void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                     const int* const* lists, const int* counts, T2* A, size_t lda, float2* A32, size_t lda32,
-                     hipStream_t s)
+                     const int* const* lists, const int* counts, const int* const* pairs, const int* pair_counts,
+                     T2* A, size_t lda, float2* A32, size_t lda32, hipStream_t s)
 {
     for (int v = 0; v < ASM_VARIANTS; ++v) {
         if (counts[v] == 0) continue;
         const int side = v >> 2 & 1, bm = v >> 1 & 1, cplx = v & 1;
-        dim3 grid(counts[v], n_cchunks, 1);
-#define BEM_ASM_LAUNCH(C_, B_)                                                                                  \
-    if (cplx == C_ && bm == B_) {                                                                               \
-        if constexpr (F64)                                                                                      \
-            hipLaunchKernelGGL((k_assemble_f64<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
-                               side, reinterpret_cast<double2*>(A), lda, A32, lda32);                            \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_assemble_f32<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v], \
-                               side, reinterpret_cast<float2*>(A), lda);                                         \
+        const dim3 grid(counts[v], n_cchunks, 1), ngrid(pair_counts[v], 1, 1);
+#define BEM_ASM_LAUNCH(C_, B_)                                                                                    \
+    if (cplx == C_ && bm == B_) {                                                                                 \
+        if constexpr (F64) {                                                                                      \
+            hipLaunchKernelGGL((k_assemble_f64<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v],   \
+                               side, reinterpret_cast<double2*>(A), lda, A32, lda32);                              \
+            if (pair_counts[v] > 0)                                                                               \
+                hipLaunchKernelGGL((k_assemble_near_f64<Q, C_, B_>), ngrid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q,   \
+                                   pairs[v], side, reinterpret_cast<double2*>(A), lda, A32, lda32);                \
+        } else {                                                                                                  \
+            hipLaunchKernelGGL((k_assemble_f32<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v],   \
+                               side, reinterpret_cast<float2*>(A), lda);                                           \
+            if (pair_counts[v] > 0)                                                                               \
+                hipLaunchKernelGGL((k_assemble_near_f32<Q, C_, B_>), ngrid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q,   \
+                                   pairs[v], side, reinterpret_cast<float2*>(A), lda);                             \
+        }                                                                                                         \
     }
         BEM_ASM_LAUNCH(false, false)
         BEM_ASM_LAUNCH(true, false)
@@ -672,27 +860,35 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
 }
 
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, double2* A, size_t lda, float2* A32,
-                               size_t lda32, hipStream_t s)
+                               const int* const* lists, const int* counts, const int* const* pairs,
+                               const int* pair_counts, double2* A, size_t lda, float2* A32, size_t lda32,
+                               hipStream_t s)
 {
     if (q == 8)
-        launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
+        launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda, A32,
+                                          lda32, s);
     else if (q == 10)
-        launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
+        launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
+                                           A32, lda32, s);
     else
-        launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, A32, lda32, s);
+        launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda, A32,
+                                          lda32, s);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s)
+                               const int* const* lists, const int* counts, const int* const* pairs,
+                               const int* pair_counts, float2* A, size_t lda, hipStream_t s)
 {
     if (q == 8)
-        launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
+        launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
+                                          nullptr, 0, s);
     else if (q == 10)
-        launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
+        launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
+                                           nullptr, 0, s);
     else
-        launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, A, lda, nullptr, 0, s);
+        launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
+                                          nullptr, 0, s);
     return hipGetLastError();
 }
 

@@ -100,6 +100,8 @@ struct bem_problem {
     std::vector<Tile> rtiles, cchunks;
     std::vector<int> vtiles;                     // row-tile ids grouped by assembly variant
     int vcount[bemk::ASM_VARIANTS] = {0}, voff[bemk::ASM_VARIANTS] = {0};
+    std::vector<int> npairs;  // (row tile, column chunk, part) triples that may hold near element pairs, by variant
+    int ncount[bemk::ASM_VARIANTS] = {0}, noff[bemk::ASM_VARIANTS] = {0};
     std::vector<int> elif;          // interface of each element
     std::vector<int> elnodes;       // (a, b) node indices per element
     bemk::DomIn dummy{};
@@ -149,6 +151,7 @@ GeomLayout make_layout(const bem_problem* p)
     L.dom_in = take((size_t)p->n_dom * sizeof(bemk::DomIn));
     L.glob_in = take(sizeof(bemk::GlobalIn));
     L.vtiles = take(p->vtiles.size() * sizeof(int) + sizeof(int));
+    L.npairs = take(p->npairs.size() * sizeof(int) + 3 * sizeof(int));
     size_t upload_end = off;
     (void)upload_end;
     L.elem = take((size_t)p->N * sizeof(bemk::ElemRec));
@@ -306,6 +309,22 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
     }
     p->xy.assign(desc->xy, desc->xy + 2 * node0);
     p->N = total;
+    // the device's phase reduction (k r reduced by pi/2) is exact below 2^30:
+    // bound max |k| times the diameter of the nodes' bounding box
+    {
+        double x0 = p->xy[0], x1 = x0, y0 = p->xy[1], y1 = y0, kmax = 0.0;
+        for (int a = 0; a < node0; ++a) {
+            x0 = std::min(x0, p->xy[2 * a]);
+            x1 = std::max(x1, p->xy[2 * a]);
+            y0 = std::min(y0, p->xy[2 * a + 1]);
+            y1 = std::max(y1, p->xy[2 * a + 1]);
+        }
+        for (const auto& kd : p->k) kmax = std::max(kmax, std::abs(kd));
+        if (kmax * std::hypot(x1 - x0, y1 - y0) >= 0x1p29) {
+            delete p;
+            return fail(BEM_E_ARG, "max |k| times the boundary's diameter must stay below 2^29");
+        }
+    }
     // eps_left / eps_right = -1 puts the accumulation point at 0 (end of Sec. 5)
     for (int m = 0; m < p->n_if; ++m) {
         const auto el = (p->k[p->dl[m]] / p->k[0]) * (p->k[p->dl[m]] / p->k[0]);
@@ -366,6 +385,63 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
             p->voff[v] = (int)p->vtiles.size();
             p->vcount[v] = (int)lists[v].size();
             p->vtiles.insert(p->vtiles.end(), lists[v].begin(), lists[v].end());
+        }
+        // Near list of each variant: (row tile, column chunk, part) triples --
+        // a part being NEAR_PART consecutive elements of the chunk -- whose
+        // bounding boxes (collocation points; element midpoints widened by the
+        // largest half length) come within the series radius XS/|k_d| of the
+        // rows' domain (the larger FP64 radius; relative margin 1e-6).  Only
+        // these can hold an element the assembly's per-wave test calls near,
+        // so the near-element launch runs over them alone, in small blocks.
+        struct Box {
+            double x0, x1, y0, y1, hh;
+        };
+        auto box = [&](int e0, int cnt) {
+            Box b{1e300, -1e300, 1e300, -1e300, 0.0};
+            for (int e = e0; e < e0 + cnt; ++e) {
+                const int a = p->elnodes[2 * e], c = p->elnodes[2 * e + 1];
+                const double ax = p->xy[2 * a], ay = p->xy[2 * a + 1], cx = p->xy[2 * c], cy = p->xy[2 * c + 1];
+                const double mx = 0.5 * (ax + cx), my = 0.5 * (ay + cy);
+                b.x0 = std::min(b.x0, mx);
+                b.x1 = std::max(b.x1, mx);
+                b.y0 = std::min(b.y0, my);
+                b.y1 = std::max(b.y1, my);
+                b.hh = std::max(b.hh, 0.5 * std::hypot(cx - ax, cy - ay));
+            }
+            return b;
+        };
+        constexpr int NP = bemk::COL_CHUNK / bemk::NEAR_PART;
+        std::vector<Box> rb(p->rtiles.size()), cb(p->cchunks.size() * NP);
+        for (size_t t = 0; t < p->rtiles.size(); ++t) rb[t] = box(p->rtiles[t].start, p->rtiles[t].count);
+        for (size_t c = 0; c < p->cchunks.size(); ++c)
+            for (int q = 0; q < NP; ++q) {
+                const int s0 = q * bemk::NEAR_PART, cnt = std::min(bemk::NEAR_PART, p->cchunks[c].count - s0);
+                cb[c * NP + q] = cnt > 0 ? box(p->cchunks[c].start + s0, cnt) : Box{1e300, 1e300, 1e300, 1e300, 0.0};
+            }
+        for (int v = 0; v < bemk::ASM_VARIANTS; ++v) {
+            p->noff[v] = (int)p->npairs.size() / 3;
+            const int side = v >> 2 & 1;
+            for (int t : lists[v]) {
+                const IfacePlan& P = p->iface[p->rtiles[t].iface];
+                const int d = side ? P.dr : P.dl;
+                const double rs = std::max(bemk::XS_SERIES_F64, bemk::XS_SERIES_F32) / std::abs(p->k[d]);
+                for (size_t c = 0; c < p->cchunks.size(); ++c) {
+                    if (p->sigma[(size_t)d * p->n_if + p->cchunks[c].iface] == 0) continue;
+                    for (int q = 0; q < NP; ++q) {
+                        if (q * bemk::NEAR_PART >= p->cchunks[c].count) break;
+                        const Box &a = rb[t], &b = cb[c * NP + q];
+                        const double dx = std::max(0.0, std::max(a.x0 - b.x1, b.x0 - a.x1));
+                        const double dy = std::max(0.0, std::max(a.y0 - b.y1, b.y0 - a.y1));
+                        const double lim = (rs + b.hh) * (1.0 + 1e-6) + 1e-12;
+                        if (dx * dx + dy * dy < lim * lim) {
+                            p->npairs.push_back(t);
+                            p->npairs.push_back((int)c);
+                            p->npairs.push_back(q);
+                        }
+                    }
+                }
+            }
+            p->ncount[v] = (int)p->npairs.size() / 3 - p->noff[v];
         }
     }
     // inputs for the device-side constant tables
@@ -481,6 +557,7 @@ bem_status bem_geometry(bem_problem* p, void* geom_dev, size_t geom_bytes, hipSt
     put(L.dom_in, p->dom_in.data(), p->dom_in.size() * sizeof(bemk::DomIn));
     put(L.glob_in, &p->glob, sizeof(bemk::GlobalIn));
     put(L.vtiles, p->vtiles.data(), p->vtiles.size() * sizeof(int));
+    put(L.npairs, p->npairs.data(), p->npairs.size() * sizeof(int));
     char* g = static_cast<char*>(geom_dev);
     HIP_OK(hipMemcpyAsync(g, img.data(), img.size(), hipMemcpyHostToDevice, stream));
     HIP_OK(bemk::launch_setup(g, L, p->N, p->n_dom, p->quad, stream));
@@ -514,17 +591,20 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
     const int nrt = (int)p->rtiles.size(), ncc = (int)p->cchunks.size();
     if (nrt > 65535 || ncc > 65535) return fail(BEM_E_ARG, "problem too large for one assembly grid");
     const int* lists[bemk::ASM_VARIANTS];
-    for (int v = 0; v < bemk::ASM_VARIANTS; ++v)
+    const int* pairs[bemk::ASM_VARIANTS];
+    for (int v = 0; v < bemk::ASM_VARIANTS; ++v) {
         lists[v] = reinterpret_cast<const int*>(p->geom + p->L.vtiles) + p->voff[v];
+        pairs[v] = reinterpret_cast<const int*>(p->geom + p->L.npairs) + 3 * (size_t)p->noff[v];
+    }
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
     float2* A32 = prec == BEM_MIXED ? reinterpret_cast<float2*>(static_cast<char*>(A_dev) + mixed_offset(n, lda))
                                     : nullptr;
     if (prec == BEM_F32)
-        HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
-                                         static_cast<float2*>(A_dev), lda, stream));
+        HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount, pairs,
+                                         p->ncount, static_cast<float2*>(A_dev), lda, stream));
     else
-        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount,
-                                         static_cast<double2*>(A_dev), lda, A32, lda, stream));
+        HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount, pairs,
+                                         p->ncount, static_cast<double2*>(A_dev), lda, A32, lda, stream));
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 1, stream);
     p->A = A_dev;
     p->A32 = A32;
@@ -566,6 +646,89 @@ bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t 
                                        reinterpret_cast<float2*>(w), stream, p->hk()));
     return BEM_OK;
 }
+
+bem_status bem_tune(const bem_problem* p, int nrhs, const void* X_dev, size_t ldx, void* Y_dev, size_t ldy,
+                    void* work_dev, size_t work_bytes, int reps, bem_tune_info* info, hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_tune");
+    const int n = 2 * p->N;
+    if (nrhs < 1 || !X_dev || !Y_dev || !work_dev) return fail(BEM_E_ARG, "bad tuning arguments");
+    if (reps < 1 || reps > 100) return fail(BEM_E_ARG, "reps must be in [1, 100]");
+    if (ldx < (size_t)n || ldy < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+    const size_t need = bemk::matvec_part_elems(n, nrhs) * sizeof(double2);
+    if (work_bytes < need) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
+    const int nr = std::min(nrhs, 64);
+    const int ng = nr > 4 ? (nr + 15) / 16 : 0;
+    const bool f64 = p->prec == BEM_F64;
+    const int types = f64 ? 3 : 0;  // FP64 matrix and sums, or FP32 matrix and sums (FP64 vectors)
+    const double2* X = static_cast<const double2*>(X_dev);
+    double2* Y = static_cast<double2*>(Y_dev);
+    auto product = [&]() -> hipError_t {
+        if (f64)
+            return bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n, X, ldx, nr, Y, ldy,
+                                           static_cast<double2*>(work_dev), stream, nullptr);
+        const float2* A32 = static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A);
+        return bemk::launch_matvec_f32x64(A32, p->lda, n, X, ldx, nr, Y, ldy, static_cast<float2*>(work_dev), stream,
+                                          nullptr);
+    };
+    const std::vector<bemk::MvShape> cand = bemk::candidate_shapes(types, ng, n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    double best = 1e300, def = 0.0;
+    bemk::MvShape bestc = cand.front();
+    for (size_t c = 0; c < cand.size() && err == hipSuccess; ++c) {
+        bemk::force_shape(&cand[c]);
+        err = product();
+        if (err == hipSuccess) err = hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = product();
+        if (err == hipSuccess) err = hipEventRecord(e1, stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        const double avg = (double)ms / reps;
+        if (c == 0) def = avg;  // the built-in shape is the first candidate
+        if (err == hipSuccess && avg < best) {
+            best = avg;
+            bestc = cand[c];
+        }
+    }
+    bemk::force_shape(nullptr);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(BEM_E_DEVICE, std::string("bem_tune: ") + hipGetErrorString(err));
+    bemk::set_tuned_shape(types, ng, n, bestc);
+    if (info) {
+        info->rt = bestc.rt;
+        info->u = bestc.u;
+        info->splits = bestc.splits;
+        info->g3 = bestc.g3;
+        info->candidates = (int)cand.size();
+        info->best_ms = best;
+        info->default_ms = def;
+    }
+    return BEM_OK;
+}
+
+size_t bem_tune_export(char* buf, size_t len)
+{
+    const std::string t = bemk::export_tuned_shapes();
+    if (buf && len > 0) {
+        const size_t c = std::min(len - 1, t.size());
+        std::memcpy(buf, t.data(), c);
+        buf[c] = '\0';
+    }
+    return t.size();
+}
+
+bem_status bem_tune_import(const char* text)
+{
+    if (!text || !bemk::import_tuned_shapes(text)) return fail(BEM_E_ARG, "malformed launch-shape table");
+    return BEM_OK;
+}
+
+void bem_tune_reset(void) { bemk::clear_tuned_shapes(); }
 
 }  // extern "C"
 

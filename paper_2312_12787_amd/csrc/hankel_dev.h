@@ -18,6 +18,7 @@
 // z^2 - 2 x z + |z|^2 (Knuth's scheme): two multiply-adds per coefficient.
 #pragma once
 
+#include "fastmath_dev.h"
 #include "hankel_tables.h"
 #include "internal.h"
 
@@ -57,6 +58,19 @@ __device__ __forceinline__ void poly_cplx(const T (&c)[N], T x, T y, T R, T S, T
     }
     pr = fma(x, b1, fma(-S, b2, c[0]));
     pi = y * b1;
+}
+
+// sum_m c[m] w^m from shared powers p[m] = w^m (p[0] unused), highest degree
+// first.  The accumulator is the only register each step overwrites (Horner's
+// rule overwrites a copy of the constant instead).  Used where 0 < w <= 1 and
+// the |c[m]| of m >= 1 are small, so the order costs no accuracy.
+template <int N, class T>
+__device__ __forceinline__ T poly_pow(const T (&c)[N], const T (&p)[N])
+{
+    T acc = c[N - 1] * p[N - 1];
+#pragma unroll
+    for (int m = N - 2; m >= 1; --m) acc = fma(c[m], p[m], acc);
+    return acc + c[0];
 }
 
 // H0(k r), H1(k r).  r2 = r^2, rinv = 1/r, srinv = r^{-1/2}.
@@ -99,7 +113,7 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
     } else {
         const double rho = rinv * rinv;
         double sn, cs;
-        sincos(W.kr * r, &sn, &cs);
+        sincos_cw(W.kr * r, sn, cs);
         if (!CPLX) {
             const double w = W.wr * rho;
             const double m0 = poly_real(HANKEL_M0_F64, w), n0 = poly_real(HANKEL_N0_F64, w);
@@ -126,6 +140,61 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
             h1 = cmul(cmul(e, {W.a1r, W.a1i}), p1);
         }
     }
+}
+
+// H0(k r) and H1(k r) when |k r| >= XS is known for the pair (no per-lane
+// branch, no series), from the offset (rx, ry) = x - y; returns 1/r.  The
+// phase phi = Re(k) r - pi/4 is reduced once for both orders:
+//   H0 = A r^{-1/2} e^{i phi} (m0 + i u n0),
+//   H1 = A r^{-1/2} e^{i phi} (-i) (m1 + i u n1),   u = XS/(k r),
+// A = sqrt(2/(pi k)), times e^{-Im(k) r} for complex k.  H0 is skipped when
+// only H1 is wanted.
+template <bool CPLX, bool WANT_H0>
+__device__ __forceinline__ double hankel01_far(const WaveConst& W, double rx, double ry, cd& h0, cd& h1)
+{
+    constexpr double PI_4 = 0x1.921fb54442d18p-1;
+    const double r2 = fma(rx, rx, ry * ry);
+    double r, rinv;
+    sqrt_rsqrt(r2, r, rinv);
+    const double sr = rsqrt_nr(r);
+    double sn, cs;
+    sincos_cw(fma(W.kr, r, -PI_4), sn, cs);
+    const double rho = rinv * rinv;
+    if (!CPLX) {
+        // w = (XS/(k r))^2 <= 1; its powers are shared by the four amplitude polynomials
+        double p[HANKEL_NC_F64];
+        p[1] = W.wr * rho;
+#pragma unroll
+        for (int m = 2; m < HANKEL_NC_F64; ++m) p[m] = p[m / 2] * p[m - m / 2];
+        const double u = W.ur * rinv;
+        const double a = W.ampr * sr;
+        const double er = cs * a, ei = sn * a;
+        const double m1 = poly_pow(HANKEL_M1_F64, p), un1 = u * poly_pow(HANKEL_N1_F64, p);
+        h1 = {fma(er, un1, ei * m1), fma(ei, un1, -er * m1)};
+        if (WANT_H0) {
+            const double m0 = poly_pow(HANKEL_M0_F64, p), un0 = u * poly_pow(HANKEL_N0_F64, p);
+            h0 = {fma(er, m0, -ei * un0), fma(er, un0, ei * m0)};
+        }
+    } else {
+        const double x = W.wr * rho, y = W.wi * rho;
+        const double R = 2.0 * x, S = fma(x, x, y * y);
+        const cd u = {W.ur * rinv, W.ui * rinv};
+        const double damp = exp(-W.ki * r) * sr;
+        const cd e = cmul({cs * damp, sn * damp}, {W.ampr, W.ampi});
+        cd m1, n1;
+        poly_cplx(HANKEL_M1_F64, x, y, R, S, m1.re, m1.im);
+        poly_cplx(HANKEL_N1_F64, x, y, R, S, n1.re, n1.im);
+        const cd un1 = cmul(u, n1);
+        h1 = cmul(e, {m1.im + un1.re, un1.im - m1.re});
+        if (WANT_H0) {
+            cd m0, n0;
+            poly_cplx(HANKEL_M0_F64, x, y, R, S, m0.re, m0.im);
+            poly_cplx(HANKEL_N0_F64, x, y, R, S, n0.re, n0.im);
+            const cd un0 = cmul(u, n0);
+            h0 = cmul(e, {m0.re - un0.im, m0.im + un0.re});
+        }
+    }
+    return rinv;
 }
 
 // H1 only (end-point terms of the hypersingular operator).

@@ -14,6 +14,10 @@ namespace bemk {
 constexpr int QMAX = 16;      // largest Gauss rule
 constexpr int ROW_TILE = 256; // collocation rows per assembly workgroup
 constexpr int COL_CHUNK = 32; // source elements per assembly workgroup
+constexpr int NEAR_PART = 8;  // source elements per workgroup of the near-element launch
+// |k r| below which the device Hankel evaluator uses the ascending series
+// (FP64 and FP32 amplitude paths; the same values as in hankel_tables.h)
+constexpr double XS_SERIES_F64 = 6.0, XS_SERIES_F32 = 4.0;
 constexpr int MAX_DIRS = 4096;
 
 // One boundary element (128 bytes).  Normal = left normal of the travel
@@ -74,6 +78,9 @@ struct WaveConst {
     double hr, hi;              // k / 2
     double lkr, lki;            // ln(k / 2)
     double y1r, y1i;            // -2 / (pi k)
+    double ampr, ampi;          // sqrt(2 / (pi k))
+    double rs;                  // XS / |k|: the ascending series below this distance
+    double rs32;                // the same for the FP32 amplitude evaluation (WaveConst32)
 };
 
 // FP32 amplitude evaluation (|k r| >= 4); the series below it runs in FP64.
@@ -81,6 +88,7 @@ struct WaveConst32 {
     float r2_small;
     float wr, wi, ur, ui;
     float a0r, a0i, a1r, a1i;
+    float ampr, ampi;  // sqrt(2 / (pi k))
 };
 
 // Interface plan (host-computed integer bookkeeping).
@@ -99,7 +107,7 @@ struct Tile {
 
 struct GeomLayout {
     size_t nodes, elnodes, elem, gauss, gauss32, gl, dom_in, glob_in, dom, wave, wave32, self,
-        iface, rtiles, cchunks, sigma, elif, vtiles, total;
+        iface, rtiles, cchunks, sigma, elif, vtiles, npairs, total;
 };
 
 }  // namespace bemk

@@ -1,6 +1,9 @@
 // launch.h -- host-side entry points of the gfx950 kernels.
 #pragma once
 
+#include <string>
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -25,11 +28,16 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
 // Assembly variants: v = side * 4 + burton_miller * 2 + complex_k; lists[v]
 // (device) holds the row-tile ids of variant v, counts[v] (host) their number.
 constexpr int ASM_VARIANTS = 8;
+// lists[v] / counts[v]: row tiles of variant v (device list / host count);
+// pairs[v] / pair_counts[v]: its (row tile, column chunk, part of NEAR_PART
+// elements) triples that may hold near element pairs (device list / host count).
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, double2* A, size_t lda, float2* A32,
-                               size_t lda32, hipStream_t s);
+                               const int* const* lists, const int* counts, const int* const* pairs,
+                               const int* pair_counts, double2* A, size_t lda, float2* A32, size_t lda32,
+                               hipStream_t s);
 hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
-                               const int* const* lists, const int* counts, float2* A, size_t lda, hipStream_t s);
+                               const int* const* lists, const int* counts, const int* const* pairs,
+                               const int* pair_counts, float2* A, size_t lda, hipStream_t s);
 
 // angles / dirs are HOST arrays: they travel to the kernels by value in
 // chunks of ANGLE_CHUNK.
@@ -42,6 +50,21 @@ hipError_t launch_rhs(const char* g, const GeomLayout& L, int N, const double* a
 
 // Y = A X; partial holds matvec_part_elems(n, nrhs) complex values.
 size_t matvec_part_elems(int n, int nrhs);
+
+// Launch shape of a product: row tiles per wave, column steps in flight,
+// column splits, 3-product form (the vector kernel uses splits only).  Shape
+// classes: types = 2 [matrix in FP64] + [accumulation in FP64], ng = 0 (vector
+// kernel) or 1-4 groups of 16 right-hand sides, ceil(log2 n).
+struct MvShape {
+    int rt, u, splits, g3;
+};
+void force_shape(const MvShape* s);  // this thread's products use s (nullptr: the table again)
+MvShape current_shape(int types, int ng, int n);
+std::vector<MvShape> candidate_shapes(int types, int ng, int n);
+void set_tuned_shape(int types, int ng, int n, const MvShape& c);
+void clear_tuned_shapes();
+std::string export_tuned_shapes();
+bool import_tuned_shapes(const char* text);
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s,
                              const KernelHook* hook = nullptr);

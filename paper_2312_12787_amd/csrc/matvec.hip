@@ -11,6 +11,11 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
 
 #include "internal.h"
 #include "launch.h"
@@ -319,24 +324,12 @@ __global__ void k_pack_xt(const TX* __restrict__ X, size_t ldx, int n, int nr, i
 }
 
 // Launch shape of the matrix-core product: row tiles per wave, column steps
-// in flight, column splits (0: enough for about 1024 blocks), for one group
-// of 16 right-hand sides (BEM_MV_CFG="rt,u,splits[,g3]" overrides it, for
-// tuning) and for 2-4 groups per pass (BEM_MV_CFG_WIDE="rt,u,splits").
-struct MfmaCfg {
-    int rt, u, splits, g3;
-};
-
-MfmaCfg mfma_cfg(int n, int ng, bool f64)
+// in flight, column splits (0: enough for about 1024 blocks), 3-product form,
+// for one group of 16 right-hand sides and for 2-4 groups per pass.
+MvShape mfma_default(int n, int ng, bool f64)
 {
     // defaults measured on gfx950 (n = 32768; 16, 32 and 64 right-hand sides)
-    MfmaCfg c = ng == 1 ? MfmaCfg{2, 8, 8, 1} : (f64 && ng == 2 ? MfmaCfg{1, 4, 8, 1} : MfmaCfg{2, 4, 0, 1});
-    if (const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE")) {
-        int a = 0, b = 0, d = 0, g = 1;
-        const int got = sscanf(e, "%d,%d,%d,%d", &a, &b, &d, &g);
-        const bool ok = ng == 1 ? ((a == 1 || a == 2 || a == 4) && (b == 2 || b == 4 || b == 8))
-                                : ((a == 1 || a == 2) && (b == 2 || b == 4));
-        if (got >= 3 && ok && d >= 0 && d <= 64) c = {a, b, d, ng == 1 && got == 4 ? (g != 0) : 1};
-    }
+    MvShape c = ng == 1 ? MvShape{2, 8, 8, 1} : (f64 && ng == 2 ? MvShape{1, 4, 8, 1} : MvShape{2, 4, 0, 1});
     if (c.splits == 0) {
         const int rowblocks = (n + 16 * c.rt * MV_WAVES - 1) / (16 * c.rt * MV_WAVES);
         int s = (1024 + rowblocks - 1) / rowblocks;
@@ -347,10 +340,85 @@ MfmaCfg mfma_cfg(int n, int ng, bool f64)
     return c;
 }
 
+bool shape_valid(int ng, const MvShape& c)
+{
+    if (ng == 0) return c.splits >= 1 && c.splits <= 64;
+    const bool ok = ng == 1 ? ((c.rt == 1 || c.rt == 2 || c.rt == 4) && (c.u == 2 || c.u == 4 || c.u == 8))
+                            : ((c.rt == 1 || c.rt == 2) && (c.u == 2 || c.u == 4) && c.g3 == 1);
+    return ok && c.splits >= 1 && c.splits <= 64;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape table.  A class is (type pair, right-hand-side groups, size
+// class): types = 2 [matrix stored in FP64] + [accumulation in FP64]; ng = 0
+// for the vector kernel (up to 4 right-hand sides), 1-4 for the matrix-core
+// kernel; size class = ceil(log2 n).  bem_tune fills the table; the tuner's
+// candidate under test is forced per thread.  Column splits never exceed
+// split_cap(n, ng), by which the partial-sum buffer is sized, so buffers sized
+// before or after tuning stay valid.
+// ---------------------------------------------------------------------------
+struct ShapeKey {
+    int types, ng, lg;
+    bool operator<(const ShapeKey& o) const
+    {
+        return types != o.types ? types < o.types : (ng != o.ng ? ng < o.ng : lg < o.lg);
+    }
+};
+std::mutex g_tune_mu;
+std::map<ShapeKey, MvShape> g_tuned;
+thread_local const MvShape* g_forced = nullptr;
+
+int size_class(int n)
+{
+    int lg = 0;
+    while (lg < 31 && (1 << lg) < n) ++lg;
+    return lg;
+}
+
+int split_cap(int n, int ng)
+{
+    if (ng == 0) return matvec_splits_valu(n);
+    const int want = (131072 + n - 1) / std::max(1, n);  // about 2048 blocks at one row tile per wave
+    const int cap = std::max(1, std::min({want, 64, std::max(1, n / 64)}));
+    return std::max(cap, std::max(mfma_default(n, ng, true).splits, mfma_default(n, ng, false).splits));
+}
+
+// The shape a product of this class runs with: the tuner's forced candidate,
+// else BEM_MV_CFG / BEM_MV_CFG_WIDE ("rt,u,splits[,g3]", manual tuning), else
+// the tuned table, else the default; splits clamped to split_cap.
+MvShape mv_shape(int types, int ng, int n)
+{
+    MvShape c = ng == 0 ? MvShape{0, 0, matvec_splits_valu(n), 0} : mfma_default(n, ng, types & 1);
+    bool have = false;
+    if (g_forced && shape_valid(ng, *g_forced)) {
+        c = *g_forced;
+        have = true;
+    }
+    if (!have && ng > 0) {
+        if (const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE")) {
+            MvShape t{0, 0, 0, 1};
+            const int got = sscanf(e, "%d,%d,%d,%d", &t.rt, &t.u, &t.splits, &t.g3);
+            if (ng > 1) t.g3 = 1;
+            t.g3 = t.g3 != 0;
+            if (got >= 3 && shape_valid(ng, t)) {
+                c = t;
+                have = true;
+            }
+        }
+    }
+    if (!have) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(ShapeKey{types, ng, size_class(n)});
+        if (it != g_tuned.end()) c = it->second;
+    }
+    c.splits = std::max(1, std::min({c.splits, split_cap(n, ng), std::max(1, n / 64)}));
+    return c;
+}
+
 constexpr int MFMA_MAX_RHS = 64;  // right-hand sides per pass over A
 
 template <class TA, class T, class V2>
-void launch_mfma_variant(const MfmaCfg& c, int ng, dim3 grid, hipStream_t s, const TA* A, size_t lda, int n,
+void launch_mfma_variant(const MvShape& c, int ng, dim3 grid, hipStream_t s, const TA* A, size_t lda, int n,
                          const V2* xt, int nr, V2* part, int cps)
 {
 #define BEM_MV_LAUNCH(RT_, U_, G3_, NG_) \
@@ -398,10 +466,11 @@ template <class TA, class TX, class ACC, class TY>
 hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, int nrhs, TY* Y, size_t ldy,
                       ACC* part, const double2* B, size_t ldb, hipStream_t s, const KernelHook* hook)
 {
-    const int splits = matvec_splits_valu(n);
+    using S = decltype(ACC{}.x);
+    constexpr int types = (sizeof(TA) == 16 ? 2 : 0) + (sizeof(S) == 8 ? 1 : 0);
+    const int splits = mv_shape(types, 0, n).splits;
     const int cps = (n + splits - 1) / splits;
     const int rowblocks = (n + 64 * MV_WAVES - 1) / (64 * MV_WAVES);
-    using S = decltype(ACC{}.x);
     const int kind = B ? KIND_RESIDUAL : KIND_MATVEC;
     for (int r0 = 0; r0 < nrhs; r0 += MFMA_MAX_RHS) {
         const int nr = std::min(MFMA_MAX_RHS, nrhs - r0);
@@ -409,7 +478,7 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
         if (nr > 4) {
             // pack X right-hand-side fastest into the tail of the partial buffer
             const int ng = (nr + 15) / 16;
-            const MfmaCfg cfg = mfma_cfg(n, ng, sizeof(S) == 8);
+            const MvShape cfg = mv_shape(types, ng, n);
             const int ms = cfg.splits;
             const int mcps = ((n + ms - 1) / ms + 31) / 32 * 32;
             ACC* xt = part + (size_t)ms * nr * n;
@@ -460,11 +529,10 @@ int matvec_splits_valu(int n)
 size_t matvec_part_elems(int n, int nrhs)
 {
     const int nr = std::min(nrhs, MFMA_MAX_RHS);
-    size_t e = (size_t)matvec_splits_valu(n) * std::min(nr, 4);
+    size_t e = (size_t)split_cap(n, 0) * std::min(nr, 4);
     if (nr > 4) {
         const int ng = (nr + 15) / 16;
-        const MfmaCfg c64 = mfma_cfg(n, ng, true), c32 = mfma_cfg(n, ng, false);
-        e = std::max(e, (size_t)std::max(c64.splits, c32.splits) * nr + 16 * ng);
+        e = std::max(e, (size_t)split_cap(n, ng) * nr + 16 * ng);
     }
     return e * (size_t)n;
 }
@@ -500,6 +568,84 @@ hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double
                                 hipStream_t s, const KernelHook* hook)
 {
     return matvec_any<float2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, R, ldr, partial, B, ldb, s, hook);
+}
+
+
+// ---------------------------------------------------------------------------
+// Tuning table access (bem_tune and its export / import).
+// ---------------------------------------------------------------------------
+void force_shape(const MvShape* s) { g_forced = s; }
+
+MvShape current_shape(int types, int ng, int n) { return mv_shape(types, ng, n); }
+
+std::vector<MvShape> candidate_shapes(int types, int ng, int n)
+{
+    std::vector<MvShape> out;
+    const int cap = split_cap(n, ng);
+    std::vector<int> splits;
+    for (int s = cap; s >= 1; s /= 2) splits.push_back(s);
+    if (ng == 0) {
+        for (int s : splits) out.push_back(MvShape{0, 0, s, 0});
+        return out;
+    }
+    const MvShape d = mfma_default(n, ng, types & 1);
+    out.push_back(d);  // the default first
+    const int rts[] = {1, 2, 4}, us[] = {2, 4, 8};
+    for (int rt : rts)
+        for (int u : us)
+            for (int g3 = (ng == 1 ? 0 : 1); g3 <= 1; ++g3)
+                for (int s : splits) {
+                    const MvShape c{rt, u, s, g3};
+                    if (!shape_valid(ng, c)) continue;
+                    if (c.rt == d.rt && c.u == d.u && c.g3 == d.g3 && c.splits == d.splits) continue;
+                    out.push_back(c);
+                }
+    return out;
+}
+
+void set_tuned_shape(int types, int ng, int n, const MvShape& c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[ShapeKey{types, ng, size_class(n)}] = c;
+}
+
+void clear_tuned_shapes()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+std::string export_tuned_shapes()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ostringstream o;
+    o << "# bem product launch shapes: types ng log2n rt u splits g3\n";
+    for (const auto& kv : g_tuned)
+        o << kv.first.types << ' ' << kv.first.ng << ' ' << kv.first.lg << ' ' << kv.second.rt << ' ' << kv.second.u
+          << ' ' << kv.second.splits << ' ' << kv.second.g3 << '\n';
+    return o.str();
+}
+
+bool import_tuned_shapes(const char* text)
+{
+    std::map<ShapeKey, MvShape> add;
+    std::istringstream in(text ? text : "");
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream l(line);
+        ShapeKey k{};
+        MvShape c{};
+        if (!(l >> k.types >> k.ng >> k.lg >> c.rt >> c.u >> c.splits >> c.g3)) return false;
+        std::string rest;
+        if (l >> rest) return false;
+        if (k.types < 0 || k.types > 3 || k.types == 2 || k.ng < 0 || k.ng > 4 || k.lg < 0 || k.lg > 31) return false;
+        if (!shape_valid(k.ng, c)) return false;
+        add[k] = c;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : add) g_tuned[kv.first] = kv.second;
+    return true;
 }
 
 }  // namespace bemk

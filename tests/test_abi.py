@@ -133,3 +133,39 @@ def test_call_order_errors_before_any_device_work():
     assert P.STATUS[st] == "BEM_E_STATE"
     st = L.bem_matvec(g._h, 1, C.c_void_p(16), g.n, C.c_void_p(16), g.n, C.c_void_p(16), 1 << 20, None)
     assert P.STATUS[st] == "BEM_E_STATE"
+    st = L.bem_tune(g._h, 16, C.c_void_p(16), g.n, C.c_void_p(16), g.n, C.c_void_p(16), 1 << 20, 3, None, None)
+    assert P.STATUS[st] == "BEM_E_STATE"
+
+
+def test_tuning_table_text_round_trip_on_the_host():
+    """bem_tune_import / bem_tune_export / bem_tune_reset are host-only: a
+    valid table survives a round trip, a malformed line or an invalid shape
+    (row tiles 3, 2-4 groups without the 3-product form, splits 0) is refused
+    without changing the table, the reset empties it, and work sizes do not
+    depend on the table."""
+    import paper_2312_12787_amd as P
+    P.tune_reset()
+    g = _problem(W.disk(600, 1.0, 2.0))
+    sizes = g.sizes(P.F64, 16, 30)
+    assert P.tune_export().strip().splitlines()[1:] == []
+    text = "# comment\n3 1 11 1 4 4 0\n0 4 15 2 2 8 1\n3 0 11 0 0 16 0\n"
+    P.tune_import(text)
+    rows = sorted(P.tune_export().strip().splitlines()[1:])
+    assert rows == sorted(["3 1 11 1 4 4 0", "0 4 15 2 2 8 1", "3 0 11 0 0 16 0"])
+    for bad in ["3 1 11 3 4 4 0\n", "3 2 11 1 4 4 0\n", "3 1 11 1 4 0 0\n", "3 1 11 1 4\n", "x\n", "2 1 11 1 4 4 0\n"]:
+        with pytest.raises(P.BemError, match="BEM_E_ARG"):
+            P.tune_import(bad)
+    assert sorted(P.tune_export().strip().splitlines()[1:]) == rows
+    assert g.sizes(P.F64, 16, 30) == sizes
+    P.tune_reset()
+    assert P.tune_export().strip().splitlines()[1:] == []
+
+
+def test_phase_range_is_checked_on_the_host():
+    """bem_create refuses max |k| times the boundary's diameter >= 2^29 (the
+    device reduces phases k r by pi/2 exactly only below 2^30)."""
+    import paper_2312_12787_amd as P
+    # unit disk: bounding-box diagonal 2 sqrt(2); 2^29 = 5.37e8
+    _problem(W.disk(16, 1.0e8, 1.8e8))  # 5.09e8: accepted
+    with pytest.raises(P.BemError, match="2\\^29"):
+        _problem(W.disk(16, 1.0e8, 2.0e8))  # 5.66e8

@@ -149,7 +149,10 @@ def test_solve_kite_forms_and_restart(form):
 
 
 def test_batched_columns_equal_single_solves():
-    """Each column of a 16-angle block solve equals its own single solve."""
+    """Each column of a 16-angle block solve equals its own single solve.  The
+    block's products run on the matrix cores, a single right-hand side's on
+    the vector units, with different summation orders: the residual histories
+    agree to rounding, so the step at which 1e-12 is reached may differ by one."""
     P = _gpu()
     spec = W.kite(256, 8.0, 12.0)
     g = P.Problem(spec)
@@ -161,7 +164,7 @@ def test_batched_columns_equal_single_solves():
     for r in (0, 5, 15):
         x1, i1 = g.solve(B[r:r + 1], restart=30, tol=1e-12)
         assert rel_err(X[r].cpu().numpy(), x1[0].cpu().numpy()) < 1e-10
-        assert i1.iters[0] == info.iters[r]
+        assert abs(int(i1.iters[0]) - int(info.iters[r])) <= 1
 
 
 def test_noconv_status_and_zero_rhs():
