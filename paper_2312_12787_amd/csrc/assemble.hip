@@ -15,7 +15,7 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr double EULER = 0.57721566490153286061;
 // Assembly kernels: minimum waves per SIMD of the far-element launch (the
-// near-element launch keeps one, with every series coefficient in registers)
+// near-element launch reads its coefficients by scalar loads and runs two)
 // and Gauss points unrolled together (measured on gfx950, kite of 4096
 // elements: one Gauss point at a time is 6 % faster than two in FP64, equal
 // in FP32; four waves per SIMD no faster than two).
@@ -353,7 +353,7 @@ __device__ __forceinline__ cd end_value(const WaveConst& W, double xi, double yi
         const double r2 = dx * dx + dy * dy;
         double r;
         sqrt_rsqrt(r2, r, rinv);
-        h1 = hankel1_only<CPLX>(W, r, r2, rinv, rsqrt_nr(r));
+        h1 = hankel1_only<CPLX, true>(W, r, r2, rinv, rsqrt_nr(r));
     }
     return cscale(h1, (tix * dx + tiy * dy) * rinv);
 }
@@ -381,7 +381,7 @@ __device__ __forceinline__ void element_entries(const WaveConst& W, const BlockC
                 const double r2 = fma(rx, rx, ry * ry);
                 double r;
                 sqrt_rsqrt(r2, r, rinv);
-                hankel01<CPLX>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
+                hankel01<CPLX, true>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
             }
             sS.re = fma(P.w, h0.re, sS.re);
             sS.im = fma(P.w, h0.im, sS.im);
@@ -430,13 +430,13 @@ struct cf {
 __device__ __forceinline__ cf cmulf(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
 // H0, H1 at k r with r given in FP64; result in FP32.
-template <bool CPLX>
+template <bool CPLX, bool MEM = false>
 __device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveConst32& W, double r, cf& h0, cf& h1)
 {
     if (r * r < (double)W.r2_small) {
         const double r2 = r * r, rinv = 1.0 / r, sr = sqrt(rinv);
         cd a0, a1;
-        hankel01<CPLX>(W64, r, r2, rinv, sr, a0, a1);
+        hankel01<CPLX, MEM>(W64, r, r2, rinv, sr, a0, a1);
         h0 = {(float)a0.re, (float)a0.im};
         h1 = {(float)a1.re, (float)a1.im};
         return;
@@ -557,7 +557,7 @@ __device__ __forceinline__ cf end_value32(const WaveConst& W64, const WaveConst3
         rinv = hankel01_far32<CPLX, false>(W64, W, dx, dy, h0, h1);
     } else {
         const double r = sqrt(dx * dx + dy * dy);
-        hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+        hankel01_mixed<CPLX, true>(W64, W, r, h0, h1);
         rinv = 1.0 / r;
     }
     const float f = (float)((tix * dx + tiy * dy) * rinv);
@@ -587,7 +587,7 @@ __device__ __forceinline__ void element_entries_f32(const WaveConst& W64, const 
                 ri = hankel01_far32<CPLX, true>(W64, W, rx, ry, h0, h1);
             } else {
                 const double r = sqrt(fma(rx, rx, ry * ry));
-                hankel01_mixed<CPLX>(W64, W, r, h0, h1);
+                hankel01_mixed<CPLX, true>(W64, W, r, h0, h1);
                 ri = (float)(1.0 / r);
             }
             const float wg = (float)P.w;
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f64(const 
 }
 
 template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, 1) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
+__global__ __launch_bounds__(ROW_TILE, 2) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
                                                                    int n_if, int q_rt, const int* __restrict__ pairs,
                                                                    int side, double2* __restrict__ A, size_t lda,
                                                                    float2* __restrict__ A32, size_t lda32)
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f32(const 
 }
 
 template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, 1) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
+__global__ __launch_bounds__(ROW_TILE, 2) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
                                                                    int n_if, int q_rt, const int* __restrict__ pairs,
                                                                    int side, float2* __restrict__ A, size_t lda)
 {

@@ -32,32 +32,69 @@ __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.
 __device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
 
-// sum_m c[m] x^m, x real
-template <int N, class T>
-__device__ __forceinline__ T poly_real(const T (&c)[N], T x)
+// sum_m c[m] x^m, x real (c: an array of N coefficients, in any address space)
+template <int N, class C, class T>
+__device__ __forceinline__ T poly_n(const C& c, T x)
 {
     T acc = c[N - 1];
 #pragma unroll
-    for (int m = N - 2; m >= 0; --m) acc = fma(acc, x, c[m]);
+    for (int m = N - 2; m >= 0; --m) acc = fma(acc, x, (T)c[m]);
     return acc;
+}
+template <int N, class T>
+__device__ __forceinline__ T poly_real(const T (&c)[N], T x)
+{
+    return poly_n<N>(c, x);
 }
 
 // sum_m c[m] z^m at complex z = x + i y for real c: with R = 2x, S = |z|^2,
 // b_{N-1} = c_{N-1}, b_{N-2} = c_{N-2} + R b_{N-1}, b_m = c_m + R b_{m+1} - S b_{m+2},
 // p(z) = (x b_1 + c_0 - S b_2) + i y b_1.   (N >= 3)
-template <int N, class T>
-__device__ __forceinline__ void poly_cplx(const T (&c)[N], T x, T y, T R, T S, T& pr, T& pi)
+template <int N, class C, class T>
+__device__ __forceinline__ void poly_cplx_n(const C& c, T x, T y, T R, T S, T& pr, T& pi)
 {
     T b2 = c[N - 1];
-    T b1 = fma(R, b2, c[N - 2]);
+    T b1 = fma(R, b2, (T)c[N - 2]);
 #pragma unroll
     for (int m = N - 3; m >= 1; --m) {
-        const T b0 = fma(R, b1, fma(-S, b2, c[m]));
+        const T b0 = fma(R, b1, fma(-S, b2, (T)c[m]));
         b2 = b1;
         b1 = b0;
     }
-    pr = fma(x, b1, fma(-S, b2, c[0]));
+    pr = fma(x, b1, fma(-S, b2, (T)c[0]));
     pi = y * b1;
+}
+template <int N, class T>
+__device__ __forceinline__ void poly_cplx(const T (&c)[N], T x, T y, T R, T S, T& pr, T& pi)
+{
+    poly_cplx_n<N>(c, x, y, R, S, pr, pi);
+}
+
+// The ascending-series coefficients as one object in device memory.  The
+// general evaluator can read them through a pointer the compiler must reload
+// on each call (scalar loads, nothing held in registers across a loop), for
+// paths that run rarely and would otherwise keep 88 coefficients resident.
+struct HankelTabs {
+    double j0[SERIES_NC], e0[SERIES_NC], j1[SERIES_NC], e1[SERIES_NC];
+};
+constexpr HankelTabs make_hankel_tabs()
+{
+    HankelTabs t{};
+    for (int m = 0; m < SERIES_NC; ++m) {
+        t.j0[m] = SERIES_J0[m];
+        t.e0[m] = SERIES_E0[m];
+        t.j1[m] = SERIES_J1[m];
+        t.e1[m] = SERIES_E1[m];
+    }
+    return t;
+}
+static __device__ const HankelTabs g_hankel_tabs = make_hankel_tabs();
+typedef const __attribute__((address_space(4))) HankelTabs* HankelTabsPtr;
+__device__ __forceinline__ HankelTabsPtr hankel_tabs_fresh()
+{
+    HankelTabsPtr t = (HankelTabsPtr)&g_hankel_tabs;
+    asm volatile("" : "+s"(t));  // opaque: loads through t are not hoisted out of loops
+    return t;
 }
 
 // sum_m c[m] w^m from shared powers p[m] = w^m (p[0] unused), highest degree
@@ -73,90 +110,16 @@ __device__ __forceinline__ T poly_pow(const T (&c)[N], const T (&p)[N])
     return acc + c[0];
 }
 
-// H0(k r), H1(k r).  r2 = r^2, rinv = 1/r, srinv = r^{-1/2}.
-template <bool CPLX>
-__device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2, double rinv, double srinv, cd& h0,
-                                         cd& h1)
-{
-    constexpr double TWO_OVER_PI = 0.63661977236758134308;
-    constexpr double EULER = 0.57721566490153286061;
-    if (r2 < W.r2_small) {
-        const double lnr = log(r);
-        if (!CPLX) {
-            const double t = W.tr * r2;
-            const double j0 = poly_real(SERIES_J0, t);
-            const double e0 = poly_real(SERIES_E0, t);
-            const double zh = W.hr * r;
-            const double j1 = zh * poly_real(SERIES_J1, t);
-            const double e1 = poly_real(SERIES_E1, t);
-            const double lz = lnr + W.lkr;
-            const double y0 = fma(TWO_OVER_PI * (lz + EULER), j0, e0);
-            const double y1 = fma(W.y1r, rinv, fma(TWO_OVER_PI * lz, j1, zh * e1));
-            h0 = {j0, y0};
-            h1 = {j1, y1};
-        } else {
-            const double x = W.tr * r2, y = W.ti * r2;
-            const double R = 2.0 * x, S = fma(x, x, y * y);
-            cd j0, e0, p1, e1;
-            poly_cplx(SERIES_J0, x, y, R, S, j0.re, j0.im);
-            poly_cplx(SERIES_E0, x, y, R, S, e0.re, e0.im);
-            poly_cplx(SERIES_J1, x, y, R, S, p1.re, p1.im);
-            poly_cplx(SERIES_E1, x, y, R, S, e1.re, e1.im);
-            const cd zh = {W.hr * r, W.hi * r};
-            const cd j1 = cmul(zh, p1);
-            const cd lz = {lnr + W.lkr, W.lki};
-            const cd y0 = cadd(cmul({TWO_OVER_PI * (lz.re + EULER), TWO_OVER_PI * lz.im}, j0), e0);
-            const cd y1 = cadd(cadd(cscale({W.y1r, W.y1i}, rinv), cmul(cscale(lz, TWO_OVER_PI), j1)), cmul(zh, e1));
-            h0 = {j0.re - y0.im, j0.im + y0.re};
-            h1 = {j1.re - y1.im, j1.im + y1.re};
-        }
-    } else {
-        const double rho = rinv * rinv;
-        double sn, cs;
-        sincos_cw(W.kr * r, sn, cs);
-        if (!CPLX) {
-            const double w = W.wr * rho;
-            const double m0 = poly_real(HANKEL_M0_F64, w), n0 = poly_real(HANKEL_N0_F64, w);
-            const double m1 = poly_real(HANKEL_M1_F64, w), n1 = poly_real(HANKEL_N1_F64, w);
-            const double u = W.ur * rinv;
-            const cd e = {cs * srinv, sn * srinv};
-            h0 = cmul(cmul(e, {W.a0r, W.a0i}), {m0, u * n0});
-            h1 = cmul(cmul(e, {W.a1r, W.a1i}), {m1, u * n1});
-        } else {
-            const double x = W.wr * rho, y = W.wi * rho;
-            const double R = 2.0 * x, S = fma(x, x, y * y);
-            cd m0, n0, m1, n1;
-            poly_cplx(HANKEL_M0_F64, x, y, R, S, m0.re, m0.im);
-            poly_cplx(HANKEL_N0_F64, x, y, R, S, n0.re, n0.im);
-            poly_cplx(HANKEL_M1_F64, x, y, R, S, m1.re, m1.im);
-            poly_cplx(HANKEL_N1_F64, x, y, R, S, n1.re, n1.im);
-            const cd u = {W.ur * rinv, W.ui * rinv};
-            const cd un0 = cmul(u, n0), un1 = cmul(u, n1);
-            const cd p0 = {m0.re - un0.im, m0.im + un0.re};
-            const cd p1 = {m1.re - un1.im, m1.im + un1.re};
-            const double damp = exp(-W.ki * r) * srinv;
-            const cd e = {cs * damp, sn * damp};
-            h0 = cmul(cmul(e, {W.a0r, W.a0i}), p0);
-            h1 = cmul(cmul(e, {W.a1r, W.a1i}), p1);
-        }
-    }
-}
-
-// H0(k r) and H1(k r) when |k r| >= XS is known for the pair (no per-lane
-// branch, no series), from the offset (rx, ry) = x - y; returns 1/r.  The
-// phase phi = Re(k) r - pi/4 is reduced once for both orders:
+// Large-argument form for |k r| >= XS, from r, 1/r and r^{-1/2}.  The phase
+// phi = Re(k) r - pi/4 is reduced once for both orders:
 //   H0 = A r^{-1/2} e^{i phi} (m0 + i u n0),
 //   H1 = A r^{-1/2} e^{i phi} (-i) (m1 + i u n1),   u = XS/(k r),
 // A = sqrt(2/(pi k)), times e^{-Im(k) r} for complex k.  H0 is skipped when
 // only H1 is wanted.
 template <bool CPLX, bool WANT_H0>
-__device__ __forceinline__ double hankel01_far(const WaveConst& W, double rx, double ry, cd& h0, cd& h1)
+__device__ __forceinline__ void hankel_asym(const WaveConst& W, double r, double rinv, double sr, cd& h0, cd& h1)
 {
     constexpr double PI_4 = 0x1.921fb54442d18p-1;
-    const double r2 = fma(rx, rx, ry * ry);
-    double r, rinv;
-    sqrt_rsqrt(r2, r, rinv);
-    const double sr = rsqrt_nr(r);
     double sn, cs;
     sincos_cw(fma(W.kr, r, -PI_4), sn, cs);
     const double rho = rinv * rinv;
@@ -194,15 +157,84 @@ __device__ __forceinline__ double hankel01_far(const WaveConst& W, double rx, do
             h0 = cmul(e, {m0.re - un0.im, m0.im + un0.re});
         }
     }
+}
+
+// H0(k r) and H1(k r) when |k r| >= XS is known for the pair (no per-lane
+// branch, no series), from the offset (rx, ry) = x - y; returns 1/r.
+template <bool CPLX, bool WANT_H0>
+__device__ __forceinline__ double hankel01_far(const WaveConst& W, double rx, double ry, cd& h0, cd& h1)
+{
+    const double r2 = fma(rx, rx, ry * ry);
+    double r, rinv;
+    sqrt_rsqrt(r2, r, rinv);
+    hankel_asym<CPLX, WANT_H0>(W, r, rinv, rsqrt_nr(r), h0, h1);
     return rinv;
 }
 
+// H0(k r), H1(k r).  r2 = r^2, rinv = 1/r, srinv = r^{-1/2}.  Below XS the
+// ascending series (MEM: its coefficients from g_hankel_tabs by scalar loads
+// instead of immediates), above it hankel_asym.
+template <bool CPLX, bool MEM = false>
+__device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2, double rinv, double srinv, cd& h0,
+                                         cd& h1)
+{
+    HankelTabsPtr T = nullptr;
+    if (MEM) T = hankel_tabs_fresh();
+    constexpr double TWO_OVER_PI = 0.63661977236758134308;
+    constexpr double EULER = 0.57721566490153286061;
+    if (r2 < W.r2_small) {
+        const double lnr = log(r);
+        if (!CPLX) {
+            const double t = W.tr * r2;
+            const double j0 = MEM ? poly_n<SERIES_NC>(T->j0, t) : poly_real(SERIES_J0, t);
+            const double e0 = MEM ? poly_n<SERIES_NC>(T->e0, t) : poly_real(SERIES_E0, t);
+            const double zh = W.hr * r;
+            const double j1 = zh * (MEM ? poly_n<SERIES_NC>(T->j1, t) : poly_real(SERIES_J1, t));
+            const double e1 = MEM ? poly_n<SERIES_NC>(T->e1, t) : poly_real(SERIES_E1, t);
+            const double lz = lnr + W.lkr;
+            const double y0 = fma(TWO_OVER_PI * (lz + EULER), j0, e0);
+            const double y1 = fma(W.y1r, rinv, fma(TWO_OVER_PI * lz, j1, zh * e1));
+            h0 = {j0, y0};
+            h1 = {j1, y1};
+        } else {
+            const double x = W.tr * r2, y = W.ti * r2;
+            const double R = 2.0 * x, S = fma(x, x, y * y);
+            cd j0, e0, p1, e1;
+            if (MEM)
+                poly_cplx_n<SERIES_NC>(T->j0, x, y, R, S, j0.re, j0.im);
+            else
+                poly_cplx(SERIES_J0, x, y, R, S, j0.re, j0.im);
+            if (MEM)
+                poly_cplx_n<SERIES_NC>(T->e0, x, y, R, S, e0.re, e0.im);
+            else
+                poly_cplx(SERIES_E0, x, y, R, S, e0.re, e0.im);
+            if (MEM)
+                poly_cplx_n<SERIES_NC>(T->j1, x, y, R, S, p1.re, p1.im);
+            else
+                poly_cplx(SERIES_J1, x, y, R, S, p1.re, p1.im);
+            if (MEM)
+                poly_cplx_n<SERIES_NC>(T->e1, x, y, R, S, e1.re, e1.im);
+            else
+                poly_cplx(SERIES_E1, x, y, R, S, e1.re, e1.im);
+            const cd zh = {W.hr * r, W.hi * r};
+            const cd j1 = cmul(zh, p1);
+            const cd lz = {lnr + W.lkr, W.lki};
+            const cd y0 = cadd(cmul({TWO_OVER_PI * (lz.re + EULER), TWO_OVER_PI * lz.im}, j0), e0);
+            const cd y1 = cadd(cadd(cscale({W.y1r, W.y1i}, rinv), cmul(cscale(lz, TWO_OVER_PI), j1)), cmul(zh, e1));
+            h0 = {j0.re - y0.im, j0.im + y0.re};
+            h1 = {j1.re - y1.im, j1.im + y1.re};
+        }
+    } else {
+        hankel_asym<CPLX, true>(W, r, rinv, srinv, h0, h1);
+    }
+}
+
 // H1 only (end-point terms of the hypersingular operator).
-template <bool CPLX>
+template <bool CPLX, bool MEM = false>
 __device__ __forceinline__ cd hankel1_only(const WaveConst& W, double r, double r2, double rinv, double srinv)
 {
     cd h0, h1;
-    hankel01<CPLX>(W, r, r2, rinv, srinv, h0, h1);
+    hankel01<CPLX, MEM>(W, r, r2, rinv, srinv, h0, h1);
     return h1;
 }
 
