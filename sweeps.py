@@ -13,6 +13,9 @@ Experiments (Sec. 7; omega = k0, k_d = omega sqrt(eps_d), eps_1 = 1):
   split_N       disk split by its vertical diameter (two triple points), 3N/4 + N/4 elements, omega = 1
   split_omega   split disk, N = 1066, eps = 1, 2, 3, omega sweep
   split_eps     split disk, N = 1066, omega = 5, eps2 = 1/eps3 sweep
+  spectra       eigenvalues of A^2 (Sec. 5 and 7.2): unit disk, N = 100, omega = 1,
+                eps2 = 2 (beta = -alpha, beta = 1, conventional); concentric disks,
+                200 + 100 elements, omega = 1 (modified, original, conventional)
 
 Single material: conventional (eq. (naive_bie)), Calderon beta = 1
 (eq. (calderon_bie1)) and beta = -alpha (eq. (calderon_bieb)).  Several
@@ -115,13 +118,57 @@ def split_eps(eps3=(0.25, 0.5, 1.5, 2.0, 4.0, 6.0, 8.0, 10.0), N=1066, omega=5.0
     return _sweep("split_eps", eps3, lambda e, f: _split(N, omega, 1.0 / e, e, f), MULTI_FORMS, "eps3")
 
 
+def _gpu_matrix(spec):
+    """The matrix assembled on the GPU (FP64), as a numpy (n, n) array."""
+    import paper_2312_12787_amd as P
+    g = P.Problem(spec)
+    A = g.assemble(P.F64)
+    return A.T.cpu().numpy()
+
+
+def spectra(N=100, n_outer=200, n_inner=100, omega=1.0):
+    """Eigenvalues of A^2 of GPU-assembled matrices (numpy.linalg.eigvals on
+    the host): per form, the largest magnitude, the spread, and for the
+    single-material beta = -alpha form the share within 0.2 of its predicted
+    accumulation point alpha^2 (1 + eps2)/4 = -3/4 (eq. (A_-alpha^2))."""
+    import workloads as W
+    t0 = time.perf_counter()
+    rows = []
+    eps2 = 2.0
+    alpha = -1j / omega
+    single = {"calderon_beta_minus_alpha": W.CALDERON, "calderon_beta1": W.CALDERON_BETA1,
+              "conventional": W.CONVENTIONAL}
+    for name, form in single.items():
+        A = _gpu_matrix(W.disk(N, omega, omega * np.sqrt(eps2), form=form))
+        ev = np.linalg.eigvals(A @ A)
+        row = {"case": "single", "form": name, "n": A.shape[0], "max_abs": float(np.abs(ev).max()),
+               "largest": [float(ev[np.argmax(np.abs(ev))].real), float(ev[np.argmax(np.abs(ev))].imag)]}
+        if form == W.CALDERON:
+            pred = alpha ** 2 * (1 + eps2) / 4
+            row["share_within_0.2_of_pred"] = float(np.mean(np.abs(ev - pred) < 0.2))
+            row["predicted_point"] = [pred.real, pred.imag]
+        rows.append(row)
+        print(f"spectra: {row}", file=sys.stderr, flush=True)
+    k = [omega, omega * np.sqrt(2.0), omega * np.sqrt(3.0)]
+    multi = {"modified": W.CALDERON, "original": W.CALDERON_ORIG, "conventional": W.CONVENTIONAL}
+    for name, form in multi.items():
+        A = _gpu_matrix(W.concentric(n_outer, n_inner, k, form=form))
+        ev = np.linalg.eigvals(A @ A)
+        lam = ev[np.argmax(np.abs(ev))]
+        row = {"case": "concentric", "form": name, "n": A.shape[0], "max_abs": float(np.abs(ev).max()),
+               "largest": [float(lam.real), float(lam.imag)], "min_abs": float(np.abs(ev).min())}
+        rows.append(row)
+        print(f"spectra: {row}", file=sys.stderr, flush=True)
+    return {"experiment": "spectra", "parameter": "form", "rows": rows, "seconds": time.perf_counter() - t0}
+
+
 EXPERIMENTS = {f.__name__: f for f in (single_N, single_omega, single_eps, conc_N, conc_omega, conc_eps, split_N,
-                                       split_omega, split_eps)}
+                                       split_omega, split_eps, spectra)}
 QUICK = {"single_N": dict(Ns=(100, 200, 400, 800)), "single_omega": dict(omegas=(1.0, 3.0, 5.0, 7.0, 9.0)),
          "single_eps": dict(eps=(2.0, 4.0, 8.0)), "conc_N": dict(Ns=(150, 300, 600)),
          "conc_omega": dict(omegas=(2.0, 5.0, 8.0)), "conc_eps": dict(eps3=(0.5, 2.0, 8.0)),
          "split_N": dict(Ns=(200, 400, 800)), "split_omega": dict(omegas=(2.0, 5.0, 8.0)),
-         "split_eps": dict(eps3=(0.5, 2.0, 8.0))}
+         "split_eps": dict(eps3=(0.5, 2.0, 8.0)), "spectra": {}}
 
 
 def main():
