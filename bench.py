@@ -343,6 +343,51 @@ def serve_mode(args, P, torch):
     print(json.dumps(out), flush=True)
 
 
+def nearfield_mode(args, P, torch):
+    """The near field of Sec. 7.1's accuracy measure: unit disk (inscribed
+    N-gon), omega = 5, eps2 = 2, solved on the GPU (FP64, GMRES to 1e-10),
+    then --steps evaluations of the total field on the 101 x 101 grid of
+    [-2.99, 2.99]^2 (bem_nearfield; points and domains resident on the
+    device), timed with events on the launch stream."""
+    import workloads as W
+    n_el = args.nf_elements
+    spec = W.disk(n_el, 5.0, 5.0 * np.sqrt(2.0))
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    X, info = g.solve(g.rhs([0.0]), restart=100, tol=1e-10)
+    t = np.linspace(-2.99, 2.99, 101)
+    xx, yy = np.meshgrid(t, t, indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    dom = (np.hypot(pts[:, 0], pts[:, 1]) < 1.0).astype(np.int32)
+    pts_t = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    dom_t = torch.as_tensor(dom, dtype=torch.int32, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        g.nearfield(X, pts_t, dom_t, [0.0])
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        U = g.nearfield(X, pts_t, dom_t, [0.0])
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    npts, q = len(pts), spec.quad
+    pairs = npts * n_el
+    out = {"mode": "nearfield", "workload": f"disk{n_el}_k5-7.07_grid101", "points": npts, "elements": n_el,
+           "gmres_iterations": int(info.iters[0]), "calls": args.steps, "avg_ms": ms,
+           "point_element_pairs_per_s": pairs / (ms * 1e-3),
+           "evals_per_s": pairs * q / (ms * 1e-3),
+           "timing": "events on the launch stream around --steps bem_nearfield calls (one launch per domain each)"}
+    rec = counter_record("nearfield_flops", out["workload"])
+    if rec:
+        fl = rec["flops_per_call"]
+        out.update({"flops_per_call": fl, "TFLOP_per_s": fl / (ms * 1e-3) / 1e12,
+                    "frac_of_valu_peak": fl / (ms * 1e-3) / VALU_PEAK_FLOPS})
+    print(json.dumps(out), flush=True)
+    del U
+
+
 def assemble_mode(args, wl, P, torch, prec):
     """Only assemblies: every case of the workload --steps times (after
     --warmup), timed with the library's HIP events (for hardware-counter runs
@@ -388,7 +433,8 @@ def main():
     ap.add_argument("--tune-file", default=None,
                     help="launch-shape table: imported if the file exists, else written after tuning "
                          "(so that profiling runs use the same shapes)")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble"],
+    ap.add_argument("--nf-elements", type=int, default=1024, help="nearfield mode: elements of the disk")
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble", "nearfield"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
                          "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
                          "assemble: only --steps assemblies of every case")
@@ -414,6 +460,8 @@ def main():
         return matvec_mode(args, wl, P, torch, prec)
     if args.mode == "assemble":
         return assemble_mode(args, wl, P, torch, prec)
+    if args.mode == "nearfield":
+        return nearfield_mode(args, P, torch)
     dirs = wl.far_dirs
     probs, mats = [], []
     nr = len(wl.angles)

@@ -15,9 +15,12 @@
 // perpendicular from x.
 //
 // Layout: points xy[2 p], xy[2 p + 1], domain dom[p]; X column-major [u; w]
-// per right-hand side (ldx); U column-major, point fastest (ldu).  One lane per
-// point; one launch per domain (uniform wavenumber and Hankel constants); the
-// source elements are walked in order with wave-uniform data.
+// per right-hand side (ldx); U column-major, point fastest (ldu).  One wave
+// per point: its 64 lanes take every 64th source element of each interface
+// and a fixed-order butterfly adds their sums (a 101 x 101 grid is ~2550
+// workgroups of four points, enough to fill the chip).  One launch per domain
+// (uniform wavenumber and Hankel constants); points of other domains return
+// at once, wave-uniformly.
 #include <hip/hip_runtime.h>
 
 #include "hankel_dev.h"
@@ -78,9 +81,10 @@ __device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, cons
         for (int g = 0; g < q; ++g) {
             const double rx = x - G.x[g], ry = y - G.y[g];
             const double r2 = fma(rx, rx, ry * ry);
-            const double r = sqrt(r2), rinv = 1.0 / r;
+            double r, rinv;
+            sqrt_rsqrt(r2, r, rinv);
             cd h0, h1;
-            hankel01<CPLX>(W, r, r2, rinv, sqrt(rinv), h0, h1);
+            hankel01<CPLX, true>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
             const double wg = G.w[g];
             S.re = fma(wg, h0.re, S.re);
             S.im = fma(wg, h0.im, S.im);
@@ -115,9 +119,10 @@ __device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, cons
             const double s = fma(half, gl[g], mid);
             const double u = xt - s;  // (x - y).t
             const double r2 = fma(u, u, xn * xn);
-            const double r = sqrt(r2), rinv = 1.0 / r;
+            double r, rinv;
+            sqrt_rsqrt(r2, r, rinv);
             cd h0, h1;
-            hankel01<CPLX>(W, r, r2, rinv, sqrt(rinv), h0, h1);
+            hankel01<CPLX, true>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
             const double wg = half * gl[QMAX + g];
             // (i/4) H0 + (1/2pi) ln r - (k^2 / 8 pi) r^2 ln r
             const double lnr = log(r);
@@ -136,16 +141,26 @@ __device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, cons
     D = {dr.re + DL + DLog.re, dr.im + DLog.im};
 }
 
+// sum over the wave's 64 lanes in a fixed butterfly order (every lane ends
+// with the same value)
+__device__ __forceinline__ double wave_add(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <bool CPLX>
-__global__ __launch_bounds__(NF_BS) void k_nearfield(const char* __restrict__ g, GeomLayout L, int n_if, int N, int q,
+__global__ __launch_bounds__(NF_BS, 2) void k_nearfield(const char* __restrict__ g, GeomLayout L, int n_if, int N, int q,
                                                    int d,
                                                    const double2* __restrict__ X, size_t ldx, int nr,
                                                    NearAngles ang, int add_incident, const double* __restrict__ xy,
                                                    const int* __restrict__ dom, int npts, double2* __restrict__ U,
                                                    size_t ldu)
 {
-    const int p = blockIdx.x * NF_BS + threadIdx.x;
-    if (p >= npts || dom[p] != d) return;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (NF_BS / 64) + (threadIdx.x >> 6);
+    if (p >= npts || dom[p] != d) return;  // uniform over the wave
     const double x = xy[2 * (size_t)p], y = xy[2 * (size_t)p + 1];
     const WaveConst W = tab<WaveConst>(g, L.wave)[d];
     const DomConst Dm = tab<DomConst>(g, L.dom)[d];
@@ -161,7 +176,7 @@ __global__ __launch_bounds__(NF_BS) void k_nearfield(const char* __restrict__ g,
         const int sg = tab<int>(g, L.sigma)[d * n_if + m];
         if (sg == 0) continue;
         const IfacePlan P = tab<IfacePlan>(g, L.iface)[m];
-        for (int e = 0; e < P.count; ++e) {
+        for (int e = lane; e < P.count; e += 64) {
             const int j = P.off + e;
             cd S, D;
             element_integrals<CPLX>(W, k, el[j], gq[j], gl, q, x, y, S, D);
@@ -180,7 +195,7 @@ __global__ __launch_bounds__(NF_BS) void k_nearfield(const char* __restrict__ g,
 #pragma unroll
     for (int r = 0; r < NF_RB; ++r) {
         if (r >= nr) continue;
-        cd v = acc[r];
+        cd v = {wave_add(acc[r].re), wave_add(acc[r].im)};
         if (d == 0 && add_incident) {
             double sn, cs;
             sincos(ang.v[r], &sn, &cs);
@@ -189,7 +204,7 @@ __global__ __launch_bounds__(NF_BS) void k_nearfield(const char* __restrict__ g,
             v.re += pc;
             v.im += ps;
         }
-        U[(size_t)r * ldu + p] = make_double2(v.re, v.im);
+        if (lane == 0) U[(size_t)r * ldu + p] = make_double2(v.re, v.im);
     }
 }
 
@@ -199,7 +214,7 @@ hipError_t launch_nearfield(const char* g, const GeomLayout& L, int n_if, int n_
                             const double2* X, size_t ldx, int nrhs, const double* angles, const double* xy,
                             const int* dom, int npts, double2* U, size_t ldu, hipStream_t s)
 {
-    const dim3 grid((npts + NF_BS - 1) / NF_BS);
+    const dim3 grid((npts + NF_BS / 64 - 1) / (NF_BS / 64));  // one wave per point
     for (int r0 = 0; r0 < nrhs; r0 += NF_RB) {
         const int nr = nrhs - r0 < NF_RB ? nrhs - r0 : NF_RB;
         NearAngles ang{};
