@@ -38,6 +38,18 @@ constexpr int MV_CH = 32;      // X columns staged in LDS per step (VALU kernel)
 // in split order by k_matvec_reduce.  TA / TX: storage types (double2 or
 // float2); ACC: accumulation type.
 // ---------------------------------------------------------------------------
+// The matrix is streamed once per product and is larger than the caches:
+// non-temporal loads keep it from displacing the reused X blocks (measured on
+// gfx950: 2.7 % faster FP64 products at n = 8192, 16 right-hand sides).
+template <class TA>
+__device__ __forceinline__ TA ld_stream(const TA* p)
+{
+    TA v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    return v;
+}
+
 template <int NR, class TA, class TX, class ACC>
 __global__ __launch_bounds__(BS) void k_matvec(const TA* __restrict__ A, size_t lda, int n,
                                                const TX* __restrict__ X, size_t ldx, int nrhs,
@@ -73,7 +85,7 @@ __global__ __launch_bounds__(BS) void k_matvec(const TA* __restrict__ A, size_t 
             if (nc == MV_CH) {
 #pragma unroll 8
                 for (int c = 0; c < MV_CH; ++c) {
-                    const TA a = ap[(size_t)c * lda];
+                    const TA a = ld_stream(ap + (size_t)c * lda);
                     const S axr = (S)a.x, axi = (S)a.y;
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
@@ -86,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_matvec(const TA* __restrict__ A, size_t 
                 }
             } else {
                 for (int c = 0; c < nc; ++c) {
-                    const TA a = ap[(size_t)c * lda];
+                    const TA a = ld_stream(ap + (size_t)c * lda);
                     const S axr = (S)a.x, axi = (S)a.y;
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
 #pragma unroll
             for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
 #pragma unroll
-            for (int t = 0; t < RT; ++t) a[u][t] = ap[t][(size_t)col * lda];
+            for (int t = 0; t < RT; ++t) a[u][t] = ld_stream(ap[t] + (size_t)col * lda);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -274,7 +286,7 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
             ar[t] = T(0);
             ai[t] = T(0);
             if (ok && rok[t]) {
-                const TA a = ap[t][(size_t)col * lda];
+                const TA a = ld_stream(ap[t] + (size_t)col * lda);
                 ar[t] = (T)a.x;
                 ai[t] = (T)a.y;
             }
