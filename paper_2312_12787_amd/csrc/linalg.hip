@@ -282,6 +282,7 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
     double2* T = tc + (size_t)r * (m + 1);
     for (int i = lane; i < jc; i += 64) {
         double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll 8
         for (int b = 0; b < ns; ++b) {
             const size_t o = ((size_t)r * ns + b) * jc + i;
             const double2 p = partP[o];
@@ -340,14 +341,19 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
         __syncthreads();
         if (lane == 0) {
             const int c0 = j - 1;
+            // the previous rotations in order; the running entry stays in
+            // registers, so only the loads (independent of the chain) touch LDS
+            double2 hi = col[0];
+#pragma unroll 4
             for (int i = 0; i < c0; ++i) {
-                const double2 hi = col[i], hn = col[i + 1];
+                const double2 hn = col[i + 1];
                 const double2 ci = lc[i], si = ls[i];
                 col[i] = make_double2(ci.x * hi.x - ci.y * hi.y + si.x * hn.x - si.y * hn.y,
                                       ci.x * hi.y + ci.y * hi.x + si.x * hn.y + si.y * hn.x);
-                col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
-                                          -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
+                hi = make_double2(-(si.x * hi.x + si.y * hi.y) + (ci.x * hn.x + ci.y * hn.y),
+                                  -(si.x * hi.y - si.y * hi.x) + (ci.x * hn.y - ci.y * hn.x));
             }
+            col[c0] = hi;
             const double2 a = col[c0], b = col[c0 + 1];
             const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
             const double rho = hypot(na, nb);
@@ -401,6 +407,7 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
     for (int i = lane; i <= j; i += 64) {
         // z_i = sum_l H[i, l] s_l over the Hessenberg band l >= i - 1
         double zr = 0.0, zi = 0.0;
+#pragma unroll 8
         for (int l = max(i - 1, 0); l < j; ++l) {
             const double2 h = Hr[(size_t)l * (m + 1) + i];
             const double2 a = S[l];
