@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFS = 157.3
-VALU_PEAK_FLOPS = 78.6e12  # FP64 vector; also FP32 vector without packed FP32 (disabled in this build)
+VALU_PEAK_FLOPS = 78.6e12  # FP64 vector; also FP32 vector without packed FP32 (the kernels are compiled without it)
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. err vs FP64; assembly FLOP/s, matvec GB/s"
 
 
@@ -440,8 +440,8 @@ def main():
                          "assemble: only --steps assemblies of every case")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU only; run with --gpus 1 "
+              "(the library has no multi-GPU path: sharding by row blocks is a design, not code)", file=sys.stderr)
         sys.exit(2)
 
     import torch

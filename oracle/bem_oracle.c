@@ -4,7 +4,7 @@
  * formulation of the 2-D Helmholtz transmission problem).
  *
  * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
- * CPU-baseline leg of the benchmark to judge the HIP path.  It shares no code
+ * CPU-baseline leg of the benchmark to check the HIP path.  It shares no code
  * with the product library.  Everything is written for readability; nothing
  * is blocked, fused or reordered beyond the definitions cited at each step.
  *
