@@ -80,3 +80,26 @@ def test_solves_after_tuning_match_the_oracle():
         assert e64 < 1e-10 and em < 1e-6
     finally:
         P.tune_reset()
+
+
+@pytest.mark.parametrize("nrhs", [64, 3])
+def test_tuned_fp32_products_equal_builtin_products(nrhs):
+    """FP32 matrix: the class of FP32 products (FP32 matrix and sums) is tuned
+    by bem_tune on the solve's product (FP64 vectors) and then used by
+    bem_matvec's FP32 products as well; only the split-K summation order
+    changes, so the products agree to FP32 rounding (1e-5 relative in the
+    2-norm, entries of both signs)."""
+    P = _gpu()
+    try:
+        g = P.Problem(W.kite(1500, 8.0, 12.0))
+        g.assemble(P.F32)
+        X = _x(nrhs, g.n, 11).to(torch.complex64)
+        Y0 = g.matvec(X).cpu().numpy().astype(np.complex128)
+        info = g.tune(nrhs, reps=2)
+        print("tuned FP32", nrhs, info, flush=True)
+        t = [int(v) for v in P.tune_export().strip().splitlines()[1].split()]
+        assert t[0] == 0 and t[3:] == [info["rt"], info["u"], info["splits"], info["g3"]]
+        Y1 = g.matvec(X).cpu().numpy().astype(np.complex128)
+        assert _rel(Y1, Y0) < 1e-5
+    finally:
+        P.tune_reset()
