@@ -257,30 +257,43 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b)
 // kernel), complete column j-1 (Givens, residual, decision), form column j and
 // the update coefficients scal = {(gamma, 0), c}.  Hraw holds the Hessenberg
 // matrix as produced, H its rotated (triangular) form for the back-solve.
-__global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, const double2* __restrict__ partP,
-                                                const double2* __restrict__ partQ, double2* __restrict__ Hraw,
-                                                double2* __restrict__ H, double2* __restrict__ cs,
-                                                double2* __restrict__ sn, double2* __restrict__ gvec,
-                                                const double* __restrict__ hnorm, double2* __restrict__ sc,
-                                                double2* __restrict__ tc, double2* __restrict__ scal,
-                                                const double* __restrict__ thr, int maxit, int* __restrict__ iters,
-                                                int* __restrict__ kdim, int* __restrict__ active,
-                                                int* __restrict__ flags_out)
+constexpr int DC_STEP_BS = 256;  // threads per right-hand side in k_dc_step
+
+// sum over the workgroup in a fixed order: each wave's DPP sum, then waves 0..3
+__device__ __forceinline__ double block_sum4(double v, double* red, int slot)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[slot * 4 + (threadIdx.x >> 6)] = v;
+    __syncthreads();
+    return ((red[slot * 4] + red[slot * 4 + 1]) + red[slot * 4 + 2]) + red[slot * 4 + 3];
+}
+
+__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, int ns, const double2* __restrict__ partP,
+                                                        const double2* __restrict__ partQ, double2* __restrict__ Hraw,
+                                                        double2* __restrict__ H, double2* __restrict__ cs,
+                                                        double2* __restrict__ sn, double2* __restrict__ gvec,
+                                                        const double* __restrict__ hnorm, double2* __restrict__ sc,
+                                                        double2* __restrict__ tc, double2* __restrict__ scal,
+                                                        const double* __restrict__ thr, int maxit,
+                                                        int* __restrict__ iters, int* __restrict__ kdim,
+                                                        int* __restrict__ active, int* __restrict__ flags_out)
 {
     __shared__ double2 col[1024 + 1];
     __shared__ double2 lc[1024], ls[1024];
+    __shared__ double2 zp[4][64];
+    __shared__ double red[3 * 4];
     __shared__ int still_s;
     const int r = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (!active[r]) {
-        if (flags_out && lane == 0) flags_out[r] = 0;
+        if (flags_out && tid == 0) flags_out[r] = 0;
         return;
     }
     const int jc = j + 1;
     const bool hasw = partQ != nullptr;
     double2* S = sc + (size_t)r * (m + 1);
     double2* T = tc + (size_t)r * (m + 1);
-    for (int i = lane; i < jc; i += 64) {
+    for (int i = tid; i < jc; i += DC_STEP_BS) {
         double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
 #pragma unroll 8
         for (int b = 0; b < ns; ++b) {
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
     const double beta = j >= 1 ? hnorm[r] : 1.0;
     const bool brk = !(beta > 0.0);  // previous step ended the Krylov space
     double ss = 0.0, str = 0.0, sti = 0.0;
-    for (int i = lane; i < j; i += 64) {
+    for (int i = tid; i < j; i += DC_STEP_BS) {
         const double2 a = brk ? make_double2(0.0, 0.0) : S[i];
         ss = fma(a.x, a.x, fma(a.y, a.y, ss));
         if (hasw) {
@@ -310,16 +323,16 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
             sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
         }
     }
-    ss = wave_sum(ss);
-    str = wave_sum(str);
-    sti = wave_sum(sti);
+    ss = block_sum4(ss, red, 0);
+    str = block_sum4(str, red, 1);
+    sti = block_sum4(sti, red, 2);
     const double alpha = S[j].x;
     const double gamma = brk ? 0.0 : sqrt(fmax(alpha - ss, 0.0));
     int still = 1;
     if (j >= 1) {
         // complete column j - 1
         double2* Hc = Hraw + (size_t)r * (m + 1) * m + (size_t)(j - 1) * (m + 1);
-        for (int i = lane; i < j; i += 64) {
+        for (int i = tid; i < j; i += DC_STEP_BS) {
             double2 h = Hc[i];
             if (!brk) {
                 const double2 a = S[i];
@@ -329,17 +342,17 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
             Hc[i] = h;
             col[i] = h;
         }
-        for (int i = lane; i < j - 1; i += 64) {
+        for (int i = tid; i < j - 1; i += DC_STEP_BS) {
             lc[i] = cs[(size_t)r * m + i];
             ls[i] = sn[(size_t)r * m + i];
         }
-        if (lane == 0) {
+        if (tid == 0) {
             const double2 sub = make_double2(brk ? 0.0 : beta * gamma, 0.0);
             Hc[j] = sub;
             col[j] = sub;
         }
         __syncthreads();
-        if (lane == 0) {
+        if (tid == 0) {
             const int c0 = j - 1;
             // the previous rotations in order; the running entry stays in
             // registers, so only the loads (independent of the chain) touch LDS
@@ -390,13 +403,13 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
         __syncthreads();
         still = still_s;
         double2* Rc = H + (size_t)r * (m + 1) * m + (size_t)(j - 1) * (m + 1);
-        for (int i = lane; i <= j; i += 64) Rc[i] = col[i];
+        for (int i = tid; i <= j; i += DC_STEP_BS) Rc[i] = col[i];
     } else if (!(gamma > 0.0)) {
         still = 0;
-        if (lane == 0) active[r] = 0;
+        if (tid == 0) active[r] = 0;
     }
     if (j == m) still = 0;  // end of the cycle
-    if (flags_out && lane == 0) flags_out[r] = still;
+    if (flags_out && tid == 0) flags_out[r] = still;
     if (!still) return;
     // column j and the update coefficients
     const double2 tau = T[j];
@@ -404,20 +417,34 @@ __global__ __launch_bounds__(64) void k_dc_step(int nr, int j, int m, int ns, co
     const double2 c = make_double2((tau.x - str) * ig, (tau.y - sti) * ig);
     const double2* Hr = Hraw + (size_t)r * (m + 1) * m;
     double2* Hj = Hraw + (size_t)r * (m + 1) * m + (size_t)j * (m + 1);
-    for (int i = lane; i <= j; i += 64) {
-        // z_i = sum_l H[i, l] s_l over the Hessenberg band l >= i - 1
+    // z_i = sum_l H[i, l] s_l over the Hessenberg band l >= i - 1, rows in
+    // chunks of 64; wave w takes the columns l = w (mod 4), the four partial
+    // sums are added in wave order
+    for (int i0 = 0; i0 < jc; i0 += 64) {
+        const int i = i0 + lane;
         double zr = 0.0, zi = 0.0;
+        if (i < jc) {
+            const int l0 = max(i - 1, 0);
+            const int first = l0 + ((wv - l0) % 4 + 4) % 4;
 #pragma unroll 8
-        for (int l = max(i - 1, 0); l < j; ++l) {
-            const double2 h = Hr[(size_t)l * (m + 1) + i];
-            const double2 a = S[l];
-            zr += h.x * a.x - h.y * a.y;
-            zi += h.x * a.y + h.y * a.x;
+            for (int l = first; l < j; l += 4) {
+                const double2 h = Hr[(size_t)l * (m + 1) + i];
+                const double2 a = S[l];
+                zr += h.x * a.x - h.y * a.y;
+                zi += h.x * a.y + h.y * a.x;
+            }
         }
-        const double2 base = i < j ? T[i] : c;
-        Hj[i] = make_double2((base.x - zr) * ig, (base.y - zi) * ig);
+        zp[wv][lane] = make_double2(zr, zi);
+        __syncthreads();
+        if (wv == 0 && i < jc) {
+            const double zx = ((zp[0][lane].x + zp[1][lane].x) + zp[2][lane].x) + zp[3][lane].x;
+            const double zy = ((zp[0][lane].y + zp[1][lane].y) + zp[2][lane].y) + zp[3][lane].y;
+            const double2 base = i < j ? T[i] : c;
+            Hj[i] = make_double2((base.x - zx) * ig, (base.y - zy) * ig);
+        }
+        __syncthreads();
     }
-    if (lane == 0) {
+    if (tid == 0) {
         scal[(size_t)r * 2] = make_double2(gamma, 0.0);
         scal[(size_t)r * 2 + 1] = c;
     }
@@ -686,7 +713,7 @@ hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
         launch_dc_dots<false>(dc, gd, s, a.V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
     else
         launch_dc_dots<true>(dc, gd, s, a.V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
-    hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(64), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
+    hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(DC_STEP_BS), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
                        a.H, a.cs, a.sn, a.gvec, a.hnorm, a.sc, a.tc, a.scal, a.thr, a.maxit, a.iters, a.kdim, a.active,
                        a.flags_out);
     if (!last) {
