@@ -72,6 +72,17 @@ def traffic_record(workload):
     return rec.get("bytes_per_launch") if rec else None
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(workload, gpu_iters, rows_per_case=None):
     """The oracle (single thread) on a bounded sample of the same workload:
     strided matrix rows of each case (48 at N = 4096, fewer for larger N so
@@ -102,10 +113,45 @@ def cpu_baseline(workload, gpu_iters, rows_per_case=None):
         t_total += t_rows / rows_n * n + iters * t_mv * (n / mv_n) ** 2
     solves = len(workload.problems) * len(workload.angles)
     return {"value": solves / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
             "sample": (f"{rows_n} strided rows per case assembled by the oracle (FP64) and one {mv_n} x {mv_n} "
                        f"oracle product, scaled to {workload.problems[0].order} rows, to the full product size "
                        f"and to the {sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation not "
                        f"modelled); {spent:.1f} s of CPU work")}
+
+
+def peaks_mode(args, torch):
+    """HBM bandwidth on this GPU by plain device kernels of known traffic
+    (the datasheet's 8 TB/s is the ceiling the rooflines quote): a read of 4
+    GiB (a sum), a write of 4 GiB (a fill) and a copy of 2 GiB (2 GiB read +
+    2 GiB written), each the median of --steps timed runs after --warmup."""
+    n = 1 << 29  # 4 GiB of float64
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty(n // 2, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        ts = []
+        for _ in range(max(3, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts))
+
+    t_read = timed(lambda: a.sum())
+    t_write = timed(lambda: a.fill_(2.0))
+    t_copy = timed(lambda: b.copy_(a[: n // 2]))
+    gb = 8.0 * n / 1e9
+    out = {"mode": "peaks", "hbm_read_GB_per_s": gb / t_read, "hbm_write_GB_per_s": gb / t_write,
+           "hbm_copy_GB_per_s": gb / t_copy, "datasheet_GB_per_s": 8000.0,
+           "kernels": "torch sum (read 4 GiB), fill (write 4 GiB), copy (2 GiB each way); median of timed runs"}
+    print(json.dumps(out), flush=True)
 
 
 def matvec_mode(args, wl, P, torch, prec):
@@ -434,7 +480,7 @@ def main():
                     help="launch-shape table: imported if the file exists, else written after tuning "
                          "(so that profiling runs use the same shapes)")
     ap.add_argument("--nf-elements", type=int, default=1024, help="nearfield mode: elements of the disk")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble", "nearfield"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble", "nearfield", "peaks"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
                          "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
                          "assemble: only --steps assemblies of every case")
@@ -462,6 +508,8 @@ def main():
         return assemble_mode(args, wl, P, torch, prec)
     if args.mode == "nearfield":
         return nearfield_mode(args, P, torch)
+    if args.mode == "peaks":
+        return peaks_mode(args, torch)
     dirs = wl.far_dirs
     probs, mats = [], []
     nr = len(wl.angles)
