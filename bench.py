@@ -278,6 +278,40 @@ def fp64_comparison(wl, probs, P, torch, F_mixed, tune=True):
                          f"{len(wl.far_dirs)} directions, max over right-hand sides of the relative 2-norm error"}
 
 
+def graphs_mode(args, wl, P, torch, prec):
+    """Solve time of the workload's cases with the Krylov steps launched kernel
+    by kernel (graph_steps 0) and as captured HIP graphs of 4, 8 and 16 steps:
+    each case assembled once, one untimed solve per setting (it captures the
+    graphs), then --steps timed solves (library timing off); the solutions of
+    every setting are compared with the kernel-by-kernel one bit for bit."""
+    settings = [0, 4, 8, 16]
+    mixed = prec != P.F64
+    cases = []
+    for spec in wl.problems:
+        g = P.Problem(spec)
+        g.assemble(prec)
+        B = g.rhs(wl.angles)
+        kw = dict(restart=wl.restart, tol=wl.tol, max_iter=20000, inner_tol=wl.inner_tol if mixed else 0.0)
+        X0, info0 = g.solve(B, **kw)
+        X0 = X0.clone()
+        row = {"case": str(spec.k), "iters_per_rhs": float(info0.iters.mean())}
+        for S in settings:
+            X, info = g.solve(B, graph_steps=S, **kw)
+            same = bool(torch.equal(X, X0)) and np.array_equal(info.iters, info0.iters)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                X, info = g.solve(B, graph_steps=S, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            row[f"graph_steps_{S}"] = {"ms_per_solve_call": ms, "identical_to_kernel_by_kernel": same}
+            log(f"  case {row['case']} graph_steps {S}: {ms:.3f} ms per solve call, identical {same}")
+        cases.append(row)
+    out = {"mode": "graphs", "workload": wl.name, "rhs_per_case": len(wl.angles), "restart": wl.restart,
+           "tol": wl.tol, "timed_solves_per_setting": args.steps, "cases": cases}
+    print(json.dumps(out), flush=True)
+
+
 def serve_mode(args, P, torch):
     """Served stream: requests with Poisson arrivals at 20/s, perturbed circles
     with N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32
@@ -295,7 +329,8 @@ def serve_mode(args, P, torch):
     solves = sum(len(r["angles"]) for r in reqs)
 
     def closed_loop(prec, tol):
-        with S.Server(arena, slots=args.slots, prec=prec, tol=tol, restart=args.serve_restart, dirs=dirs) as srv:
+        with S.Server(arena, slots=args.slots, prec=prec, tol=tol, restart=args.serve_restart, dirs=dirs,
+                      graph_steps=args.graph_steps) as srv:
             for r in reqs[:8]:  # warm-up: code objects, host paths
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -320,7 +355,8 @@ def serve_mode(args, P, torch):
     T64, r64, _ = closed_loop(P.F64, args.serve_tol)
     log(f"  {T64:.1f} s; FP64 reference to 1e-12 on every 10th request ...")
     sample = list(range(0, len(reqs), 10))
-    with S.Server(arena, slots=args.slots, prec=P.F64, tol=1e-12, restart=args.serve_restart, dirs=dirs) as srv:
+    with S.Server(arena, slots=args.slots, prec=P.F64, tol=1e-12, restart=args.serve_restart, dirs=dirs,
+                      graph_steps=args.graph_steps) as srv:
         ids = {srv.submit(reqs[i]["spec"], reqs[i]["angles"]): i for i in sample}
         ref = {ids[o.id]: o for o in srv.drain()}
     bad = [i for i in range(len(reqs)) if r32[i].status != 0 or r64[i].status != 0]
@@ -331,7 +367,7 @@ def serve_mode(args, P, torch):
     if not args.no_open_loop:
         log("  open loop at the arrival times ...")
         with S.Server(arena, slots=args.slots, prec=P.MIXED, tol=args.serve_tol, restart=args.serve_restart,
-                      dirs=dirs) as srv:
+                      dirs=dirs, graph_steps=args.graph_steps) as srv:
             for r in reqs[:8]:
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -367,7 +403,8 @@ def serve_mode(args, P, torch):
         "config": {"workload": f"served stream: {len(reqs)} requests, Poisson 20/s, perturbed circles N 512-8192 "
                                f"log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
                    "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
-                   "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs)},
+                   "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs),
+                   "graph_steps": args.graph_steps},
         "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
                      "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
                      "arena_high_water_GiB": st32["arena_high_water"] / 2**30},
@@ -475,15 +512,18 @@ def main():
                     help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="Krylov steps per captured HIP graph in the solves (0: kernel-by-kernel launches)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuning (bem_tune) before timing")
     ap.add_argument("--tune-file", default=None,
                     help="launch-shape table: imported if the file exists, else written after tuning "
                          "(so that profiling runs use the same shapes)")
     ap.add_argument("--nf-elements", type=int, default=1024, help="nearfield mode: elements of the disk")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble", "nearfield", "peaks"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "assemble", "nearfield", "peaks", "graphs"],
                     help="matvec: assemble case 1 and run only --steps block products with all the workload's "
                          "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
-                         "assemble: only --steps assemblies of every case")
+                         "assemble: only --steps assemblies of every case; graphs: --steps solves per case "
+                         "kernel by kernel and as captured HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; run with --gpus 1 "
@@ -510,6 +550,8 @@ def main():
         return nearfield_mode(args, P, torch)
     if args.mode == "peaks":
         return peaks_mode(args, torch)
+    if args.mode == "graphs":
+        return graphs_mode(args, wl, P, torch, prec)
     dirs = wl.far_dirs
     probs, mats = [], []
     nr = len(wl.angles)
@@ -535,7 +577,7 @@ def main():
             g.assemble(prec, out=A)
             B = g.rhs(wl.angles)
             X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000,
-                              inner_tol=wl.inner_tol if mixed else 0.0)
+                              inner_tol=wl.inner_tol if mixed else 0.0, graph_steps=args.graph_steps)
             F = g.farfield(X, dirs)
             torch.cuda.synchronize()
             if record:
@@ -627,6 +669,7 @@ def main():
                    "share_of_step_time": mv_ms / (T * 1e3)},
         "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
         "tuning": tuning,
+        "graph_steps": args.graph_steps,
         "roofline": roofline,
     }
     if mixed:

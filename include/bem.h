@@ -184,6 +184,16 @@ typedef struct {
     double inner_tol;   /* BEM_F32 / BEM_MIXED only: relative tolerance of each inner solve;
                            0 selects 1e-5                                               */
     int max_refine;     /* BEM_F32 / BEM_MIXED only: cap on FP64 refinement steps; 0 -> 20 */
+    int graph_steps;    /* 0: every Krylov step is launched kernel by kernel.  1..16: the
+                           steps run as captured HIP graphs of graph_steps steps each
+                           (product + orthogonalisation kernels), captured on first use
+                           and replayed in later cycles and calls; the host reads the
+                           device-side stopping flags one segment late, so up to about
+                           2 graph_steps products past a column's stop are spent.  Same
+                           kernels and order as 0, hence the same X.  The graphs keep the
+                           matrix, work buffer, nrhs, restart, max_iter and product launch
+                           shapes they were captured with; a call that changes any of
+                           them captures again.  Ignored while bem_profile_enable is on. */
 } bem_solve_opts;
 
 typedef struct {

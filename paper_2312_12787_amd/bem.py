@@ -49,7 +49,7 @@ class bem_desc(C.Structure):
 
 class bem_solve_opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double), ("inner_tol", C.c_double),
-                ("max_refine", C.c_int)]
+                ("max_refine", C.c_int), ("graph_steps", C.c_int)]
 
 
 class bem_profile(C.Structure):
@@ -322,8 +322,10 @@ class Problem:
                 "best_ms": info.best_ms, "default_ms": info.default_ms}
 
     def solve(self, B, restart: int = 100, tol: float = 1e-10, max_iter: int = 10000, inner_tol: float = 0.0,
-              max_refine: int = 0, X=None, stream=None, raise_on_noconv: bool = False):
-        """Solve A X = B (B complex128 of shape (nrhs, n)); returns (X, SolveInfo)."""
+              max_refine: int = 0, X=None, stream=None, raise_on_noconv: bool = False, graph_steps: int = 0):
+        """Solve A X = B (B complex128 of shape (nrhs, n)); returns (X, SolveInfo).
+        graph_steps > 0 runs the Krylov steps as captured HIP graphs of that many
+        steps (bem_solve_opts.graph_steps)."""
         import torch
         B = B.contiguous()
         nrhs = B.shape[0]
@@ -331,7 +333,7 @@ class Problem:
             X = torch.empty_like(B)
         _, _, wb = self.sizes(self.prec if self.prec is not None else F64, nrhs, restart)
         W = self._workspace(wb)
-        opts = bem_solve_opts(restart, max_iter, tol, inner_tol, max_refine)
+        opts = bem_solve_opts(restart, max_iter, tol, inner_tol, max_refine, graph_steps)
         info = (bem_solve_info * nrhs)()
         st = lib().bem_solve(self._h, nrhs, C.c_void_p(B.data_ptr()), B.shape[1], C.byref(opts),
                              C.c_void_p(X.data_ptr()), X.shape[1], C.c_void_p(W.data_ptr()), W.numel(), info,

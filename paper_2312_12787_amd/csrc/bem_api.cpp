@@ -114,6 +114,18 @@ struct bem_problem {
     size_t pinned_ints = 0;
     hipEvent_t flag_ev[bemk::FLAG_RING] = {};
     bool lent = false;  // pinned / flag_ev belong to the caller (request server slot)
+    // Arnoldi segments captured as HIP graphs (bem_solve_opts.graph_steps), by
+    // segment index, and everything their launches bake in
+    struct StepGraphs {
+        std::vector<hipGraphExec_t> seg;
+        const void *A = nullptr, *A32 = nullptr;
+        const char* w = nullptr;
+        const int* flags = nullptr;
+        size_t lda = 0, ldv = 0;
+        int prec = -1, n = 0, nr = 0, m = 0, S = 0, maxit = 0;
+        unsigned gen = 0;
+    } graphs;
+    hipStream_t cap = nullptr;  // private stream the segments are captured on (never runs work)
     // device state recorded by the calls
     char* geom = nullptr;
     void* A = nullptr;      // FP64 or FP32 matrix (BEM_MIXED: the FP64 one)
@@ -123,6 +135,13 @@ struct bem_problem {
 };
 
 namespace {
+
+void drop_graphs(bem_problem* p)
+{
+    for (hipGraphExec_t e : p->graphs.seg)
+        if (e) (void)hipGraphExecDestroy(e);
+    p->graphs.seg.clear();
+}
 
 int sigma_of(const bem_problem* p, int d, int m)
 {
@@ -470,6 +489,8 @@ void bem_destroy(bem_problem* p)
 {
     if (!p) return;
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+    drop_graphs(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     if (!p->lent) {
         for (hipEvent_t e : p->flag_ev)
             if (e) (void)hipEventDestroy(e);
@@ -741,6 +762,7 @@ struct Solver {
     char* w;
     hipStream_t s;
     int n, nr, m;
+    int graph = 0;  // Krylov steps per captured graph (0: kernel-by-kernel launches)
     template <class T>
     T* at(size_t off) const
     {
@@ -806,6 +828,65 @@ int flag_lag(int n, int prec)
     return bemk::FLAG_RING - 1;
 }
 
+// The executable graph of Arnoldi segment sg: steps j = sg S .. min(m, sg S + S - 1),
+// each the product V_j -> W (none for j = m) and the orthogonalisation kernels,
+// the stopping flags of step j going to pinned slot j % ring.  Captured on the
+// problem's private stream the first time the segment is reached (capture only
+// records the launches), instantiated, and kept for later cycles and calls
+// while nothing the launches bake in has changed.
+bem_status segment_graph(Solver& c, bemk::ArnoldiArgs arn, int sg, int S, int ring, hipGraphExec_t& out)
+{
+    bem_problem* p = c.p;
+    auto& G = p->graphs;
+    const unsigned gen = bemk::tuning_generation();
+    if (G.A != p->A || G.A32 != p->A32 || G.lda != p->lda || G.prec != p->prec || G.w != c.w ||
+        G.ldv != c.W.ldv || G.n != c.n || G.nr != c.nr || G.m != c.m || G.S != S || G.maxit != arn.maxit ||
+        G.flags != p->pinned_dev || G.gen != gen || G.seg.empty()) {
+        drop_graphs(p);
+        G.A = p->A;
+        G.A32 = p->A32;
+        G.lda = p->lda;
+        G.prec = p->prec;
+        G.w = c.w;
+        G.ldv = c.W.ldv;
+        G.n = c.n;
+        G.nr = c.nr;
+        G.m = c.m;
+        G.S = S;
+        G.maxit = arn.maxit;
+        G.flags = p->pinned_dev;
+        G.gen = gen;
+        G.seg.assign((size_t)(c.m + S) / S, nullptr);
+    }
+    if (!G.seg[sg]) {
+        if (!p->cap) HIP_OK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+        Solver cc = c;
+        cc.s = p->cap;
+        bem_status st = BEM_OK;
+        hipError_t e = hipSuccess;
+        const int j1 = std::min(c.m, sg * S + S - 1);
+        for (int j = sg * S; j <= j1 && st == BEM_OK && e == hipSuccess; ++j) {
+            if (j < c.m) st = apply_A(cc, c.V(j), c.W.ldv, c.at<double2>(c.W.W), c.W.ldv);
+            if (st != BEM_OK) break;
+            arn.flags_out = p->pinned_dev + (size_t)(j % ring) * c.nr;
+            e = bemk::launch_arnoldi(arn, j, p->cap);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(p->cap, &g);
+        if (st == BEM_OK && e == hipSuccess) e = ee;
+        if (st == BEM_OK && e == hipSuccess) e = hipGraphInstantiateWithFlags(&G.seg[sg], g, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (st != BEM_OK) return st;
+        if (e != hipSuccess) {
+            G.seg[sg] = nullptr;
+            return hip_fail(e, "capturing an Arnoldi segment");
+        }
+    }
+    out = G.seg[sg];
+    return BEM_OK;
+}
+
 // GMRES(m) from X = 0 on the columns with want[r] != 0 (Sec. 3.2).  Arnoldi
 // with delayed re-orthogonalisation (launch_arnoldi: steps 0..m, the last one
 // only completes column m - 1); the true residual is recomputed at the end of
@@ -855,10 +936,16 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     // small matrix gets a longer lag (its steps are shorter than the host's
     // launch work); steps enqueued after every column stopped do nothing but
     // an unused product.
-    const int lag = flag_lag(n, c.p->prec);
-    const int ring = lag + 1;
+    // With captured segments of S steps the host reads the flags of a
+    // segment's last step one segment late: S + 1 slots keep that slot clear
+    // of the segment running meanwhile; two events mark segment ends.
+    const bool graphs = c.graph > 0 && !c.p->prof.on;
+    const int S = graphs ? c.graph : 0;
+    const int lag = graphs ? 1 : flag_lag(n, c.p->prec);
+    const int ring = graphs ? S + 1 : lag + 1;
+    const int nev = graphs ? 2 : ring;
     if (c.p->pinned_ints < (size_t)ring * nr) {
-        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than (lag + 1) * nrhs");
+        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than the flag ring times nrhs");
         if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
         c.p->pinned = nullptr;
         c.p->pinned_dev = nullptr;
@@ -868,9 +955,9 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     }
     if (!c.p->pinned_dev)
         HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.p->pinned_dev), c.p->pinned, 0));
-    for (int k = 0; k < ring; ++k)
+    for (int k = 0; k < nev; ++k)
         if (!c.p->flag_ev[k]) {
-            if (c.p->lent) return fail(BEM_E_ARG, "lent flag events fewer than lag + 1");
+            if (c.p->lent) return fail(BEM_E_ARG, "lent flag events fewer than the flag ring");
             HIP_OK(hipEventCreateWithFlags(&c.p->flag_ev[k], hipEventDisableTiming));
         }
     bemk::ArnoldiArgs arn{};
@@ -904,7 +991,21 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
         HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
                                         c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
-        for (int j = 0; j <= m; ++j) {
+        for (int sg = 0; graphs && sg < (m + S) / S; ++sg) {
+            hipGraphExec_t ex = nullptr;
+            if (bem_status st = segment_graph(c, arn, sg, S, ring, ex)) return st;
+            HIP_OK(hipGraphLaunch(ex, c.s));
+            HIP_OK(hipEventRecord(c.p->flag_ev[sg & 1], c.s));
+            if (sg >= 1) {
+                HIP_OK(hipEventSynchronize(c.p->flag_ev[(sg - 1) & 1]));
+                const int jl = sg * S - 1;  // last step of the previous segment
+                const int* prev = c.p->pinned + (size_t)(jl % ring) * nr;
+                bool any = false;
+                for (int r = 0; r < nr; ++r) any = any || prev[r];
+                if (!any) break;
+            }
+        }
+        for (int j = 0; !graphs && j <= m; ++j) {
             if (j < m)
                 if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
             arn.flags_out = c.p->pinned_dev + (size_t)(j % ring) * nr;
@@ -964,7 +1065,10 @@ bem_status bem_solve(bem_problem* p, int nrhs, const void* B_dev, size_t ldb, co
     if (ldb < (size_t)n || ldx < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
     if (opts->restart < 1 || opts->restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
     if (!(opts->tol > 0.0) || opts->max_iter < 1) return fail(BEM_E_ARG, "tol must be > 0 and max_iter >= 1");
-    Solver c{p, make_work(n, nrhs, opts->restart), static_cast<char*>(work_dev), stream, n, nrhs, opts->restart};
+    if (opts->graph_steps < 0 || opts->graph_steps > bemk::GRAPH_MAX_STEPS)
+        return fail(BEM_E_ARG, "graph_steps must be in [0, " + std::to_string(bemk::GRAPH_MAX_STEPS) + "]");
+    Solver c{p, make_work(n, nrhs, opts->restart), static_cast<char*>(work_dev), stream, n, nrhs, opts->restart,
+             opts->graph_steps};
     if (work_bytes < c.W.total) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
     const double2* B = static_cast<const double2*>(B_dev);
     double2* X = static_cast<double2*>(X_dev);

@@ -15,6 +15,9 @@ namespace bemk {
 enum { KIND_ASSEMBLE = 0, KIND_MATVEC = 1, KIND_RESIDUAL = 2, N_KINDS = 3 };
 // GMRES stopping-flag read-back: ring of pinned slots and events (host lag + 1)
 constexpr int FLAG_RING = 5;
+// Graph-captured Arnoldi: at most this many Krylov steps per captured segment
+// (the flag ring of that path has GRAPH_MAX_STEPS + 1 slots)
+constexpr int GRAPH_MAX_STEPS = 16;
 struct KernelHook {
     void (*fn)(void* ctx, int kind, int phase, hipStream_t s);
     void* ctx;
@@ -65,6 +68,7 @@ void set_tuned_shape(int types, int ng, int n, const MvShape& c);
 void clear_tuned_shapes();
 std::string export_tuned_shapes();
 bool import_tuned_shapes(const char* text);
+unsigned tuning_generation();  // changes whenever the tuned table does (captured launches depend on it)
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s,
                              const KernelHook* hook = nullptr);

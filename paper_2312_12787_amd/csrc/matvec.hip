@@ -378,6 +378,7 @@ struct ShapeKey {
 };
 std::mutex g_tune_mu;
 std::map<ShapeKey, MvShape> g_tuned;
+unsigned g_tune_gen = 0;  // bumped whenever the table changes
 thread_local const MvShape* g_forced = nullptr;
 
 int size_class(int n)
@@ -619,12 +620,20 @@ void set_tuned_shape(int types, int ng, int n, const MvShape& c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[ShapeKey{types, ng, size_class(n)}] = c;
+    ++g_tune_gen;
 }
 
 void clear_tuned_shapes()
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
+    ++g_tune_gen;
+}
+
+unsigned tuning_generation()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_gen;
 }
 
 std::string export_tuned_shapes()
@@ -657,6 +666,7 @@ bool import_tuned_shapes(const char* text)
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : add) g_tuned[kv.first] = kv.second;
+    ++g_tune_gen;
     return true;
 }
 

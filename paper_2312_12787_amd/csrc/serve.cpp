@@ -31,7 +31,10 @@ namespace {
 
 constexpr int MAX_SLOTS = 16;
 constexpr int MAX_REQ_RHS = 256;
-constexpr size_t FLAG_INTS = (size_t)bemk::FLAG_RING * MAX_REQ_RHS;
+// flag slots per right-hand side: the kernel-by-kernel ring or the captured
+// path's GRAPH_MAX_STEPS + 1, whichever is longer
+constexpr size_t FLAG_INTS =
+    (size_t)(bemk::FLAG_RING > bemk::GRAPH_MAX_STEPS + 1 ? bemk::FLAG_RING : bemk::GRAPH_MAX_STEPS + 1) * MAX_REQ_RHS;
 
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 

@@ -75,12 +75,13 @@ class Server:
     slots: requests in flight at once; arena_bytes: device memory the server
     sub-allocates per request (admission by footprint); prec: F32 (FP32 matrix
     and products with FP64 refinement) or F64; dirs: far-field directions
-    returned for every right-hand side.
+    returned for every right-hand side; graph_steps: Krylov steps per captured
+    HIP graph in every request's solve (0: launched kernel by kernel).
     """
 
     def __init__(self, arena_bytes: int, slots: int = 4, prec: int = F32, restart: int = 100, tol: float = 1e-8,
                  inner_tol: float = 1e-5, max_iter: int = 20000, max_refine: int = 0,
-                 dirs: Sequence[float] = (0.0,), device: str = "cuda"):
+                 dirs: Sequence[float] = (0.0,), device: str = "cuda", graph_steps: int = 0):
         import torch
         L = _serve_lib()
         self.device = torch.device(device)
@@ -94,7 +95,8 @@ class Server:
         o.arena_dev = self.arena.data_ptr()
         o.arena_bytes = self.arena.numel()
         o.prec = int(prec)
-        o.solve = bem_solve_opts(int(restart), int(max_iter), float(tol), float(inner_tol), int(max_refine))
+        o.solve = bem_solve_opts(int(restart), int(max_iter), float(tol), float(inner_tol), int(max_refine),
+                                int(graph_steps))
         o.ndir = len(self.dirs)
         o.dirs = self.dirs.ctypes.data_as(C.POINTER(C.c_double))
         h = C.c_void_p()
