@@ -768,22 +768,28 @@ struct Solver {
     {
         return reinterpret_cast<T*>(w + off);
     }
+    // The Krylov basis: complex128, or complex64 when the products run in FP32
+    // (the inner solves of BEM_F32 / BEM_MIXED; same element offsets, half
+    // the bytes of the region)
+    bool v32() const { return p->prec != BEM_F64; }
     double2* V(int i) const { return at<double2>(W.V) + (size_t)i * nr * W.ldv; }
+    float2* V32(int i) const { return at<float2>(W.V) + (size_t)i * nr * W.ldv; }
 };
 
-// Y = A X for FP64 vectors; with an FP32 matrix the product runs in FP32.
-bem_status apply_A(const Solver& c, const double2* X, size_t ldx, double2* Y, size_t ldy)
+// Y = A v_j for basis vector j of every right-hand side: the FP64 product, or
+// the FP32 one on the complex64 basis (FP32 matrix, or the FP32 copy of a
+// BEM_MIXED one), Y in FP64 either way.
+bem_status apply_basis(const Solver& c, int j, double2* Y, size_t ldy)
 {
     const bem_problem* p = c.p;
-    if (p->prec == BEM_F64) {
-        HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, Y, ldy,
+    if (!c.v32()) {
+        HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, c.V(j), c.W.ldv, c.nr, Y, ldy,
                                        c.at<double2>(c.W.mv_part), c.s, p->hk()));
-    } else {
-        // FP32 products: the FP32 matrix, or the FP32 copy of a BEM_MIXED one
-        const float2* A32 = static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A);
-        HIP_OK(bemk::launch_matvec_f32x64(A32, p->lda, c.n, X, ldx, c.nr, Y, ldy,
-                                          reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk()));
+        return BEM_OK;
     }
+    const float2* A32 = static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A);
+    HIP_OK(bemk::launch_matvec_f32v(A32, p->lda, c.n, c.V32(j), c.W.ldv, c.nr, Y, ldy,
+                                    reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk()));
     return BEM_OK;
 }
 
@@ -867,7 +873,7 @@ bem_status segment_graph(Solver& c, bemk::ArnoldiArgs arn, int sg, int S, int ri
         hipError_t e = hipSuccess;
         const int j1 = std::min(c.m, sg * S + S - 1);
         for (int j = sg * S; j <= j1 && st == BEM_OK && e == hipSuccess; ++j) {
-            if (j < c.m) st = apply_A(cc, c.V(j), c.W.ldv, c.at<double2>(c.W.W), c.W.ldv);
+            if (j < c.m) st = apply_basis(cc, j, c.at<double2>(c.W.W), c.W.ldv);
             if (st != BEM_OK) break;
             arn.flags_out = p->pinned_dev + (size_t)(j % ring) * c.nr;
             e = bemk::launch_arnoldi(arn, j, p->cap);
@@ -962,6 +968,7 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         }
     bemk::ArnoldiArgs arn{};
     arn.V = c.V(0);
+    arn.v32 = c.v32();
     arn.ldv = ldv;
     arn.nr = nr;
     arn.m = m;
@@ -989,8 +996,12 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     while (std::count(alive.begin(), alive.end(), 1) > 0) {
         if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
         HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
-        HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
-                                        c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
+        if (c.v32())
+            HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V32(0), ldv,
+                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
+        else
+            HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
+                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
         for (int sg = 0; graphs && sg < (m + S) / S; ++sg) {
             hipGraphExec_t ex = nullptr;
             if (bem_status st = segment_graph(c, arn, sg, S, ring, ex)) return st;
@@ -1007,7 +1018,7 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         }
         for (int j = 0; !graphs && j <= m; ++j) {
             if (j < m)
-                if (bem_status st = apply_A(c, c.V(j), ldv, Wv, ldv)) return st;
+                if (bem_status st = apply_basis(c, j, Wv, ldv)) return st;
             arn.flags_out = c.p->pinned_dev + (size_t)(j % ring) * nr;
             HIP_OK(bemk::launch_arnoldi(arn, j, c.s));
             HIP_OK(hipEventRecord(c.p->flag_ev[j % ring], c.s));
@@ -1021,7 +1032,12 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
         }
         HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
                                       c.at<double2>(c.W.y), c.s));
-        HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx, c.s));
+        if (c.v32())
+            HIP_OK(bemk::launch_xupdate(c.V32(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx,
+                                        c.s));
+        else
+            HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx,
+                                        c.s));
         // FP64 accumulation also inside the refinement: with FP32 products the
         // rounding of the restart residual (about 1e-7 kappa ||b||) can exceed
         // the inner tolerance of an ill-conditioned problem, which then never

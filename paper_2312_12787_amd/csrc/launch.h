@@ -77,6 +77,10 @@ hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2*
 hipError_t launch_matvec_f32x64(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                                 double2* Y, size_t ldy, float2* partial, hipStream_t s,
                                 const KernelHook* hook = nullptr);
+// The same with an FP32 X (a complex64 Krylov basis vector); Y in FP64.
+hipError_t launch_matvec_f32v(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs,
+                              double2* Y, size_t ldy, float2* partial, hipStream_t s,
+                              const KernelHook* hook = nullptr);
 hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
                              size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr);
 // R = B - A X (FP64)
@@ -111,13 +115,18 @@ struct ArnoldiArgs {
     int maxit;
     int *iters, *kdim, *active;    // counters and flags (device)
     int* flags_out;                // copy of the stopping flags in pinned host memory (device address)
+    bool v32;                      // basis stored as complex64 at V (same element offsets), else complex128
 };
 hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
                               double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
+hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
+                              float2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
                             hipStream_t s);
 hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+                          double2* X, size_t ldx, hipStream_t s);
+hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s);
 hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, size_t ldax, int n, int nr,
                             double2* R, size_t ldr, hipStream_t s);

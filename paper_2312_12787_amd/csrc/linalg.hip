@@ -22,6 +22,17 @@ constexpr int BS = 256;        // threads per block
 template <class T>
 __device__ __forceinline__ const T* tab(const char* g, size_t off) { return reinterpret_cast<const T*>(g + off); }
 
+// Krylov basis entries: complex128, or complex64 (the FP32-product solves)
+// widened on load and rounded on store; all arithmetic stays FP64.
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2* p)
+{
+    const float2 f = *p;
+    return make_double2(f.x, f.y);
+}
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
 // Move a double between lanes with a DPP pattern (two 32-bit moves); lanes
 // whose row is masked off or whose source is out of range receive 0.
 template <int CTRL, int ROW_MASK>
@@ -196,8 +207,8 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
 // Partial projections of the candidate (and of wt when HASW) on V_0..V_j for a
 // batch of BATCH basis vectors (grid x), one right-hand side (grid y) and one
 // chunk of rpt * BS rows (grid z): partP/partQ[(r * ns + chunk) * jc + i].
-template <int BATCH, bool HASW>
-__global__ __launch_bounds__(BS) void k_dc_dots(const double2* __restrict__ V, size_t ldv, int nr, int jc,
+template <int BATCH, bool HASW, class TV>
+__global__ __launch_bounds__(BS) void k_dc_dots(const TV* __restrict__ V, size_t ldv, int nr, int jc,
                                                 const double2* __restrict__ W, size_t ldw, int n, int rpt,
                                                 double2* __restrict__ partP, double2* __restrict__ partQ,
                                                 const int* __restrict__ active)
@@ -211,20 +222,20 @@ __global__ __launch_bounds__(BS) void k_dc_dots(const double2* __restrict__ V, s
 #pragma unroll
     for (int b = 0; b < NV; ++b) acc[b] = 0.0;
     const size_t vstride = (size_t)nr * ldv;
-    const double2* vb = V + ((size_t)i0 * nr + r) * ldv;
-    const double2* vt = V + ((size_t)(jc - 1) * nr + r) * ldv;
+    const TV* vb = V + ((size_t)i0 * nr + r) * ldv;
+    const TV* vt = V + ((size_t)(jc - 1) * nr + r) * ldv;
     const double2* wr = HASW ? W + (size_t)r * ldw : nullptr;
     const int nb = min(BATCH, jc - i0);
     const int q0 = chunk * rpt * BS + threadIdx.x;
     const int q1 = min(n, (chunk + 1) * rpt * BS);
     for (int q = q0; q < q1; q += BS) {
-        const double2 a = vt[q];
+        const double2 a = ld2(vt + q);
         double2 w = make_double2(0.0, 0.0);
         if (HASW) w = wr[q];
 #pragma unroll
         for (int b = 0; b < BATCH; ++b) {
             if (b < nb) {
-                const double2 v = vb[b * vstride + q];
+                const double2 v = ld2(vb + b * vstride + q);
                 acc[2 * b] = fma(v.x, a.x, fma(v.y, a.y, acc[2 * b]));
                 acc[2 * b + 1] = fma(v.x, a.y, fma(-v.y, a.x, acc[2 * b + 1]));
                 if (HASW) {
@@ -453,7 +464,8 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
 // One pass over V_0..V_{j-1}: v_j = (vt - V s) / gamma (in place of the
 // candidate) and w = (wt - V t - v_j c) / gamma; norm_out gets the partial of
 // |w|^2 of each block.
-__global__ __launch_bounds__(BS) void k_dc_update(double2* __restrict__ V, size_t ldv, int nr, int j, int m,
+template <class TV>
+__global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv, int nr, int j, int m,
                                                   const double2* __restrict__ sc, const double2* __restrict__ tc,
                                                   const double2* __restrict__ scal, double2* __restrict__ W,
                                                   size_t ldw, int n, double* __restrict__ norm_out,
@@ -474,11 +486,11 @@ __global__ __launch_bounds__(BS) void k_dc_update(double2* __restrict__ V, size_
     double nn[1] = {0.0};
     const int q = blockIdx.x * BS + threadIdx.x;
     if (q < n) {
-        double2* vj = V + ((size_t)j * nr + r) * ldv;
-        double2 v = vj[q];
+        TV* vj = V + ((size_t)j * nr + r) * ldv;
+        double2 v = ld2(vj + q);
         double2 w = W[(size_t)r * ldw + q];
         for (int i = 0; i < j; ++i) {
-            const double2 b = V[((size_t)i * nr + r) * ldv + q];
+            const double2 b = ld2(V + ((size_t)i * nr + r) * ldv + q);
             const double2 a = sl[i], t = tl[i];
             v.x -= a.x * b.x - a.y * b.y;
             v.y -= a.x * b.y + a.y * b.x;
@@ -488,7 +500,7 @@ __global__ __launch_bounds__(BS) void k_dc_update(double2* __restrict__ V, size_
         v = make_double2(v.x * ig, v.y * ig);
         const double2 vc = cmul2(v, c);
         w = make_double2((w.x - vc.x) * ig, (w.y - vc.y) * ig);
-        vj[q] = v;
+        st2(vj + q, v);
         W[(size_t)r * ldw + q] = w;
         nn[0] = fma(w.x, w.x, w.y * w.y);
     }
@@ -498,9 +510,10 @@ __global__ __launch_bounds__(BS) void k_dc_update(double2* __restrict__ V, size_
 
 // beta = |w| from the update partials (every block sums them in the same
 // order), V_{j+1} = w / beta (0 if beta = 0: the Krylov space ended).
+template <class TV>
 __global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, size_t ldw, int n,
                                                 const double* __restrict__ norm_part, int nu,
-                                                double2* __restrict__ V, size_t ldv, double* __restrict__ hnorm,
+                                                TV* __restrict__ V, size_t ldv, double* __restrict__ hnorm,
                                                 const int* __restrict__ active)
 {
     __shared__ double bsh;
@@ -519,11 +532,12 @@ __global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, s
     if (q >= n) return;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const double2 w = W[(size_t)r * ldw + q];
-    V[(size_t)r * ldv + q] = make_double2(w.x * inv, w.y * inv);
+    st2(V + (size_t)r * ldv + q, make_double2(w.x * inv, w.y * inv));
 }
 
+template <class TV>
 __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, int nr,
-                              const double* __restrict__ rnorm, int m, double2* __restrict__ V, size_t ldv,
+                              const double* __restrict__ rnorm, int m, TV* __restrict__ V, size_t ldv,
                               double2* __restrict__ gvec, const int* __restrict__ active)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -533,13 +547,14 @@ __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, 
     const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
     if (q < n) {
         const double2 v = R[(size_t)r * ldr + q];
-        V[(size_t)r * ldv + q] = make_double2(v.x * inv, v.y * inv);
+        st2(V + (size_t)r * ldv + q, make_double2(v.x * inv, v.y * inv));
     }
     if (q <= m) gvec[(size_t)r * (m + 1) + q] = make_double2(q == 0 ? nv : 0.0, 0.0);
 }
 
 
-__global__ void k_xupdate(const double2* __restrict__ V, size_t ldv, int nr, int n, const double2* __restrict__ y,
+template <class TV>
+__global__ void k_xupdate(const TV* __restrict__ V, size_t ldv, int nr, int n, const double2* __restrict__ y,
                           const int* __restrict__ kdim, double2* __restrict__ X, size_t ldx)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -551,7 +566,7 @@ __global__ void k_xupdate(const double2* __restrict__ V, size_t ldv, int nr, int
     const double2* yr = y + (size_t)r * 1024;
     for (int i = 0; i < k; ++i) {
         const double2 c = yr[i];
-        const double2 v = V[((size_t)i * nr + r) * ldv + q];
+        const double2 v = ld2(V + ((size_t)i * nr + r) * ldv + q);
         x.x += c.x * v.x - c.y * v.y;
         x.y += c.x * v.y + c.y * v.x;
     }
@@ -683,23 +698,26 @@ DotCfg dot_cfg()
 
 int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().rows - 1) / dot_cfg().rows); }
 
-template <bool HASW>
-void launch_dc_dots(const DotCfg& c, dim3 grid, hipStream_t s, const double2* V, size_t ldv, int nr, int jc,
+namespace {
+
+template <bool HASW, class TV>
+void launch_dc_dots(const DotCfg& c, dim3 grid, hipStream_t s, const TV* V, size_t ldv, int nr, int jc,
                     const double2* W, size_t ldw, int n, double2* partP, double2* partQ, const int* active)
 {
     const int rpt = c.rows / BS;
     if (c.batch == 4)
-        hipLaunchKernelGGL((k_dc_dots<4, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP, partQ,
-                           active);
+        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
+                           partQ, active);
     else if (c.batch == 16)
-        hipLaunchKernelGGL((k_dc_dots<16, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
+        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
                            partQ, active);
     else
-        hipLaunchKernelGGL((k_dc_dots<8, HASW>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP, partQ,
-                           active);
+        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
+                           partQ, active);
 }
 
-hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
+template <class TV>
+hipError_t launch_arnoldi_t(const ArnoldiArgs& a, TV* V, int j, hipStream_t s)
 {
     const DotCfg dc = dot_cfg();
     const int n = a.n, nr = a.nr, m = a.m;
@@ -710,28 +728,53 @@ hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
     dim3 gd((jc + dc.batch - 1) / dc.batch, nr, ns);
     dim3 gu(nu, nr);
     if (last)
-        launch_dc_dots<false>(dc, gd, s, a.V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
+        launch_dc_dots<false, TV>(dc, gd, s, V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
     else
-        launch_dc_dots<true>(dc, gd, s, a.V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
+        launch_dc_dots<true, TV>(dc, gd, s, V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
     hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(DC_STEP_BS), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
                        a.H, a.cs, a.sn, a.gvec, a.hnorm, a.sc, a.tc, a.scal, a.thr, a.maxit, a.iters, a.kdim, a.active,
                        a.flags_out);
     if (!last) {
-        hipLaunchKernelGGL(k_dc_update, gu, dim3(BS), 0, s, a.V, a.ldv, nr, j, m, a.sc, a.tc, a.scal, a.W, a.ldw, n,
-                           a.norm_part, a.active);
-        hipLaunchKernelGGL(k_dc_next, gu, dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
-                           a.V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active);
+        hipLaunchKernelGGL((k_dc_update<TV>), gu, dim3(BS), 0, s, V, a.ldv, nr, j, m, a.sc, a.tc, a.scal, a.W,
+                           a.ldw, n, a.norm_part, a.active);
+        hipLaunchKernelGGL((k_dc_next<TV>), gu, dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
+                           V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active);
     }
     return hipGetLastError();
 }
 
+}  // namespace
+
+hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
+{
+    if (a.v32) return launch_arnoldi_t<float2>(a, reinterpret_cast<float2*>(a.V), j, s);
+    return launch_arnoldi_t<double2>(a, a.V, j, s);
+}
+
+namespace {
+
+template <class TV>
+hipError_t start_cycle_t(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m, TV* V, size_t ldv,
+                         double2* gvec, const int* active, hipStream_t s)
+{
+    const int len = std::max(n, m + 1);
+    hipLaunchKernelGGL((k_start_cycle<TV>), dim3((len + BS - 1) / BS, nr), dim3(BS), 0, s, R, ldr, n, nr, rnorm, m,
+                       V, ldv, gvec, active);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
                               double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s)
 {
-    const int len = std::max(n, m + 1);
-    hipLaunchKernelGGL(k_start_cycle, dim3((len + BS - 1) / BS, nr), dim3(BS), 0, s, R, ldr, n, nr, rnorm, m, V,
-                       ldv, gvec, active);
-    return hipGetLastError();
+    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, s);
+}
+
+hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
+                              float2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s)
+{
+    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, s);
 }
 
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
@@ -744,7 +787,16 @@ hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec
 hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_xupdate, dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, y, kdim, X, ldx);
+    hipLaunchKernelGGL((k_xupdate<double2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, y, kdim, X,
+                       ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+                          double2* X, size_t ldx, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_xupdate<float2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, y, kdim, X,
+                       ldx);
     return hipGetLastError();
 }
 

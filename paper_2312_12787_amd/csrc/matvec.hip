@@ -569,6 +569,12 @@ hipError_t launch_matvec_f32x64(const float2* A, size_t lda, int n, const double
     return matvec_any<float2, double2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook);
 }
 
+hipError_t launch_matvec_f32v(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs,
+                              double2* Y, size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook)
+{
+    return matvec_any<float2, float2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook);
+}
+
 hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                               const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,
                               const KernelHook* hook)
