@@ -14,7 +14,8 @@ region.  value = solved right-hand sides per second over the K timed steps.
 
 Also reported: p50/p99 latency of one case (16 solves), the assembly rate, and
 the roofline record of the dominant kernel measured with the library's HIP
-events on the solve stream, plus the CPU oracle timed on a bounded sample.
+events on the solve stream, plus the CPU oracle timed on a bounded sample, on
+one core and as one concurrent copy per available core (at most 16).
 
 Other workloads (--workload): disk256 (unit disk, N = 256), sectors (three
 material sectors with junctions, about 7500 graded elements), kite16384_mixed
@@ -37,6 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_FACTORIES = {"kite4096": lambda W: W.workload_kite4096, "disk256": lambda W: W.workload_disk256,
+                      "sectors": lambda W: W.workload_sectors,
+                      "kite16384_mixed": lambda W: W.workload_kite16384_fp32}
 FP32_MFMA_PEAK_TFS = 157.3
 VALU_PEAK_FLOPS = 78.6e12  # FP64 vector; also FP32 vector without packed FP32 (the kernels are compiled without it)
 METRIC = "solves/s + p50/p99 latency at 1e-6 rel. err vs FP64; assembly FLOP/s, matvec GB/s"
@@ -83,48 +87,106 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(workload, gpu_iters, rows_per_case=None):
-    """The oracle (single thread) on a bounded sample of the same workload:
+def oracle_sample(workload, gpu_iters, rows_per_case=None, start_at=None):
+    """Time the oracle (single thread) on a bounded sample of the workload:
     strided matrix rows of each case (48 at N = 4096, fewer for larger N so
     the sample stays near the same CPU time) and one product of at most
     8192 x 8192; scaled to full assembly (rows x n), to the full product size
     (n^2) and to the product count the GPU solve needed (sum of GMRES
-    iterations and restart residuals)."""
+    iterations and restart residuals).  start_at: wall-clock time (time.time)
+    to wait for once the inputs are prepared, so that concurrent copies time
+    the same interval.  Returns (modelled seconds for the workload's solves,
+    seconds spent, rows per case, product size)."""
     import oracle as O
-    t_total = 0.0
-    spent = 0.0
-    mv_n = None
-    for spec, iters in zip(workload.problems, gpu_iters):
+    cases = []
+    for spec in workload.problems:
         P = O.Problem(spec)
         n = P.n
-        rows_n = rows_per_case or max(12, int(48 * 8192 / n))
+        rows_n = min(n, rows_per_case or max(12, int(48 * 8192 / n)))
         rows = np.linspace(0, n - 1, rows_n).round().astype(np.int32)
+        mv_n = min(n, 8192)
+        cases.append((P, n, rows, mv_n))
+    # written, not just allocated: untouched pages of a fresh allocation all
+    # map the kernel's one zero page, and a product over them runs from cache
+    A = np.empty((cases[0][3], cases[0][3]), dtype=np.complex128, order="F")
+    A.fill(0.5 + 0.25j)
+    if start_at is not None:
+        time.sleep(max(0.0, start_at - time.time()))
+    t_total = 0.0
+    spent = 0.0
+    for (P, n, rows, mv_n), iters in zip(cases, gpu_iters):
         t0 = time.perf_counter()
         P.assemble_rows(rows)
         t_rows = time.perf_counter() - t0
-        mv_n = min(n, 8192)
-        A = np.zeros((mv_n, mv_n), dtype=np.complex128, order="F")
+        if A.shape[0] != mv_n:
+            A = np.empty((mv_n, mv_n), dtype=np.complex128, order="F")
+            A.fill(0.5 + 0.25j)
         x = np.ones(mv_n, dtype=np.complex128)
         t0 = time.perf_counter()
         O.matvec(A, x)
         t_mv = time.perf_counter() - t0
-        del A
         spent += t_rows + t_mv
-        t_total += t_rows / rows_n * n + iters * t_mv * (n / mv_n) ** 2
+        t_total += t_rows / len(rows) * n + iters * t_mv * (n / mv_n) ** 2
+    return t_total, spent, len(cases[-1][2]), cases[-1][3]
+
+
+def cpu_baseline(workload, wl_key, gpu_iters, gpu_value):
+    """The oracle on one core (the record's value), then the same sample in P
+    concurrent worker processes, one per available core (at most 16), each
+    pinned to its core and started together: their summed rate is the CPU
+    throughput on P cores (requests and right-hand sides are independent)."""
+    t_total, spent, rows_n, mv_n = oracle_sample(workload, gpu_iters)
     solves = len(workload.problems) * len(workload.angles)
-    return {"value": solves / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    one = solves / t_total
+    cores = sorted(os.sched_getaffinity(0))[:16]
+    import subprocess
+    start = time.time() + 4.0 + 0.5 * len(cores)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--workload", wl_key,
+           "--cpu-iters", ",".join(str(int(i)) for i in gpu_iters), "--cpu-start-at", repr(start)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen(cmd + ["--cpu-core", str(c)], stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env)
+             for c in cores]
+    rates, errs = [], []
+    for p in procs:
+        out, err = p.communicate(timeout=900)
+        if p.returncode == 0:
+            rates.append(solves / json.loads(out.decode().strip().splitlines()[-1])["t_total"])
+        else:
+            errs.append(err.decode()[-300:])
+    par = {"processes": len(cores), "completed": len(rates), "value": float(sum(rates)), "unit": "solves/s",
+           "per_process_min": float(min(rates)) if rates else None,
+           "per_process_max": float(max(rates)) if rates else None}
+    if errs:
+        par["errors"] = errs
+    return {"value": one, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
             "sample": (f"{rows_n} strided rows per case assembled by the oracle (FP64) and one {mv_n} x {mv_n} "
                        f"oracle product, scaled to {workload.problems[0].order} rows, to the full product size "
                        f"and to the {sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation not "
-                       f"modelled); {spent:.1f} s of CPU work")}
+                       f"modelled); {spent:.1f} s of CPU work"),
+            "parallel": par,
+            "gpu_speedup": {"vs_1_core": gpu_value / one,
+                            f"vs_{len(rates)}_cores": gpu_value / par["value"] if rates else None}}
+
+
+def cpu_worker(args):
+    """One worker of the parallel CPU baseline: the oracle sample on one
+    pinned core, its modelled time printed as a JSON line."""
+    import workloads as W
+    os.sched_setaffinity(0, {args.cpu_core})
+    wl = WORKLOAD_FACTORIES[args.workload](W)()
+    iters = [int(v) for v in args.cpu_iters.split(",")]
+    t_total, spent, _, _ = oracle_sample(wl, iters, start_at=args.cpu_start_at)
+    print(json.dumps({"t_total": t_total, "spent": spent, "core": args.cpu_core}), flush=True)
 
 
 def peaks_mode(args, torch):
     """HBM bandwidth on this GPU by plain device kernels of known traffic
     (the datasheet's 8 TB/s is the ceiling the rooflines quote): a read of 4
     GiB (a sum), a write of 4 GiB (a fill) and a copy of 2 GiB (2 GiB read +
-    2 GiB written), each the median of --steps timed runs after --warmup."""
+    2 GiB written), and the streaming read of libbem_diag.so over 1 GiB (the
+    kite4096 matrix size) and 4 GiB at its best of 12 launch shapes; each the
+    median of --steps timed runs after --warmup."""
     n = 1 << 29  # 4 GiB of float64
     a = torch.empty(n, dtype=torch.float64, device="cuda")
     a.fill_(1.0)
@@ -148,9 +210,31 @@ def peaks_mode(args, torch):
     t_write = timed(lambda: a.fill_(2.0))
     t_copy = timed(lambda: b.copy_(a[: n // 2]))
     gb = 8.0 * n / 1e9
+    # the library's streaming read (one contiguous panel per workgroup,
+    # non-temporal 16-byte loads) over a buffer of ones, best launch shape
+    import ctypes as C
+    diag = C.CDLL(os.path.join(ROOT, "paper_2312_12787_amd", "libbem_diag.so"))
+    diag.bem_diag_stream_read.restype = C.c_int
+    diag.bem_diag_stream_read.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    a.fill_(1.0)
+    sink = torch.empty(1 << 16, dtype=torch.float64, device="cuda")
+    stream_read = {}
+    for size in (1 << 30, 1 << 32):
+        best = (0.0, None)
+        for grid in (1024, 2048, 4096, 8192, 16384, 32768):
+            for unroll in (4, 8):
+                def rd():
+                    rc = diag.bem_diag_stream_read(a.data_ptr(), size, grid, unroll, sink.data_ptr(), st.cuda_stream)
+                    if rc != 0:
+                        raise RuntimeError(f"bem_diag_stream_read: hip error {rc}")
+                rate = size / 1e9 / timed(rd)
+                if rate > best[0]:
+                    best = (rate, {"grid": grid, "unroll": unroll})
+        stream_read[f"{size >> 30}GiB"] = {"GB_per_s": best[0], **best[1]}
     out = {"mode": "peaks", "hbm_read_GB_per_s": gb / t_read, "hbm_write_GB_per_s": gb / t_write,
-           "hbm_copy_GB_per_s": gb / t_copy, "datasheet_GB_per_s": 8000.0,
-           "kernels": "torch sum (read 4 GiB), fill (write 4 GiB), copy (2 GiB each way); median of timed runs"}
+           "hbm_copy_GB_per_s": gb / t_copy, "hbm_stream_read": stream_read, "datasheet_GB_per_s": 8000.0,
+           "kernels": "torch sum (read 4 GiB), fill (write 4 GiB), copy (2 GiB each way); hbm_stream_read: "
+                      "bem_diag_stream_read (libbem_diag.so), best of 12 launch shapes; median of timed runs"}
     print(json.dumps(out), flush=True)
 
 
@@ -524,7 +608,13 @@ def main():
                          "right-hand sides, then one plain 1 GiB device copy (for hardware-counter runs); "
                          "assemble: only --steps assemblies of every case; graphs: --steps solves per case "
                          "kernel by kernel and as captured HIP graphs")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-iters", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-start-at", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-core", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        return cpu_worker(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only; run with --gpus 1 "
               "(the library has no multi-GPU path: sharding by row blocks is a design, not code)", file=sys.stderr)
@@ -538,8 +628,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "serve":
         return serve_mode(args, P, torch)
-    wl = {"kite4096": W.workload_kite4096, "disk256": W.workload_disk256,
-          "sectors": W.workload_sectors, "kite16384_mixed": W.workload_kite16384_fp32}[args.workload]()
+    wl = WORKLOAD_FACTORIES[args.workload](W)()
     mixed = wl.precision == "f32"
     prec = P.F32 if mixed else P.F64
     if args.mode == "matvec":
@@ -678,7 +767,7 @@ def main():
         out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F, tune=not args.no_tune)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl, [p // args.steps for p in products])
+        out["cpu_baseline"] = cpu_baseline(wl, args.workload, [p // args.steps for p in products], out["value"])
     print(json.dumps(out), flush=True)
 
 

@@ -1,4 +1,5 @@
-"""Build the gfx950 HIP library libbem_hip.so in-tree (hipcc, no JIT).
+"""Build the gfx950 HIP library libbem_hip.so in-tree (hipcc, no JIT), and
+the benchmark's small diagnostics library libbem_diag.so.
 
 Run ``python -m paper_2312_12787_amd.build`` (or call ``build()``).  The
 library exports the C ABI declared in include/bem.h.
@@ -11,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbem_hip.so")
+DIAG_LIB = os.path.join(HERE, "libbem_diag.so")  # streaming-read kernel of bench.py --mode peaks
 SOURCES = ["assemble.hip", "linalg.hip", "matvec.hip", "nearfield.hip", "bem_api.cpp", "serve.cpp"]
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
@@ -40,6 +42,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)
+    diag = [hipcc] + common + ["-shared", os.path.join(CSRC, "diag.hip"), "-o", DIAG_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(diag), flush=True)
+    subprocess.run(diag, check=True)
+    os.replace(DIAG_LIB + ".tmp", DIAG_LIB)
     return LIB
 
 
