@@ -239,18 +239,23 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
                 }
             }
     };
-    int c = c0;
-    for (; c + 4 * U <= c1; c += 4 * U) {
-        TA a[U][RT];
-        V2 x[U][NG];
+    // HBM-bound shapes (one group of 16 right-hand sides, at most 16 tile
+    // loads per step) walk the columns software-pipelined: the loads of the
+    // next 4U columns are issued before the products of the current ones, so
+    // a wave keeps its reads in flight while its matrix-core work runs.  The
+    // wider shapes are matrix-core bound and would spill the second buffer.
+    constexpr bool PIPE = NG == 1 && RT * U <= 16;
+    auto load = [&](TA (&a)[U][RT], V2 (&x)[U][NG], int cc) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int col = c + 4 * u + lk;
+            const int col = cc + 4 * u + lk;
 #pragma unroll
             for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
 #pragma unroll
             for (int t = 0; t < RT; ++t) a[u][t] = ld_stream(ap[t] + (size_t)col * lda);
         }
+    };
+    auto compute = [&](const TA (&a)[U][RT], const V2 (&x)[U][NG]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             T ar[RT], ai[RT], xr[NG], xi[NG];
@@ -265,6 +270,60 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
                 xi[g] = x[u][g].y;
             }
             step(ar, ai, xr, xi);
+        }
+    };
+    int c = c0;
+    if constexpr (!PIPE) {
+        for (; c + 4 * U <= c1; c += 4 * U) {
+            TA a[U][RT];
+            V2 x[U][NG];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int col = c + 4 * u + lk;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) a[u][t] = ld_stream(ap[t] + (size_t)col * lda);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                T ar[RT], ai[RT], xr[NG], xi[NG];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    ar[t] = rok[t] ? (T)a[u][t].x : T(0);
+                    ai[t] = rok[t] ? (T)a[u][t].y : T(0);
+                }
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    xr[g] = x[u][g].x;
+                    xi[g] = x[u][g].y;
+                }
+                step(ar, ai, xr, xi);
+            }
+        }
+    } else if (c + 4 * U <= c1) {
+        TA a[U][RT];
+        V2 x[U][NG];
+        load(a, x, c);
+        for (;;) {
+            const int cn = c + 4 * U;
+            if (cn + 4 * U > c1) {
+                compute(a, x);
+                c = cn;
+                break;
+            }
+            TA an[U][RT];
+            V2 xn[U][NG];
+            load(an, xn, cn);
+            compute(a, x);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t) a[u][t] = an[u][t];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) x[u][g] = xn[u][g];
+            }
+            c = cn;
         }
     }
     for (; c < c1; c += 4) {
