@@ -429,18 +429,37 @@ struct cf {
 };
 __device__ __forceinline__ cf cmulf(cf a, cf b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
+template <bool CPLX>
+__device__ __forceinline__ void hankel_far32_body(const WaveConst& W64, const WaveConst32& W, double r, float& h0r,
+                                                  float& h0i, float& h1r, float& h1i);
+
 // H0, H1 at k r with r given in FP64; result in FP32.
 template <bool CPLX, bool MEM = false>
 __device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveConst32& W, double r, cf& h0, cf& h1)
 {
+    // one write of h0, h1 after the join (as in hankel01)
+    float h0r, h0i, h1r, h1i;
     if (r * r < (double)W.r2_small) {
         const double r2 = r * r, rinv = 1.0 / r, sr = sqrt(rinv);
         cd a0, a1;
         hankel01<CPLX, MEM>(W64, r, r2, rinv, sr, a0, a1);
-        h0 = {(float)a0.re, (float)a0.im};
-        h1 = {(float)a1.re, (float)a1.im};
-        return;
+        h0r = (float)a0.re;
+        h0i = (float)a0.im;
+        h1r = (float)a1.re;
+        h1i = (float)a1.im;
+    } else {
+        hankel_far32_body<CPLX>(W64, W, r, h0r, h0i, h1r, h1i);
     }
+    h0 = {h0r, h0i};
+    h1 = {h1r, h1i};
+}
+
+// The large-argument branch of hankel01_mixed.
+template <bool CPLX>
+__device__ __forceinline__ void hankel_far32_body(const WaveConst& W64, const WaveConst32& W, double r, float& h0r,
+                                                  float& h0i, float& h1r, float& h1i)
+{
+    cf h0, h1;
     constexpr double TWO_PI = 6.283185307179586476925;
     constexpr double INV_TWO_PI = 0.159154943091895335769;
     const double ph = W64.kr * r;
@@ -474,6 +493,10 @@ __device__ __forceinline__ void hankel01_mixed(const WaveConst& W64, const WaveC
         h0 = cmulf(cmulf(e, {W.a0r, W.a0i}), {m0.re - un0.im, m0.im + un0.re});
         h1 = cmulf(cmulf(e, {W.a1r, W.a1i}), {m1.re - un1.im, m1.im + un1.re});
     }
+    h0r = h0.re;
+    h0i = h0.im;
+    h1r = h1.re;
+    h1i = h1.im;
 }
 
 // FP32 large-argument form for |k r| >= XS_F32 (no series, no per-lane

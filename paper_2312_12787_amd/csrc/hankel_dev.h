@@ -182,6 +182,11 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
     if (MEM) T = hankel_tabs_fresh();
     constexpr double TWO_OVER_PI = 0.63661977236758134308;
     constexpr double EULER = 0.57721566490153286061;
+    // both branches set these scalars and h0, h1 are written once after the
+    // join: stores to different fields at the ends of the two branches would
+    // be merged into one store through a selected address, which keeps the
+    // caller's h0, h1 in scratch memory
+    double h0r, h0i, h1r, h1i;
     if (r2 < W.r2_small) {
         const double lnr = log(r);
         if (!CPLX) {
@@ -194,8 +199,10 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
             const double lz = lnr + W.lkr;
             const double y0 = fma(TWO_OVER_PI * (lz + EULER), j0, e0);
             const double y1 = fma(W.y1r, rinv, fma(TWO_OVER_PI * lz, j1, zh * e1));
-            h0 = {j0, y0};
-            h1 = {j1, y1};
+            h0r = j0;
+            h0i = y0;
+            h1r = j1;
+            h1i = y1;
         } else {
             const double x = W.tr * r2, y = W.ti * r2;
             const double R = 2.0 * x, S = fma(x, x, y * y);
@@ -221,12 +228,21 @@ __device__ __forceinline__ void hankel01(const WaveConst& W, double r, double r2
             const cd lz = {lnr + W.lkr, W.lki};
             const cd y0 = cadd(cmul({TWO_OVER_PI * (lz.re + EULER), TWO_OVER_PI * lz.im}, j0), e0);
             const cd y1 = cadd(cadd(cscale({W.y1r, W.y1i}, rinv), cmul(cscale(lz, TWO_OVER_PI), j1)), cmul(zh, e1));
-            h0 = {j0.re - y0.im, j0.im + y0.re};
-            h1 = {j1.re - y1.im, j1.im + y1.re};
+            h0r = j0.re - y0.im;
+            h0i = j0.im + y0.re;
+            h1r = j1.re - y1.im;
+            h1i = j1.im + y1.re;
         }
     } else {
-        hankel_asym<CPLX, true>(W, r, rinv, srinv, h0, h1);
+        cd a0, a1;
+        hankel_asym<CPLX, true>(W, r, rinv, srinv, a0, a1);
+        h0r = a0.re;
+        h0i = a0.im;
+        h1r = a1.re;
+        h1i = a1.im;
     }
+    h0 = {h0r, h0i};
+    h1 = {h1r, h1i};
 }
 
 // H1 only (end-point terms of the hypersingular operator).
