@@ -1,0 +1,42 @@
+"""Host-side parts of bench.py (no GPU): the refusal of more than one GPU, the
+CPU oracle worker of the multi-core baseline, and the modelled oracle time
+of a bounded sample."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BENCH = os.path.join(ROOT, "bench.py")
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = subprocess.run([sys.executable, BENCH, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_cpu_worker_prints_its_modelled_time():
+    core = sorted(os.sched_getaffinity(0))[0]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, BENCH, "--cpu-worker", "--workload", "disk256", "--cpu-iters", "16",
+                        "--cpu-core", str(core)], capture_output=True, text=True, timeout=300, env=env)
+    assert p.returncode == 0, p.stderr[-500:]
+    rec = json.loads(p.stdout.strip().splitlines()[-1])
+    assert rec["core"] == core
+    assert rec["t_total"] > 0.0 and rec["spent"] > 0.0
+
+
+def test_oracle_sample_scales_with_the_product_count():
+    """The modelled time grows with the number of products the GPU solve
+    used (one timed product per case, scaled by the count)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    wl = W.workload_disk256()
+    t1, spent1, rows, mv = bench.oracle_sample(wl, [1])
+    t100, _, _, _ = bench.oracle_sample(wl, [400])
+    assert rows == wl.problems[0].order and mv == wl.problems[0].order
+    assert t100 > t1 > 0.0 and spent1 > 0.0
