@@ -193,7 +193,9 @@ typedef struct {
                            kernels and order as 0, hence the same X.  The graphs keep the
                            matrix, work buffer, nrhs, restart, max_iter and product launch
                            shapes they were captured with; a call that changes any of
-                           them captures again.  Ignored while bem_profile_enable is on. */
+                           them (the tuned-shape table included; the BEM_MV_CFG
+                           environment overrides are read at capture only) captures
+                           again.  Ignored while bem_profile_enable is on.           */
 } bem_solve_opts;
 
 typedef struct {
