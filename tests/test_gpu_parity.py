@@ -213,6 +213,39 @@ def test_kite4096_block_solve_residuals_against_oracle_rows():
     assert np.abs(res).max() < 1e-7 * scale.min()
 
 
+@pytest.mark.parametrize("tuned", [False, True], ids=["built-in shape", "tuned shape"])
+def test_kite4096_block_product_sampled_rows(tuned):
+    """The benchmark's dominant kernel at full size: Y = A X for the 8192 x
+    8192 FP64 kite matrix and 16 right-hand sides (one pass of the matrix-core
+    product), in the built-in and in the autotuned launch shape.  Ten sampled
+    rows of Y (first / last / ragged row tiles of both equation blocks)
+    against the same rows of the GPU's matrix times X, which isolates the
+    product (1e-13 of the largest sampled entry), and against the oracle's
+    rows times X, which adds the assembly difference (1e-10)."""
+    P = _gpu()
+    P.tune_reset()
+    try:
+        spec = W.kite(4096, 20.0, 30.0)
+        g = P.Problem(spec)
+        A_t = g.assemble(P.F64)
+        rng = np.random.default_rng(11)
+        X = rng.standard_normal((g.n, 16)) + 1j * rng.standard_normal((g.n, 16))
+        Xt = torch.as_tensor(X.T.copy(), device="cuda")
+        if tuned:
+            _say("tuned", g.tune(16, reps=2, X=Xt))
+        Y = g.matvec(Xt).cpu().numpy().T
+        rows = np.array([0, 127, 128, 2048, 4095, 4096, 5555, 6143, 8064, 8191], dtype=np.int32)
+        Ag = A_t[:, torch.as_tensor(rows, device=A_t.device).long()].T.cpu().numpy()
+        ref = Ag @ X
+        err = np.abs(Y[rows] - ref).max() / np.abs(ref).max()
+        Ao = O.Problem(spec).assemble_rows(rows)
+        err_o = np.abs(Y[rows] - Ao @ X).max() / np.abs(ref).max()
+        _say("kite4096 product, tuned" if tuned else "kite4096 product", "vs GPU rows", err, "vs oracle rows", err_o)
+        assert err < 1e-13 and err_o < 1e-10
+    finally:
+        P.tune_reset()
+
+
 def test_profile_counts_assembly_products_and_residuals():
     """The library's kernel timing tallies every assembly, product and
     residual launch of a solve (FP64 and mixed), and a reset clears it."""
