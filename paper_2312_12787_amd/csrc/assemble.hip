@@ -14,13 +14,19 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr double EULER = 0.57721566490153286061;
-// Assembly kernels: minimum waves per SIMD of the far-element launch (the
-// near-element launch reads its coefficients by scalar loads and runs two)
-// and Gauss points unrolled together (measured on gfx950, kite of 4096
+// Assembly kernels: minimum waves per SIMD of the far-element and of the
+// near-element launch (the latter reads its series coefficients by scalar
+// loads) and Gauss points unrolled together (measured on gfx950, kite of 4096
 // elements: one Gauss point at a time is 6 % faster than two in FP64, equal
-// in FP32; four waves per SIMD no faster than two).
+// in FP32, and unrolling the near-element loop by 2 or 8 gains nothing; four
+// waves per SIMD no faster than two; a third near-element wave makes the
+// complex Burton-Miller variant spill).  The source elements per near-element
+// workgroup, NEAR_PART, are set with the shared layout constants.
 #ifndef ASM_FAR_WAVES
 #define ASM_FAR_WAVES 2
+#endif
+#ifndef ASM_NEAR_WAVES
+#define ASM_NEAR_WAVES 2
 #endif
 #ifndef ASM_GAUSS_UNROLL
 #define ASM_GAUSS_UNROLL 1
@@ -800,7 +806,7 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f64(const 
 }
 
 template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, 2) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
+__global__ __launch_bounds__(ROW_TILE, ASM_NEAR_WAVES) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
                                                                    int n_if, int q_rt, const int* __restrict__ pairs,
                                                                    int side, double2* __restrict__ A, size_t lda,
                                                                    float2* __restrict__ A32, size_t lda32)
@@ -824,7 +830,7 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f32(const 
 }
 
 template <int Q, bool CPLX, bool BM>
-__global__ __launch_bounds__(ROW_TILE, 2) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
+__global__ __launch_bounds__(ROW_TILE, ASM_NEAR_WAVES) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
                                                                    int n_if, int q_rt, const int* __restrict__ pairs,
                                                                    int side, float2* __restrict__ A, size_t lda)
 {

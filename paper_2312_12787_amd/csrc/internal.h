@@ -14,7 +14,10 @@ namespace bemk {
 constexpr int QMAX = 16;      // largest Gauss rule
 constexpr int ROW_TILE = 256; // collocation rows per assembly workgroup
 constexpr int COL_CHUNK = 32; // source elements per assembly workgroup
-constexpr int NEAR_PART = 8;  // source elements per workgroup of the near-element launch
+#ifndef ASM_NEAR_PART
+#define ASM_NEAR_PART 4  // 2.24 ms against 2.36 ms at 8 and 2.51 ms at 16 (FP64 kite of 4096 elements)
+#endif
+constexpr int NEAR_PART = ASM_NEAR_PART;  // source elements per workgroup of the near-element launch
 // |k r| below which the device Hankel evaluator uses the ascending series
 // (FP64 and FP32 amplitude paths; the same values as in hankel_tables.h)
 constexpr double XS_SERIES_F64 = 6.0, XS_SERIES_F32 = 4.0;
