@@ -858,10 +858,12 @@ hipError_t launch_setup(char* g, const GeomLayout& L, int N, int n_dom, int q, h
 template <class T2, bool F64, int Q>
 void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                      const int* const* lists, const int* counts, const int* const* pairs, const int* pair_counts,
-                     T2* A, size_t lda, float2* A32, size_t lda32, hipStream_t s)
+                     T2* A, size_t lda, float2* A32, size_t lda32, hipStream_t s0, hipStream_t s1)
 {
+    int k = 0;  // variants write disjoint rows: alternate them over the two streams
     for (int v = 0; v < ASM_VARIANTS; ++v) {
         if (counts[v] == 0) continue;
+        const hipStream_t s = (k++ & 1) ? s1 : s0;
         const int side = v >> 2 & 1, bm = v >> 1 & 1, cplx = v & 1;
         const dim3 grid(counts[v], n_cchunks, 1), ngrid(pair_counts[v], 1, 1);
 #define BEM_ASM_LAUNCH(C_, B_)                                                                                    \
@@ -891,33 +893,33 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                                const int* const* lists, const int* counts, const int* const* pairs,
                                const int* pair_counts, double2* A, size_t lda, float2* A32, size_t lda32,
-                               hipStream_t s)
+                               hipStream_t s, hipStream_t s1)
 {
     if (q == 8)
         launch_variants<double2, true, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda, A32,
-                                          lda32, s);
+                                          lda32, s, s1);
     else if (q == 10)
         launch_variants<double2, true, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
-                                           A32, lda32, s);
+                                           A32, lda32, s, s1);
     else
         launch_variants<double2, true, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda, A32,
-                                          lda32, s);
+                                          lda32, s, s1);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                                const int* const* lists, const int* counts, const int* const* pairs,
-                               const int* pair_counts, float2* A, size_t lda, hipStream_t s)
+                               const int* pair_counts, float2* A, size_t lda, hipStream_t s, hipStream_t s1)
 {
     if (q == 8)
         launch_variants<float2, false, 8>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
-                                          nullptr, 0, s);
+                                          nullptr, 0, s, s1);
     else if (q == 10)
         launch_variants<float2, false, 10>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
-                                           nullptr, 0, s);
+                                           nullptr, 0, s, s1);
     else
         launch_variants<float2, false, 0>(g, L, N, n_if, n_cchunks, q, lists, counts, pairs, pair_counts, A, lda,
-                                          nullptr, 0, s);
+                                          nullptr, 0, s, s1);
     return hipGetLastError();
 }
 

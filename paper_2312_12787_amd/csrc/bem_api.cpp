@@ -126,6 +126,8 @@ struct bem_problem {
         unsigned gen = 0;
     } graphs;
     hipStream_t cap = nullptr;  // private stream the segments are captured on (never runs work)
+    hipStream_t asm_side = nullptr;       // second stream of the assembly launches
+    hipEvent_t asm_ev[2] = {};            // its fork and join events
     // device state recorded by the calls
     char* geom = nullptr;
     void* A = nullptr;      // FP64 or FP32 matrix (BEM_MIXED: the FP64 one)
@@ -491,6 +493,9 @@ void bem_destroy(bem_problem* p)
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
     drop_graphs(p);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    for (hipEvent_t e : p->asm_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->asm_side) (void)hipStreamDestroy(p->asm_side);
     if (!p->lent) {
         for (hipEvent_t e : p->flag_ev)
             if (e) (void)hipEventDestroy(e);
@@ -620,12 +625,30 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
     float2* A32 = prec == BEM_MIXED ? reinterpret_cast<float2*>(static_cast<char*>(A_dev) + mixed_offset(n, lda))
                                     : nullptr;
+    // The equation-block variants write disjoint rows, so every second one
+    // runs on the problem's side stream (forked from the caller's stream and
+    // joined back below): one variant's launches fill the other's tails.
+    int nvar = 0;
+    for (int v = 0; v < bemk::ASM_VARIANTS; ++v) nvar += p->vcount[v] > 0;
+    hipStream_t side = stream;
+    if (nvar >= 2) {
+        if (!p->asm_side) HIP_OK(hipStreamCreateWithFlags(&p->asm_side, hipStreamNonBlocking));
+        for (hipEvent_t& e : p->asm_ev)
+            if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_OK(hipEventRecord(p->asm_ev[0], stream));
+        HIP_OK(hipStreamWaitEvent(p->asm_side, p->asm_ev[0], 0));
+        side = p->asm_side;
+    }
     if (prec == BEM_F32)
         HIP_OK(bemk::launch_assemble_f32(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount, pairs,
-                                         p->ncount, static_cast<float2*>(A_dev), lda, stream));
+                                         p->ncount, static_cast<float2*>(A_dev), lda, stream, side));
     else
         HIP_OK(bemk::launch_assemble_f64(p->geom, p->L, p->N, p->n_if, ncc, p->quad, lists, p->vcount, pairs,
-                                         p->ncount, static_cast<double2*>(A_dev), lda, A32, lda, stream));
+                                         p->ncount, static_cast<double2*>(A_dev), lda, A32, lda, stream, side));
+    if (side != stream) {
+        HIP_OK(hipEventRecord(p->asm_ev[1], side));
+        HIP_OK(hipStreamWaitEvent(stream, p->asm_ev[1], 0));
+    }
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 1, stream);
     p->A = A_dev;
     p->A32 = A32;

@@ -34,13 +34,14 @@ constexpr int ASM_VARIANTS = 8;
 // lists[v] / counts[v]: row tiles of variant v (device list / host count);
 // pairs[v] / pair_counts[v]: its (row tile, column chunk, part of NEAR_PART
 // elements) triples that may hold near element pairs (device list / host count).
+// Variants go alternately to s and s1 (they write disjoint rows; s1 may be s).
 hipError_t launch_assemble_f64(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                                const int* const* lists, const int* counts, const int* const* pairs,
                                const int* pair_counts, double2* A, size_t lda, float2* A32, size_t lda32,
-                               hipStream_t s);
+                               hipStream_t s, hipStream_t s1);
 hipError_t launch_assemble_f32(const char* g, const GeomLayout& L, int N, int n_if, int n_cchunks, int q,
                                const int* const* lists, const int* counts, const int* const* pairs,
-                               const int* pair_counts, float2* A, size_t lda, hipStream_t s);
+                               const int* pair_counts, float2* A, size_t lda, hipStream_t s, hipStream_t s1);
 
 // angles / dirs are HOST arrays: they travel to the kernels by value in
 // chunks of ANGLE_CHUNK.
