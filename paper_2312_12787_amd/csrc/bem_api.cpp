@@ -10,6 +10,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -631,7 +632,11 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
     int nvar = 0;
     for (int v = 0; v < bemk::ASM_VARIANTS; ++v) nvar += p->vcount[v] > 0;
     hipStream_t side = stream;
-    if (nvar >= 2) {
+    static const bool one_stream = [] {
+        const char* e = getenv("BEM_ASM_ONE_STREAM");  // measurement switch: every variant on the caller's stream
+        return e && e[0] == '1';
+    }();
+    if (nvar >= 2 && !one_stream) {
         if (!p->asm_side) HIP_OK(hipStreamCreateWithFlags(&p->asm_side, hipStreamNonBlocking));
         for (hipEvent_t& e : p->asm_ev)
             if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
