@@ -597,7 +597,9 @@ def main():
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-steps", type=int, default=0,
-                    help="Krylov steps per captured HIP graph in the solves (0: kernel-by-kernel launches)")
+                    help="Krylov steps per captured HIP graph in the solves (0: kernel-by-kernel launches); "
+                         "takes effect in the serve workload; the full mode times kernels with the library's "
+                         "events, which keeps kernel-by-kernel launches (--mode graphs compares both)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuning (bem_tune) before timing")
     ap.add_argument("--tune-file", default=None,
                     help="launch-shape table: imported if the file exists, else written after tuning "
