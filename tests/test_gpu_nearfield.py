@@ -122,3 +122,28 @@ def test_incident_wave_is_added_at_host_points_only():
     uin = np.exp(1j * 4.0 * (np.cos(ang)[:, None] * pts[None, :, 0] + np.sin(ang)[:, None] * pts[None, :, 1]))
     assert np.abs(Ut[:, :2] - Us[:, :2] - uin[:, :2]).max() < 1e-14
     assert np.array_equal(Ut[:, 2:], Us[:, 2:])
+
+
+def test_nearfield_full_size_bench_configuration_sampled_points():
+    """The benchmark's near-field workload at full size: unit disk as a
+    1024-gon (k0 = 5, eps2 = 2), the whole 101 x 101 grid of [-2.99, 2.99]^2
+    in one call, one incident angle.  The 40 grid points nearest the circle
+    (the near-singular and series regimes) and 40 random ones against the
+    oracle, with random boundary data (the operator, not a solution, is
+    under test)."""
+    P = _gpu()
+    spec = W.disk(1024, 5.0, 5.0 * np.sqrt(2.0))
+    rng = np.random.default_rng(21)
+    n = 2 * spec.n_elements
+    X = rng.standard_normal((n, 1)) + 1j * rng.standard_normal((n, 1))
+    pts = paper_grid(101)
+    dom = (np.hypot(pts[:, 0], pts[:, 1]) < 1.0).astype(np.int32)
+    g = P.Problem(spec)
+    g.geometry()
+    U = g.nearfield(torch.as_tensor(X.T.copy(), device="cuda"), pts, dom, angles=[0.0]).cpu().numpy().T
+    near = np.argsort(np.abs(np.hypot(pts[:, 0], pts[:, 1]) - 1.0))[:40]
+    pick = np.unique(np.concatenate([near, rng.choice(len(pts), 40, replace=False)]))
+    Uo = O.Problem(spec).nearfield(X, pts[pick], dom[pick], angles=[0.0])
+    err = np.abs(U[pick] - Uo).max() / np.abs(Uo).max()
+    print("full-size grid, sampled points", len(pick), "max error / max|U|", err, flush=True)
+    assert err < 1e-9
