@@ -63,8 +63,12 @@ __device__ __forceinline__ double r2log_integral(double u0, double u1, double xn
     return F(u1) - F(u0);
 }
 
+// The Gauss points of the element are formed here from its midpoint, tangent
+// and length and the shared rule (as the geometry tables form them): lanes
+// take different elements, and reading per-element point tables would cost
+// one scattered load per point and coordinate.
 template <bool CPLX>
-__device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, const ElemRec& E, const GaussRec& G,
+__device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, const ElemRec& E,
                                                   const double* __restrict__ gl, int q, double x, double y, cd& S,
                                                   cd& D)
 {
@@ -78,14 +82,16 @@ __device__ __forceinline__ void element_integrals(const WaveConst& W, cd k, cons
     S = {0.0, 0.0};
     D = {0.0, 0.0};
     if (dist >= 2.0 * h) {
+        const double cx = E.cx, cy = E.cy, tx = E.tx, ty = E.ty, hh = 0.5 * h;
         for (int g = 0; g < q; ++g) {
-            const double rx = x - G.x[g], ry = y - G.y[g];
+            const double sg = hh * gl[g];
+            const double rx = x - (cx + sg * tx), ry = y - (cy + sg * ty);
             const double r2 = fma(rx, rx, ry * ry);
             double r, rinv;
             sqrt_rsqrt(r2, r, rinv);
             cd h0, h1;
             hankel01<CPLX, true>(W, r, r2, rinv, rsqrt_nr(r), h0, h1);
-            const double wg = G.w[g];
+            const double wg = hh * gl[QMAX + g];
             S.re = fma(wg, h0.re, S.re);
             S.im = fma(wg, h0.im, S.im);
             const double wd = wg * (rx * E.nx + ry * E.ny) * rinv;
@@ -167,7 +173,6 @@ __global__ __launch_bounds__(NF_BS, 2) void k_nearfield(const char* __restrict__
     const cd k = {Dm.k[0], Dm.k[1]};
     const cd eps = {Dm.eps[0], Dm.eps[1]};
     const ElemRec* el = tab<ElemRec>(g, L.elem);
-    const GaussRec* gq = tab<GaussRec>(g, L.gauss);
     const double* gl = tab<double>(g, L.gl);
     cd acc[NF_RB];
 #pragma unroll
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(NF_BS, 2) void k_nearfield(const char* __restrict__
         for (int e = lane; e < P.count; e += 64) {
             const int j = P.off + e;
             cd S, D;
-            element_integrals<CPLX>(W, k, el[j], gq[j], gl, q, x, y, S, D);
+            element_integrals<CPLX>(W, k, el[j], gl, q, x, y, S, D);
             const cd eS = cscale(cmul(eps, S), (double)sg);
             const cd sD = cscale(D, (double)sg);
 #pragma unroll
