@@ -262,3 +262,46 @@ def test_profile_counts_assembly_products_and_residuals():
         assert pr["residual_launches"] >= 1 and pr["residual_ms"] > 0
         assert g.profile_read(reset=True)["matvec_launches"] == 0
         g.profile(False)
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "F32"])
+def test_padded_leading_dimension_same_matrix_and_solution(prec_name):
+    """Columns padded to a 128-byte multiple (how the benchmark stores
+    matrices whose order is not a multiple of 8 or 16): the same entries,
+    and the same solves through both product paths (one right-hand side:
+    vector product; six: matrix cores), which match the oracle's LU solution."""
+    P = _gpu()
+    prec = getattr(P, prec_name)
+    spec = W.kite(151, 5.0, 7.5 + 0.1j)
+    g = P.Problem(spec)
+    n = g.n
+    assert n % 8 != 0
+    ld = (n + 15) // 16 * 16
+    dt = torch.complex128 if prec == P.F64 else torch.complex64
+    A0 = g.assemble(prec).clone()
+    A1 = torch.full((n, ld), complex(7.0, -7.0), dtype=dt, device="cuda")
+    tol = 1e-12 if prec == P.F64 else 1e-8
+    po = O.Problem(spec)
+    Ao = po.assemble()
+    for ang in ([0.4], [0.1 * r for r in range(6)]):
+        g.assemble(prec, out=A0.clone())
+        B = g.rhs(ang)
+        X0, i0 = g.solve(B, restart=60, tol=tol)
+        X0 = X0.clone()
+        g.assemble(prec, out=A1, lda=ld)
+        torch.cuda.synchronize()
+        assert torch.equal(A1[:, :n], A0)
+        assert bool((A1[:, n:] == complex(7.0, -7.0)).all())  # padding untouched
+        X1, i1 = g.solve(B, restart=60, tol=tol)
+        torch.cuda.synchronize()
+        _say(prec_name, "nrhs", len(ang), "iters", i0.iters.tolist(), i1.iters.tolist())
+        assert np.array_equal(i1.iters, i0.iters) and i1.converged.all()
+        assert float((X1 - X0).abs().max()) <= 1e-12 * float(X0.abs().max())
+        Xo = O.lu_solve(Ao, po.rhs(ang))
+        assert rel_err(X1.cpu().numpy().T, Xo) < (1e-9 if prec == P.F64 else 1e-4)
+        Xm = X1 if prec == P.F64 else X1.to(torch.complex64)
+        Y0 = g.matvec(Xm).clone()
+        g.assemble(prec, out=A0.clone())
+        Y1 = g.matvec(Xm)
+        torch.cuda.synchronize()
+        assert float((Y1 - Y0).abs().max()) <= 1e-13 * float(Y0.abs().max())
