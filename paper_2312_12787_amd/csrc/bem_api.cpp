@@ -555,10 +555,7 @@ bem_status bem_sizes(const bem_problem* p, int prec, int nrhs, int restart, size
     if (restart < 1 || restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
     const size_t n = 2 * (size_t)p->N;
     if (geom_bytes) *geom_bytes = p->L.total;
-    if (matrix_bytes)
-        *matrix_bytes = prec == BEM_F64 ? n * n * sizeof(double2)
-                        : prec == BEM_F32 ? n * n * sizeof(float2)
-                                          : mixed_offset(n, n) + n * n * sizeof(float2);
+    if (matrix_bytes) *matrix_bytes = bemk::matrix_bytes_ld(prec, n, n);
     if (work_bytes) *work_bytes = make_work((int)n, nrhs, restart).total;
     return BEM_OK;
 }
@@ -1231,6 +1228,15 @@ bem_status bem_nearfield(const bem_problem* p, int nrhs, const void* X_dev, size
 }  // extern "C"
 
 namespace bemk {
+
+// Bytes of a matrix buffer of order n with leading dimension lda (the
+// BEM_MIXED buffer holds the FP64 matrix, then its FP32 copy, same lda).
+size_t matrix_bytes_ld(int prec, size_t n, size_t lda)
+{
+    return prec == BEM_F64   ? lda * n * sizeof(double2)
+           : prec == BEM_F32 ? lda * n * sizeof(float2)
+                             : mixed_offset(n, lda) + lda * n * sizeof(float2);
+}
 
 // The request server keeps one pinned flag buffer and FLAG_RING events per slot and
 // lends them to each problem it runs, so that no request allocates or frees

@@ -119,6 +119,10 @@ struct ArnoldiArgs {
     bool v32;                      // basis stored as complex64 at V (same element offsets), else complex128
 };
 hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s);
+
+// Host side (bem_api.cpp): bytes of a matrix buffer of order n and leading
+// dimension lda in precision prec (a bem_prec value).
+size_t matrix_bytes_ld(int prec, size_t n, size_t lda);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
                               double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,

@@ -100,6 +100,7 @@ struct Request {
     int n = 0, nrhs = 0;
     std::vector<double> angles;
     bem_z* out = nullptr;
+    size_t lda = 0;  // leading dimension of the matrix (n rounded up to 16)
     size_t geom = 0, mat = 0, work = 0, vec = 0, far = 0, footprint = 0;
     double t_submit = 0, t_admit = 0;
     int passed_over = 0;
@@ -143,6 +144,11 @@ struct bem_server {
         size_t g = 0, m = 0, w = 0;
         if (bem_status st = bem_sizes(r.p, (bem_prec)o.prec, r.nrhs, o.solve.restart, &g, &m, &w)) return st;
         r.n = bem_order(r.p);
+        // columns start on 128-byte lines (16 complex64 / 8 complex128
+        // entries): an unaligned start costs the products one more cache
+        // line per column segment a workgroup reads
+        r.lda = ((size_t)r.n + 15) / 16 * 16;
+        m = bemk::matrix_bytes_ld(o.prec, (size_t)r.n, r.lda);
         r.geom = al(g);
         r.mat = al(m);
         r.work = al(w);
@@ -181,7 +187,7 @@ struct bem_server {
         std::vector<bem_solve_info> info((size_t)r->nrhs);
         bemk::lend_flag_buffers(r->p, sl.pinned, FLAG_INTS, sl.ev);
         bem_status st = bem_geometry(r->p, g, r->geom, sl.stream);
-        if (!st) st = bem_assemble(r->p, (bem_prec)o.prec, A, n, sl.stream);
+        if (!st) st = bem_assemble(r->p, (bem_prec)o.prec, A, r->lda, sl.stream);
         if (!st) st = bem_rhs(r->p, r->nrhs, r->angles.data(), B, n, sl.stream);
         bem_status solve_st = BEM_OK;
         if (!st) {
