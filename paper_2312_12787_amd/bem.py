@@ -251,7 +251,10 @@ class Problem:
     def assemble(self, prec: int = F64, out=None, lda: Optional[int] = None, stream=None):
         """Assemble into `out` (allocated if None) and return the matrix tensor.
         MIXED: `out` is a uint8 buffer of sizes(MIXED)[1] bytes holding the
-        FP64 matrix and its FP32 copy; the FP64 part is returned."""
+        FP64 matrix and its FP32 copy; the FP64 part is returned.  F64 / F32:
+        `out` is (n, lda) (column-major, lda >= n); an lda that is a multiple
+        of 8 (complex128) or 16 (complex64) entries starts every column on a
+        128-byte line, which the products read faster when n is not one."""
         import torch
         if self.geom is None:
             self.geometry(stream)
