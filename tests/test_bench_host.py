@@ -40,3 +40,22 @@ def test_oracle_sample_scales_with_the_product_count():
     t100, _, _, _ = bench.oracle_sample(wl, [400])
     assert rows == wl.problems[0].order and mv == wl.problems[0].order
     assert t100 > t1 > 0.0 and spent1 > 0.0
+
+
+def test_benchmark_matrices_have_128_byte_aligned_columns():
+    """padded_ld rounds the order up to 8 complex128 / 16 complex64 entries
+    and leaves multiples alone."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class P:  # precision constants as the binding defines them
+        F64, F32 = 0, 1
+
+    assert bench.padded_ld(14970, P.F64, P) == 14976
+    assert bench.padded_ld(8192, P.F64, P) == 8192
+    assert bench.padded_ld(602, P.F32, P) == 608
+    assert bench.padded_ld(32768, P.F32, P) == 32768
+    for n in range(1, 200):
+        for prec, per, esz in ((P.F64, 8, 16), (P.F32, 16, 8)):
+            ld = bench.padded_ld(n, prec, P)
+            assert n <= ld < n + per and (ld * esz) % 128 == 0
