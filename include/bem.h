@@ -159,7 +159,12 @@ bem_status bem_geometry_update(bem_problem *p, hipStream_t stream);
  * in precision prec (BEM_F64: complex128; BEM_F32: complex64 entries, with
  * self terms computed in FP64 and rounded; BEM_MIXED: complex128 and its
  * complex64 rounding, layout under bem_prec).  Requires bem_geometry.  The
- * problem records A_dev, lda and prec for bem_matvec / bem_solve.           */
+ * problem records A_dev, lda and prec for bem_matvec / bem_solve.  An lda
+ * whose columns start on 128-byte lines (a multiple of 8 entries for
+ * complex128, 16 for complex64) lets the products read each column segment
+ * without a partial line; a buffer with lda > n needs lda / n times the
+ * bem_sizes matrix bytes (for BEM_MIXED: the FP64 part, rounded up to 256
+ * bytes, then lda * n complex64).                                           */
 bem_status bem_assemble(bem_problem *p, int prec, void *A_dev, size_t lda, hipStream_t stream);
 
 /* Right-hand sides of the plane waves exp(i k0 (cos th, sin th) . x), one per
