@@ -120,9 +120,12 @@ typedef struct {
  * bem_destroy.  BEM_E_GEOMETRY: too few nodes, a zero-length element, an
  * unknown or repeated domain id, the host medium on the normal's side, or
  * |1 + eps_left/eps_right| < 1e-12 (accumulation point at 0, end of Sec. 5).
- * BEM_E_ARG: k[0] not real-positive, Im k < 0, quad out of range, or max |k|
- * times the diameter of the nodes' bounding box >= 2^29 (the device reduces
- * phases k r by pi/2 exactly only below 2^30).                              */
+ * BEM_E_ARG: k[0] not real-positive, Im k < 0, a lossy wavenumber with
+ * arg k > 10 degrees (Im k > tan(10 deg) Re k: the device's large-argument
+ * Hankel form continues real-axis amplitude fits to complex arguments, with a
+ * relative error of 1e-14 at arg k = 3.2 deg and 1.7e-12 at 10 deg), quad out
+ * of range, or max |k| times the diameter of the nodes' bounding box >= 2^29
+ * (the device reduces phases k r by pi/2 exactly only below 2^30).           */
 bem_status bem_create(const bem_desc *desc, bem_problem **out);
 void bem_destroy(bem_problem *p);
 

@@ -22,6 +22,8 @@ constexpr int NEAR_PART = ASM_NEAR_PART;  // source elements per workgroup of th
 // (FP64 and FP32 amplitude paths; the same values as in hankel_tables.h)
 constexpr double XS_SERIES_F64 = 6.0, XS_SERIES_F32 = 4.0;
 constexpr int MAX_DIRS = 4096;
+// Largest Im k / Re k of a lossy medium: tan(10 degrees).
+constexpr double MAX_TAN_ARG_K = 0.17632698070846498;
 
 // One boundary element (128 bytes).  Normal = left normal of the travel
 // direction a -> b.

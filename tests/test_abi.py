@@ -86,8 +86,8 @@ def test_create_validation_errors():
     cases.append((s, "BEM_E_GEOMETRY"))
     s = W.single_material(W.circle_nodes(2), 1.0, 2.0)
     cases.append((s, "BEM_E_GEOMETRY"))
-    s = W.disk(16, 1.0, 1.0j)  # eps = -1: accumulation point at 0
-    cases.append((s, "BEM_E_GEOMETRY"))
+    s = W.disk(16, 1.0, 1.0j)  # eps = -1 (accumulation point at 0) needs arg k = 90 deg: refused as such
+    cases.append((s, "BEM_E_ARG"))
     s = W.disk(16, 1.0, 2.0, quad=17)
     cases.append((s, "BEM_E_ARG"))
     s = W.disk(16, 1.0, 2.0)
@@ -169,3 +169,17 @@ def test_phase_range_is_checked_on_the_host():
     _problem(W.disk(16, 1.0e8, 1.8e8))  # 5.09e8: accepted
     with pytest.raises(P.BemError, match="2\\^29"):
         _problem(W.disk(16, 1.0e8, 2.0e8))  # 5.66e8
+
+
+def test_lossy_wavenumber_argument_is_bounded_on_the_host():
+    """bem_create accepts lossy media up to arg k = 10 degrees (the device's
+    large-argument Hankel form is validated to 1.7e-12 there) and refuses a
+    larger argument with BEM_E_ARG."""
+    import paper_2312_12787_amd as P
+    t10 = np.tan(np.deg2rad(10.0))
+    _problem(W.disk(16, 1.0, 30.0 + 0.3j))
+    _problem(W.disk(16, 1.0, 30.0 * (1.0 + 0.999999 * t10 * 1j)))
+    _problem(W.sectors([10.0, 12.0, 18.0, 9.0 + 0.5j], h=1 / 10))
+    for k1 in (30.0 * (1.0 + 1.000001 * t10 * 1j), 2.0 + 2.0j, -1.0 + 0.1j):
+        with pytest.raises(P.BemError, match="arg k"):
+            _problem(W.disk(16, 1.0, k1))

@@ -192,7 +192,8 @@ def test_state_errors():
 
 def test_kite4096_block_solve_residuals_against_oracle_rows():
     """Full-size benchmark case: 16 angles, GMRES(100) to 1e-10.  The GPU
-    residual claim is checked on 8 sampled rows of the oracle's own matrix."""
+    residual claim is checked on 8 sampled rows of the oracle's own matrix,
+    each against the root-mean-square of its right-hand side."""
     P = _gpu()
     spec = W.kite(4096, 20.0, 30.0)
     g = P.Problem(spec)
@@ -208,9 +209,13 @@ def test_kite4096_block_solve_residuals_against_oracle_rows():
     Bo = po.rhs(ang)
     Xn = X.cpu().numpy().T
     res = Bo[rows] - Ar @ Xn
-    scale = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
-    _say("sampled residual / rms(b)", np.abs(res).max() / scale.min())
-    assert np.abs(res).max() < 1e-7 * scale.min()
+    rms_b = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
+    rr = float(np.max(np.abs(res) / rms_b))
+    _say("sampled residual / rms(b)", rr)
+    # ||r|| <= 1e-10 ||b|| bounds the rms of the residual rows by 1e-10 rms(b);
+    # 2e-9 rms(b) allows the largest of 8192 rows 20 times that (the matrices
+    # differ by < 1e-13 of the largest entry, far below it)
+    assert rr < 2e-9
 
 
 @pytest.mark.parametrize("tuned", [False, True], ids=["built-in shape", "tuned shape"])

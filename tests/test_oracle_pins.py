@@ -40,12 +40,16 @@ def test_gauss_legendre_exact_on_polynomials(q):
 HANKEL_POINTS = [1e-5, 1e-3, 0.05, 0.7, 1.0, 3.3, 6.0, 7.999, 8.001, 11.0, 17.5, 24.99, 25.01,
                  37.0, 90.0, 420.0, 2 + 0.4j, 7.9 + 1.0j, 8.1 + 0.2j, 14 + 0.9j, 24 + 2j, 30 + 0.3j,
                  95 + 0.95j, 0.02 + 0.01j, 4.5 + 0.25j, 1e-3j + 1e-3]
+# the largest argument of a lossy wavenumber the library accepts (10 degrees), in every regime
+ARG10 = complex(np.cos(np.deg2rad(10.0)), np.sin(np.deg2rad(10.0)))
+HANKEL_POINTS += [r * ARG10 for r in (0.5, 5.0, 7.9, 8.1, 12.0, 24.9, 25.1, 60.0, 150.0)]
 
 
 @pytest.mark.parametrize("z", HANKEL_POINTS)
 def test_hankel_against_mpmath(z):
-    """H0^(1), H1^(1) against mpmath at 30 digits (library used as a black box)."""
-    mpmath.mp.dps = 30
+    """H0^(1), H1^(1) against mpmath at 60 digits (library used as a black box;
+    the digits cover the cancellation between J and Y at Im z up to 26)."""
+    mpmath.mp.dps = 60
     h0, h1 = O.hankel01(z)
     r0 = complex(mpmath.hankel1(0, z))
     r1 = complex(mpmath.hankel1(1, z))

@@ -286,3 +286,16 @@ def request_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 0, n_
                                name=f"req{i}")
         out.append(dict(arrival=float(t[i]), spec=spec, angles=angles))
     return out
+
+
+def stream_like_request(n: int, k0: float, ratio: float, nrhs: int, seed: int):
+    """One request shaped like those of request_stream (a perturbed circle
+    with a_m ~ U(0, 0.08), phi_m ~ U(0, 2 pi), nrhs angles ~ U(0, 2 pi)) with
+    its size and wavenumbers fixed by the caller, e.g. at the ends of the
+    stream's ranges."""
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.0, 0.08, size=5)
+    phases = rng.uniform(0.0, 2 * np.pi, size=5)
+    angles = rng.uniform(0.0, 2 * np.pi, size=nrhs)
+    spec = single_material(perturbed_circle_nodes(n, amps, phases), k0, k0 * ratio, name=f"req_n{n}_k{k0:g}")
+    return dict(arrival=0.0, spec=spec, angles=angles)
