@@ -87,16 +87,55 @@ def cpu_model():
     return None
 
 
-def oracle_sample(workload, gpu_iters, rows_per_case=None, start_at=None):
-    """Time the oracle (single thread) on a bounded sample of the workload:
-    strided matrix rows of each case (48 at N = 4096, fewer for larger N so
-    the sample stays near the same CPU time) and one product of at most
-    8192 x 8192; scaled to full assembly (rows x n), to the full product size
-    (n^2) and to the product count the GPU solve needed (sum of GMRES
-    iterations and restart residuals).  start_at: wall-clock time (time.time)
-    to wait for once the inputs are prepared, so that concurrent copies time
-    the same interval.  Returns (modelled seconds for the workload's solves,
-    seconds spent, rows per case, product size)."""
+def arnoldi_units(rhs_steps, restart, n):
+    """(basis vector x row) units of modified Gram-Schmidt that a GMRES(restart)
+    solve with these Krylov step counts (one per right-hand side) does: step j
+    of a cycle projects on j + 1 basis vectors of n rows."""
+    u = 0
+    for s in rhs_steps:
+        s = int(s)
+        while s > 0:
+            c = min(restart, s)
+            u += c * (c + 1) // 2
+            s -= c
+    return float(u) * n
+
+
+def arnoldi_unit_seconds():
+    """Seconds per (basis vector x row) unit of the oracle's Gram-Schmidt:
+    its GMRES(600) run for 600 steps on an order-1024 matrix (3 I plus a
+    scaled random matrix: no early stop), minus its 602 products timed alone
+    (the product is the same routine); 180 300 x 1024 units."""
+    import oracle as O
+    n, m = 1024, 600
+    rng = np.random.default_rng(0)
+    A = np.asfortranarray(3.0 * np.eye(n) + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+                          / np.sqrt(n))
+    b = np.ones(n, dtype=np.complex128)
+    x = np.ones(n, dtype=np.complex128)
+    O.matvec(A, x)
+    t0 = time.perf_counter()
+    for _ in range(40):
+        O.matvec(A, x)
+    t_mv = (time.perf_counter() - t0) / 40
+    t0 = time.perf_counter()
+    _, it, _, _ = O.gmres(A, b, m, 0.0, m)
+    T = time.perf_counter() - t0
+    units = m * (m + 1) / 2 * n
+    return max(0.0, T - (it + 2) * t_mv) / units, T + 40 * t_mv
+
+
+def oracle_sample(workload, products, arn_units, rows_per_case=None, start_at=None):
+    """Time the oracle (single thread) on a bounded sample of the workload and
+    model its whole solve from it: strided matrix rows of each case (48 at
+    N = 4096, fewer for larger N) scaled to the full assembly, one product of
+    at most 8192 x 8192 scaled to the full product size and to the products
+    the GPU solve needed (GMRES steps and restart residuals), and the
+    Gram-Schmidt work of those steps (arnoldi_unit_seconds x arn_units).
+    start_at: wall-clock time (time.time) to wait for once the inputs are
+    prepared, so that concurrent copies time the same interval.  Returns
+    (modelled seconds for the workload's solves, seconds spent, rows per
+    case, product size, seconds per Gram-Schmidt unit)."""
     import oracle as O
     cases = []
     for spec in workload.problems:
@@ -112,9 +151,9 @@ def oracle_sample(workload, gpu_iters, rows_per_case=None, start_at=None):
     A.fill(0.5 + 0.25j)
     if start_at is not None:
         time.sleep(max(0.0, start_at - time.time()))
+    c_arn, spent = arnoldi_unit_seconds()
     t_total = 0.0
-    spent = 0.0
-    for (P, n, rows, mv_n), iters in zip(cases, gpu_iters):
+    for (P, n, rows, mv_n), nprod, units in zip(cases, products, arn_units):
         t0 = time.perf_counter()
         P.assemble_rows(rows)
         t_rows = time.perf_counter() - t0
@@ -126,23 +165,47 @@ def oracle_sample(workload, gpu_iters, rows_per_case=None, start_at=None):
         O.matvec(A, x)
         t_mv = time.perf_counter() - t0
         spent += t_rows + t_mv
-        t_total += t_rows / len(rows) * n + iters * t_mv * (n / mv_n) ** 2
-    return t_total, spent, len(cases[-1][2]), cases[-1][3]
+        t_total += t_rows / len(rows) * n + nprod * t_mv * (n / mv_n) ** 2 + c_arn * units
+    return t_total, spent, len(cases[-1][2]), cases[-1][3], c_arn
 
 
-def cpu_baseline(workload, wl_key, gpu_iters, gpu_value):
+def oracle_full_solve():
+    """The oracle's whole solve of the unit disk as a 256-gon (k0 = 1, k1 = 2,
+    one plane wave, 8-point Gauss): assembly of the 512 x 512 system, its
+    GMRES(50) to 1e-10 and the far field at 360 directions, single thread,
+    timed end to end (no model)."""
+    import oracle as O
+    import workloads as W
+    wl = W.workload_disk256()
+    t0 = time.perf_counter()
+    po = O.Problem(wl.problems[0])
+    A = po.assemble()
+    b = po.rhs(wl.angles)[:, 0]
+    x, it, rel, ok = O.gmres(A, b, wl.restart, wl.tol)
+    po.farfield(x.reshape(-1, 1), wl.far_dirs)
+    T = time.perf_counter() - t0
+    return {"workload": wl.name, "seconds_per_solve": T, "value": 1.0 / T, "unit": "solves/s", "cores": 1,
+            "gmres_iterations": int(it), "converged": bool(ok),
+            "what": "oracle assembly + GMRES(50) to 1e-10 + far field at 360 directions, measured end to end"}
+
+
+def cpu_baseline(workload, wl_key, products, arn_units, gpu_value):
     """The oracle on one core (the record's value), then the same sample in P
     concurrent worker processes, one per available core (at most 16), each
     pinned to its core and started together: their summed rate is the CPU
-    throughput on P cores (requests and right-hand sides are independent)."""
-    t_total, spent, rows_n, mv_n = oracle_sample(workload, gpu_iters)
+    throughput on P cores (requests and right-hand sides are independent).
+    The workload's solves are modelled from the sample (the full oracle solve
+    of the 8192 x 8192 systems would take about an hour); the disk of 256
+    elements is solved by the oracle in full."""
+    t_total, spent, rows_n, mv_n, c_arn = oracle_sample(workload, products, arn_units)
     solves = len(workload.problems) * len(workload.angles)
     one = solves / t_total
     cores = sorted(os.sched_getaffinity(0))[:16]
     import subprocess
     start = time.time() + 4.0 + 0.5 * len(cores)
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--workload", wl_key,
-           "--cpu-iters", ",".join(str(int(i)) for i in gpu_iters), "--cpu-start-at", repr(start)]
+           "--cpu-iters", ",".join(str(int(i)) for i in products),
+           "--cpu-arn", ",".join(repr(float(u)) for u in arn_units), "--cpu-start-at", repr(start)]
     env = dict(os.environ, OMP_NUM_THREADS="1")
     procs = [subprocess.Popen(cmd + ["--cpu-core", str(c)], stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env)
              for c in cores]
@@ -158,15 +221,19 @@ def cpu_baseline(workload, wl_key, gpu_iters, gpu_value):
            "per_process_max": float(max(rates)) if rates else None}
     if errs:
         par["errors"] = errs
-    return {"value": one, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    full = oracle_full_solve()
+    return {"value": one, "unit": "solves/s", "cores": 1, "kind": "oracle", "modelled": True,
             "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
-            "sample": (f"{rows_n} strided rows per case assembled by the oracle (FP64) and one {mv_n} x {mv_n} "
-                       f"oracle product, scaled to {workload.problems[0].order} rows, to the full product size "
-                       f"and to the {sum(gpu_iters)} products the GPU solves used (Arnoldi orthogonalisation not "
-                       f"modelled); {spent:.1f} s of CPU work"),
+            "sample": (f"MODELLED from a timed sample: {rows_n} strided rows per case assembled by the oracle "
+                       f"(FP64), scaled to {workload.problems[0].order} rows; one {mv_n} x {mv_n} oracle product, "
+                       f"scaled to the full product size and to the {int(sum(products))} products the GPU solves "
+                       f"used; the oracle's Gram-Schmidt at {c_arn * 1e9:.2f} ns per (basis vector x row) "
+                       f"(its GMRES(600) on an order-1024 matrix minus its products) times the "
+                       f"{sum(arn_units):.3g} units of the GPU solves' Krylov steps; {spent:.1f} s of CPU work"),
             "parallel": par,
-            "gpu_speedup": {"vs_1_core": gpu_value / one,
-                            f"vs_{len(rates)}_cores": gpu_value / par["value"] if rates else None}}
+            "gpu_speedup_modelled": {"vs_1_core": gpu_value / one,
+                                     f"vs_{len(rates)}_cores": gpu_value / par["value"] if rates else None},
+            "measured_full_solve": full}
 
 
 def cpu_worker(args):
@@ -175,8 +242,9 @@ def cpu_worker(args):
     import workloads as W
     os.sched_setaffinity(0, {args.cpu_core})
     wl = WORKLOAD_FACTORIES[args.workload](W)()
-    iters = [int(v) for v in args.cpu_iters.split(",")]
-    t_total, spent, _, _ = oracle_sample(wl, iters, start_at=args.cpu_start_at)
+    products = [int(v) for v in args.cpu_iters.split(",")]
+    arn = [float(v) for v in args.cpu_arn.split(",")]
+    t_total, spent, _, _, _ = oracle_sample(wl, products, arn, start_at=args.cpu_start_at)
     print(json.dumps({"t_total": t_total, "spent": spent, "core": args.cpu_core}), flush=True)
 
 
@@ -413,18 +481,19 @@ def graphs_mode(args, wl, P, torch, prec):
     print(json.dumps(out), flush=True)
 
 
-def serve_mode(args, P, torch):
+def served_record(args, P, torch, n_requests, open_loop=True):
     """Served stream: requests with Poisson arrivals at 20/s, perturbed circles
     with N log-uniform in [512, 8192], k0 ~ U[1, 50], k1/k0 ~ U[1.2, 3], 1-32
-    angles.  Capacity: every request submitted at once (closed loop), solves/s
-    = right-hand sides / wall time, for the mixed server (BEM_MIXED) and the
-    FP64 server; accuracy: far field of every request, mixed against FP64, and
-    both against FP64 solved to 1e-12 on every 10th request.  Latency: the
-    arrivals replayed in real time (open loop) on the mixed server, p50/p99 of
-    completion minus arrival."""
+    angles (the first n_requests of the seeded stream).  Capacity: every
+    request submitted at once (closed loop), solves/s = right-hand sides /
+    wall time, for the mixed server (BEM_MIXED) and the FP64 server; accuracy:
+    far field of every request, mixed against FP64, and both against FP64
+    solved to 1e-12 on every 10th request.  Latency: the arrivals replayed in
+    real time (open loop) on the mixed server, p50/p99 of completion minus
+    arrival."""
     import workloads as W
     from paper_2312_12787_amd import serve as S
-    reqs = W.request_stream(args.requests)
+    reqs = W.request_stream(n_requests)
     dirs = W.equispaced_angles(360)
     arena = int(args.arena_gb * (1 << 30))
     solves = sum(len(r["angles"]) for r in reqs)
@@ -457,7 +526,7 @@ def serve_mode(args, P, torch):
     log(f"  {T64:.1f} s; FP64 reference to 1e-12 on every 10th request ...")
     sample = list(range(0, len(reqs), 10))
     with S.Server(arena, slots=args.slots, prec=P.F64, tol=1e-12, restart=args.serve_restart, dirs=dirs,
-                      graph_steps=args.graph_steps) as srv:
+                  graph_steps=args.graph_steps) as srv:
         ids = {srv.submit(reqs[i]["spec"], reqs[i]["angles"]): i for i in sample}
         ref = {ids[o.id]: o for o in srv.drain()}
     bad = [i for i in range(len(reqs)) if r32[i].status != 0 or r64[i].status != 0]
@@ -465,7 +534,7 @@ def serve_mode(args, P, torch):
     err32 = [ff_err(r32[i], ref[i]) for i in sample]
     err64 = [ff_err(r64[i], ref[i]) for i in sample]
     lat = []
-    if not args.no_open_loop:
+    if open_loop:
         log("  open loop at the arrival times ...")
         with S.Server(arena, slots=args.slots, prec=P.MIXED, tol=args.serve_tol, restart=args.serve_restart,
                       dirs=dirs, graph_steps=args.graph_steps) as srv:
@@ -488,27 +557,17 @@ def serve_mode(args, P, torch):
         # latency = completion - arrival: the server's own submit-to-done time
         # plus how late the replay submitted the request
         lat_ms = np.array([(o.t_done - o.t_submit + lag[o.id]) * 1e3 for o in lat])
-    out = {
-        "metric": METRIC,
-        "value": solves / T32,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": T32 * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"served stream: {len(reqs)} requests, Poisson 20/s, perturbed circles N 512-8192 "
-                               f"log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
-                   "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
-                   "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs),
-                   "graph_steps": args.graph_steps},
+    rec = {
+        "workload": f"served stream: first {len(reqs)} requests of the seeded stream, Poisson 20/s, perturbed "
+                    f"circles N 512-8192 log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
+        "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
+        "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs),
+        "graph_steps": args.graph_steps,
         "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
+                     "mixed_over_fp64": T64 / T32,
                      "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
-                     "arena_high_water_GiB": st32["arena_high_water"] / 2**30},
+                     "arena_high_water_GiB": st32["arena_high_water"] / 2**30,
+                     "unit": "closed loop: every request submitted at once; right-hand sides solved / wall time"},
         "accuracy": {"far_field_rel_err_mixed_vs_fp64_max": err,
                      "vs_fp64_1e-12_sample": {"requests": len(sample), "mixed_max": max(err32),
                                               "mixed_p50": float(np.median(err32)), "fp64_path_max": max(err64),
@@ -519,11 +578,39 @@ def serve_mode(args, P, torch):
                                "FP64 Arnoldi, refinement residuals with the FP64 matrix", "fp64": "BEM_F64"},
         "gmres_iterations_max_per_request": {"p50": float(np.median([r32[i].iters_max for i in r32])),
                                              "max": int(max(r32[i].iters_max for i in r32))},
-        "roofline": None,
     }
     if lat:
-        out["latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                             "unit": "open loop at the stream's arrival times: completion - submission, mixed server"}
+        rec["latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                             "unit": "open loop at the stream's arrival times: completion - arrival, mixed server"}
+    return rec
+
+
+def serve_mode(args, P, torch):
+    """The served stream alone (--workload serve): its record as the bench line,
+    value = the mixed server's capacity."""
+    rec = served_record(args, P, torch, args.requests, open_loop=not args.no_open_loop)
+    out = {
+        "metric": METRIC,
+        "value": rec["capacity"]["mixed_solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": rec["solves"] / rec["capacity"]["mixed_solves_per_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": rec["workload"], "requests": rec["requests"], "solves": rec["solves"],
+                   "slots": rec["slots"], "arena_GiB": rec["arena_GiB"], "tol": rec["tol"],
+                   "restart": rec["restart"], "far_field_dirs": rec["far_field_dirs"],
+                   "graph_steps": rec["graph_steps"]},
+        "roofline": None,
+    }
+    out.update({k: rec[k] for k in ("capacity", "accuracy", "precision", "gmres_iterations_max_per_request")})
+    if "latency_ms" in rec:
+        out["latency_ms"] = rec["latency_ms"]
     print(json.dumps(out), flush=True)
 
 
@@ -598,6 +685,185 @@ def assemble_mode(args, wl, P, torch, prec):
     print(json.dumps({"mode": "assemble", "workload": wl.name, "precision": wl.precision, "cases": out}), flush=True)
 
 
+def sectors_far_field_error(wl, F_full, P, torch):
+    """Far-field error of the multi-material workload: its solution (h = 1/800)
+    against the mesh refined to h = 1/1600, and the observed order from
+    h = 1/400 (outside the timed region, FP64, GMRES(100) to 1e-10)."""
+    import workloads as W
+    spec0 = wl.problems[0]
+    F = {800: F_full}
+    its = {}
+    for inv_h in (400, 1600):
+        spec = W.sectors(spec0.k, h=1.0 / inv_h)
+        g = P.Problem(spec)
+        g.assemble(P.F64)
+        X, info = g.solve(g.rhs(wl.angles), restart=wl.restart, tol=wl.tol, max_iter=20000)
+        F[inv_h] = g.farfield(X, wl.far_dirs)
+        its[inv_h] = (spec.n_elements, int(info.iters.max()))
+        del g, X
+        torch.cuda.empty_cache()
+    d = {h: float(max_rel_err(F[h], F[1600])) for h in (400, 800)}
+    ratio = d[400] / d[800]
+    order = float(np.log2(max(ratio - 1.0, 1e-3)))
+    x = 2.0 ** order
+    return {"vs_h_1_1600": d[800], "h_1_400_vs_h_1_1600": d[400], "observed_order": order,
+            "estimated_error": d[800] * x / (x - 1.0) if x > 1.0 else None,
+            "refined_meshes": {f"h=1/{h}": {"elements": e, "gmres_iterations": i} for h, (e, i) in its.items()},
+            "measure": "relative 2-norm of the far-field difference at 360 directions; error estimate "
+                       "|F_h - F_h/2| 2^p / (2^p - 1) with p the observed order"}
+
+
+def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
+    """The full hot path of the workload, K timed steps after W untimed ones:
+    each case's device tables, assembly, right-hand sides, GMRES solve and far
+    field.  Returns the bench record (without the CPU baseline) and what the
+    CPU model needs (GMRES products and per-right-hand-side steps)."""
+    mixed = wl.precision == "f32"
+    prec = P.F32 if mixed else P.F64
+    dirs = wl.far_dirs
+    probs, mats = [], []
+    nr = len(wl.angles)
+    for spec in wl.problems:
+        g = P.Problem(spec)
+        g.geometry()  # uploads the inputs (nodes, plan) once
+        mats.append(matrix_buffer(g, prec, P, torch))
+        _, _, wb = g.sizes(P.F64, nr, wl.restart)
+        g._workspace(wb)
+        probs.append(g)
+    torch.cuda.synchronize()
+
+    lat = []
+    iters = [0] * len(probs)
+    products = [0] * len(probs)
+    refine = [0] * len(probs)
+    rhs_steps = [None] * len(probs)
+    last_F = [None] * len(probs)
+
+    def step(record):
+        for ci, (g, A) in enumerate(zip(probs, mats)):
+            t0 = time.perf_counter()
+            g.geometry_update()
+            g.assemble(prec, out=A, lda=A.shape[1])
+            B = g.rhs(wl.angles)
+            X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000,
+                              inner_tol=wl.inner_tol if mixed else 0.0, graph_steps=graph_steps)
+            F = g.farfield(X, dirs)
+            torch.cuda.synchronize()
+            if record:
+                lat.append(time.perf_counter() - t0)
+                iters[ci] += int(info.iters.sum())
+                refine[ci] += int(info.restarts.sum())
+                # products a one-right-hand-side-at-a-time solver needs: one per
+                # Arnoldi step plus one residual per cycle
+                products[ci] += int(info.iters.sum() + info.restarts.sum()) + nr
+                rhs_steps[ci] = info.iters.tolist()
+                last_F[ci] = F
+            if not info.converged.all():
+                raise RuntimeError(f"case {ci} did not converge: {info}")
+
+    for _ in range(warmup):
+        step(False)
+    tuning = None
+    if tune and not args.no_tune:
+        # launch-shape autotuning of the solve's products (bem_tune), outside the timed region
+        if warmup == 0:
+            probs[0].geometry_update()
+            probs[0].assemble(prec, out=mats[0], lda=mats[0].shape[1])
+        log("autotuning the product launch shape ...")
+        tuning = tune_or_import(args, P, probs[0], nr)
+        log("tuned:", tuning)
+    for g in probs:
+        g.profile(True)
+        g.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    prof = [g.profile_read(reset=True) for g in probs]
+    for g in probs:
+        g.profile(False)
+
+    n = probs[0].n
+    N = probs[0].N
+    q = wl.problems[0].quad
+    esz = 8.0 if mixed else 16.0
+    solves = steps * len(probs) * nr
+    mv_launch = sum(p["matvec_launches"] for p in prof)
+    mv_ms = sum(p["matvec_ms"] for p in prof)
+    rs_launch = sum(p["residual_launches"] for p in prof)
+    rs_ms = sum(p["residual_ms"] for p in prof)
+    as_launch = sum(p["assemble_launches"] for p in prof)
+    as_ms = sum(p["assemble_ms"] for p in prof)
+    mv_bytes = esz * n * n + 2 * esz * n * nr  # matrix + X + Y per launch (algorithmic)
+    mv_flops = 8.0 * n * n * nr
+    mv_avg_ms = mv_ms / max(1, mv_launch)
+    mv_gbs = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
+    mv_tfs = mv_flops / (mv_avg_ms * 1e-3) / 1e12
+    as_avg_ms = as_ms / max(1, as_launch)
+    evals = sum(assembly_evals(s) for s in wl.problems) / len(wl.problems)
+    lat_ms = np.array(lat) * 1e3
+    if mixed:
+        # more than 16 right-hand sides always run the 3-product form, which
+        # issues 6 of the 8 algorithmic flops of a complex multiply-add on the
+        # matrix cores: the cores are busy 6/8 of the algorithmic fraction
+        g3 = True if nr > 16 else bool(tuning.get("g3", 1)) if isinstance(tuning, dict) else True
+        roofline = {"kernel": f"k_matvec_mfma (FP32 MFMA split-K block product, {nr} right-hand sides in one pass "
+                              f"over A)", "bound": "mfma", "achieved": mv_tfs, "peak": FP32_MFMA_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": mv_tfs / FP32_MFMA_PEAK_TFS,
+                    "mfma_busy_frac": mv_tfs / FP32_MFMA_PEAK_TFS * (0.75 if g3 else 1.0),
+                    "note": "achieved counts 8 flops per complex multiply-add; the 3-product form runs 6 of them "
+                            "on the matrix cores (mfma_busy_frac)" if g3 else "4-product form",
+                    "traffic": traffic_record(wl.name)}
+    else:
+        roofline = {"kernel": f"k_matvec_mfma (FP64 MFMA split-K block product, {nr} right-hand sides)"
+                    if nr > 4 else f"k_matvec (FP64 VALU split-K product, {nr} right-hand side(s))",
+                    "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(wl.name)}
+    out = {
+        "metric": METRIC,
+        "value": solves / T,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": T / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "elements": N, "system_order": n,
+                   "wavenumbers": [[str(k) for k in s.k] for s in wl.problems], "rhs_per_case": nr,
+                   "restart": wl.restart, "tol": wl.tol, "quad": q, "far_field_dirs": len(dirs),
+                   "solves_per_step": len(probs) * nr, "precision": wl.precision},
+        "case_time_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                         "unit": f"closed loop, one case after another: geometry tables + assembly + {nr} solves + "
+                                 f"far field (served latency: the served record)"},
+        "gmres_iterations_per_rhs": [it / (steps * nr) for it in iters],
+        "assembly": assembly_record(wl, as_launch, as_avg_ms, evals),
+        "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
+                   "share_of_step_time": mv_ms / (T * 1e3)},
+        "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
+        "tuning": tuning,
+        "graph_steps": graph_steps,
+        "roofline": roofline,
+    }
+    if mixed:
+        out["refinement_steps_per_rhs"] = [r / (steps * nr) for r in refine]
+        log("FP64 path on the same workload (reference solve, then one timed run) ...")
+        out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F, tune=tune and not args.no_tune)
+    if wl.name.startswith("sectors"):
+        log("far-field error against refined meshes ...")
+        out["far_field_error"] = sectors_far_field_error(wl, last_F[0], P, torch)
+    model = {"products": [p // steps for p in products],
+             "arn_units": [arnoldi_units(st, wl.restart, g.n) for st, g in zip(rhs_steps, probs)]}
+    del probs, mats
+    torch.cuda.empty_cache()
+    return out, model
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -613,6 +879,10 @@ def main():
                     help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the precision-path, served-prefix and disk256 records")
+    ap.add_argument("--serve-prefix", type=int, default=200,
+                    help="requests of the stream in the default run's served record")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="Krylov steps per captured HIP graph in the solves (0: kernel-by-kernel launches); "
                          "takes effect in the serve workload; the full mode times kernels with the library's "
@@ -629,6 +899,7 @@ def main():
                          "kernel by kernel and as captured HIP graphs")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-iters", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-arn", default="", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-start-at", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-core", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -648,8 +919,7 @@ def main():
     if args.workload == "serve":
         return serve_mode(args, P, torch)
     wl = WORKLOAD_FACTORIES[args.workload](W)()
-    mixed = wl.precision == "f32"
-    prec = P.F32 if mixed else P.F64
+    prec = P.F32 if wl.precision == "f32" else P.F64
     if args.mode == "matvec":
         return matvec_mode(args, wl, P, torch, prec)
     if args.mode == "assemble":
@@ -660,133 +930,40 @@ def main():
         return peaks_mode(args, torch)
     if args.mode == "graphs":
         return graphs_mode(args, wl, P, torch, prec)
-    dirs = wl.far_dirs
-    probs, mats = [], []
-    nr = len(wl.angles)
-    for spec in wl.problems:
-        g = P.Problem(spec)
-        g.geometry()  # uploads the inputs (nodes, plan) once
-        mats.append(matrix_buffer(g, prec, P, torch))
-        _, _, wb = g.sizes(P.F64, nr, wl.restart)
-        g._workspace(wb)
-        probs.append(g)
-    torch.cuda.synchronize()
-
-    lat = []
-    iters = [0] * len(probs)
-    products = [0] * len(probs)
-    refine = [0] * len(probs)
-    last_F = [None] * len(probs)
-
-    def step(record):
-        for ci, (g, A) in enumerate(zip(probs, mats)):
-            t0 = time.perf_counter()
-            g.geometry_update()
-            g.assemble(prec, out=A, lda=A.shape[1])
-            B = g.rhs(wl.angles)
-            X, info = g.solve(B, restart=wl.restart, tol=wl.tol, max_iter=20000,
-                              inner_tol=wl.inner_tol if mixed else 0.0, graph_steps=args.graph_steps)
-            F = g.farfield(X, dirs)
-            torch.cuda.synchronize()
-            if record:
-                lat.append(time.perf_counter() - t0)
-                iters[ci] += int(info.iters.sum())
-                refine[ci] += int(info.restarts.sum())
-                # products a one-right-hand-side-at-a-time solver needs: one per
-                # Arnoldi step plus one residual per cycle
-                products[ci] += int(info.iters.sum() + info.restarts.sum()) + nr
-                last_F[ci] = F
-            if not info.converged.all():
-                raise RuntimeError(f"case {ci} did not converge: {info}")
-
-    for _ in range(args.warmup):
-        step(False)
-    tuning = None
-    if not args.no_tune:
-        # launch-shape autotuning of the solve's products (bem_tune), outside the timed region
-        if args.warmup == 0:
-            probs[0].geometry_update()
-            probs[0].assemble(prec, out=mats[0], lda=mats[0].shape[1])
-        log("autotuning the product launch shape ...")
-        tuning = tune_or_import(args, P, probs[0], nr)
-        log("tuned:", tuning)
-    for g in probs:
-        g.profile(True)
-        g.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    prof = [g.profile_read(reset=True) for g in probs]
-    for g in probs:
-        g.profile(False)
-
-    n = probs[0].n
-    N = probs[0].N
-    q = wl.problems[0].quad
-    esz = 8.0 if mixed else 16.0
-    solves = args.steps * len(probs) * nr
-    mv_launch = sum(p["matvec_launches"] for p in prof)
-    mv_ms = sum(p["matvec_ms"] for p in prof)
-    rs_launch = sum(p["residual_launches"] for p in prof)
-    rs_ms = sum(p["residual_ms"] for p in prof)
-    as_launch = sum(p["assemble_launches"] for p in prof)
-    as_ms = sum(p["assemble_ms"] for p in prof)
-    mv_bytes = esz * n * n + 2 * esz * n * nr  # matrix + X + Y per launch (algorithmic)
-    mv_flops = 8.0 * n * n * nr
-    mv_avg_ms = mv_ms / max(1, mv_launch)
-    mv_gbs = mv_bytes / (mv_avg_ms * 1e-3) / 1e9
-    mv_tfs = mv_flops / (mv_avg_ms * 1e-3) / 1e12
-    as_avg_ms = as_ms / max(1, as_launch)
-    evals = sum(assembly_evals(s) for s in wl.problems) / len(wl.problems)
-    lat_ms = np.array(lat) * 1e3
-    if mixed:
-        roofline = {"kernel": f"k_matvec_mfma (FP32 MFMA split-K block product, {nr} right-hand sides in one pass "
-                              f"over A)", "bound": "mfma", "achieved": mv_tfs, "peak": FP32_MFMA_PEAK_TFS,
-                    "unit": "TFLOP/s", "frac": mv_tfs / FP32_MFMA_PEAK_TFS,
-                    "traffic": traffic_record(wl.name)}
-    else:
-        roofline = {"kernel": f"k_matvec_mfma (FP64 MFMA split-K block product, {nr} right-hand sides)"
-                    if nr > 4 else f"k_matvec (FP64 VALU split-K product, {nr} right-hand side(s))",
-                    "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(wl.name)}
-    out = {
-        "metric": METRIC,
-        "value": solves / T,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": T / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "elements": N, "system_order": n,
-                   "wavenumbers": [[str(k) for k in s.k] for s in wl.problems], "rhs_per_case": nr,
-                   "restart": wl.restart, "tol": wl.tol, "quad": q, "far_field_dirs": len(dirs),
-                   "solves_per_step": len(probs) * nr, "precision": wl.precision},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "unit": f"one case: geometry tables + assembly + {nr} solves + far field"},
-        "gmres_iterations_per_rhs": [it / (args.steps * nr) for it in iters],
-        "assembly": assembly_record(wl, as_launch, as_avg_ms, evals),
-        "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
-                   "share_of_step_time": mv_ms / (T * 1e3)},
-        "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
-        "tuning": tuning,
-        "graph_steps": args.graph_steps,
-        "roofline": roofline,
-    }
-    if mixed:
-        out["refinement_steps_per_rhs"] = [r / (args.steps * nr) for r in refine]
-        log("FP64 path on the same workload (reference solve, then one timed run) ...")
-        out["fp64_comparison"] = fp64_comparison(wl, probs, P, torch, last_F, tune=not args.no_tune)
+    out, model = run_workload(args, wl, P, torch, args.steps, args.warmup, graph_steps=args.graph_steps)
+    if args.workload == "kite4096" and not args.no_extras:
+        # the metric's other halves, each outside the headline's timed region
+        import copy
+        xargs = copy.copy(args)
+        xargs.tune_file = None  # the headline's launch-shape file stays the headline's
+        log("precision path: kite N = 16384, FP32 products + FP64 refinement, 64 angles ...")
+        pp, _ = run_workload(xargs, W.workload_kite16384_fp32(), P, torch, 2, 1)
+        fc = pp["fp64_comparison"]
+        out["precision_path"] = {
+            "workload": pp["config"]["workload"], "mixed_solves_per_s": pp["value"],
+            "fp64_path_solves_per_s": fc["fp64_path_solves_per_s"],
+            "mixed_over_fp64": pp["value"] / fc["fp64_path_solves_per_s"],
+            "far_field_rel_err_mixed": fc["far_field_rel_err_mixed"],
+            "far_field_rel_err_fp64_path": fc["far_field_rel_err_fp64_path"], "reference": fc["reference"],
+            "gmres_iterations_per_rhs": pp["gmres_iterations_per_rhs"],
+            "refinement_steps_per_rhs": pp["refinement_steps_per_rhs"], "steps_timed": 2,
+            "assembly": pp["assembly"], "roofline": pp["roofline"]}
+        P.tune_reset()  # the served stream runs the built-in launch shapes, as with --workload serve
+        log(f"served stream: first {args.serve_prefix} requests ...")
+        out["served"] = served_record(xargs, P, torch, args.serve_prefix, open_loop=True)
+        log("disk256 (unit disk, N = 256), 20 steps ...")
+        dk, _ = run_workload(xargs, W.workload_disk256(), P, torch, 20, 3, tune=False)
+        out["disk256"] = {"workload": dk["config"]["workload"], "value": dk["value"], "unit": "solves/s",
+                          "case_time_ms": dk["case_time_ms"], "gmres_iterations_per_rhs":
+                              dk["gmres_iterations_per_rhs"],
+                          "note": "4 MB matrix: launch- and latency-bound, not a roofline case"}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.workload, [p // args.steps for p in products], out["value"])
+        out["cpu_baseline"] = cpu_baseline(wl, args.workload, model["products"], model["arn_units"], out["value"])
+        full = out["cpu_baseline"]["measured_full_solve"]
+        if "disk256" in out:
+            full["gpu_solves_per_s"] = out["disk256"]["value"]
+            full["gpu_speedup_measured"] = out["disk256"]["value"] / full["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -201,9 +201,9 @@ typedef struct {
                            kernels and order as 0, hence the same X.  The graphs keep the
                            matrix, work buffer, nrhs, restart, max_iter and product launch
                            shapes they were captured with; a call that changes any of
-                           them (the tuned-shape table included; the BEM_MV_CFG
-                           environment overrides are read at capture only) captures
-                           again.  Ignored while bem_profile_enable is on.           */
+                           them (a new assembly that resolved other shapes, or a
+                           bem_tune of this problem, included) captures again.
+                           Ignored while bem_profile_enable is on.                   */
 } bem_solve_opts;
 
 typedef struct {
@@ -287,8 +287,15 @@ bem_status bem_profile_read(bem_problem *p, bem_profile *out, int reset);
  * or the FP32 copy of BEM_MIXED, with FP64 vectors otherwise), `reps` timed
  * products each after one untimed, and installs the fastest for its shape
  * class: (matrix and accumulation precision, right-hand-side groups of 16 up
- * to 64 or the vector kernel's up to 4, ceil(log2 n)).  Every later product
- * of that class in this process, on any problem and thread, uses it.  X_dev
+ * to 64 or the vector kernel's up to 4, ceil(log2 n)) in the process's table.
+ * A problem resolves the shapes of all its products when bem_assemble runs
+ * (from that table and the BEM_MV_CFG / BEM_MV_CFG_WIDE overrides as they are
+ * then) and keeps them until its next bem_assemble: the tuned problem itself
+ * switches to the new shape at once, every other problem at its next
+ * assembly, so a table change (bem_tune, bem_tune_import, bem_tune_reset)
+ * never changes the rounding of the products of a problem already assembled.
+ * A request server resolves every request from a copy of the table taken when
+ * the server was created (bem_serve.h).  X_dev
  * (complex128, n x nrhs, ldx >= n) is read, Y_dev (same shape, ldy) is
  * overwritten with A X, work_dev as for bem_matvec.  Candidates never need
  * more work memory than bem_sizes reports, before or after tuning.  The call

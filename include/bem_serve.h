@@ -24,8 +24,11 @@
  *     has been passed over 2 * slots times by younger ones admits no younger
  *     one before itself (no starvation);
  *   - results do not depend on what else runs: every reduction inside the
- *     path has a fixed order, so a request gives bit-identical output alone
- *     or in the mix.
+ *     path has a fixed order, and every request's products use the launch
+ *     shapes of a copy of the tuned-shape table (and of the BEM_MV_CFG
+ *     overrides) taken by bem_server_create, so a request gives bit-identical
+ *     output alone or in the mix, whatever bem_tune / bem_tune_import calls
+ *     the process makes meanwhile.
  *
  * The server allocates no device memory.  Host memory: request copies and
  * one pinned flag buffer per slot.

@@ -25,7 +25,8 @@ CALDERON, CALDERON_BETA1, CONVENTIONAL, CALDERON_ORIG = 0, 1, 2, 3
 STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4: "BEM_E_DEVICE",
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
 EXPORTS = ["bem_create", "bem_destroy", "bem_n_elements", "bem_order", "bem_sizes", "bem_geometry",
-           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield", "bem_nearfield",
+           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield",
+           "bem_nearfield",
            "bem_profile_enable", "bem_profile_read", "bem_tune", "bem_tune_export", "bem_tune_import",
            "bem_tune_reset", "bem_last_error"]
 
@@ -101,8 +102,8 @@ def lib():
         L.bem_tune_reset.argtypes = []
         L.bem_tune_reset.restype = None
         L.bem_last_error.restype = C.c_char_p
-        for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve",
-                  "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
+        for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec",
+                  "bem_solve", "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

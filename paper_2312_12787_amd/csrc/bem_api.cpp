@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -124,7 +125,7 @@ struct bem_problem {
         const int* flags = nullptr;
         size_t lda = 0, ldv = 0;
         int prec = -1, n = 0, nr = 0, m = 0, S = 0, maxit = 0;
-        unsigned gen = 0;
+        bemk::MvShapes shapes{};
     } graphs;
     hipStream_t cap = nullptr;  // private stream the segments are captured on (never runs work)
     hipStream_t asm_side = nullptr;       // second stream of the assembly launches
@@ -135,6 +136,11 @@ struct bem_problem {
     void* A32 = nullptr;    // BEM_MIXED: the FP32 copy (leading dimension lda)
     size_t lda = 0;
     int prec = -1;
+    // launch shapes of this problem's products, resolved at bem_assemble from
+    // `frozen` (a request server's copy of the shape sources) or else from the
+    // live tuned table and environment; bem_tune of this problem updates them
+    mutable bemk::MvShapes shapes{};
+    std::shared_ptr<const bemk::ShapeSnapshot> frozen;
 };
 
 namespace {
@@ -629,6 +635,7 @@ bem_status bem_assemble(bem_problem* p, int prec, void* A_dev, size_t lda, hipSt
         lists[v] = reinterpret_cast<const int*>(p->geom + p->L.vtiles) + p->voff[v];
         pairs[v] = reinterpret_cast<const int*>(p->geom + p->L.npairs) + 3 * (size_t)p->noff[v];
     }
+    bemk::resolve_shapes(p->frozen.get(), (int)n, p->shapes);
     bemk::hook_call(p->hk(), bemk::KIND_ASSEMBLE, 0, stream);
     float2* A32 = prec == BEM_MIXED ? reinterpret_cast<float2*>(static_cast<char*>(A_dev) + mixed_offset(n, lda))
                                     : nullptr;
@@ -694,11 +701,11 @@ bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t 
     if (p->prec != BEM_F32)
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n,
                                        static_cast<const double2*>(X_dev), ldx, nrhs, static_cast<double2*>(Y_dev),
-                                       ldy, reinterpret_cast<double2*>(w), stream, p->hk()));
+                                       ldy, reinterpret_cast<double2*>(w), stream, p->hk(), &p->shapes));
     else
         HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, n, static_cast<const float2*>(X_dev),
                                        ldx, nrhs, static_cast<float2*>(Y_dev), ldy,
-                                       reinterpret_cast<float2*>(w), stream, p->hk()));
+                                       reinterpret_cast<float2*>(w), stream, p->hk(), &p->shapes));
     return BEM_OK;
 }
 
@@ -754,6 +761,8 @@ bem_status bem_tune(const bem_problem* p, int nrhs, const void* X_dev, size_t ld
     if (e1) (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(BEM_E_DEVICE, std::string("bem_tune: ") + hipGetErrorString(err));
     bemk::set_tuned_shape(types, ng, n, bestc);
+    // this problem runs the tuned shape from now on (others when assembled next)
+    p->shapes.s[types][ng] = bemk::current_shape(types, ng, n);
     if (info) {
         info->rt = bestc.rt;
         info->u = bestc.u;
@@ -818,12 +827,12 @@ bem_status apply_basis(const Solver& c, int j, double2* Y, size_t ldy)
     const bem_problem* p = c.p;
     if (!c.v32()) {
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, c.V(j), c.W.ldv, c.nr, Y, ldy,
-                                       c.at<double2>(c.W.mv_part), c.s, p->hk()));
+                                       c.at<double2>(c.W.mv_part), c.s, p->hk(), &p->shapes));
         return BEM_OK;
     }
     const float2* A32 = static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A);
     HIP_OK(bemk::launch_matvec_f32v(A32, p->lda, c.n, c.V32(j), c.W.ldv, c.nr, Y, ldy,
-                                    reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk()));
+                                    reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), c.s, p->hk(), &p->shapes));
     return BEM_OK;
 }
 
@@ -835,10 +844,10 @@ bem_status residual(const Solver& c, const double2* B, size_t ldb, const double2
     const bem_problem* p = c.p;
     if (p->prec != BEM_F32)
         HIP_OK(bemk::launch_residual_f64(static_cast<const double2*>(p->A), p->lda, c.n, X, ldx, c.nr, B, ldb, R, ldr,
-                                         c.at<double2>(c.W.mv_part), c.s, p->hk()));
+                                         c.at<double2>(c.W.mv_part), c.s, p->hk(), &p->shapes));
     else
         HIP_OK(bemk::launch_residual_f32A(static_cast<const float2*>(p->A), p->lda, c.n, X, ldx, c.nr, B, ldb, R,
-                                          ldr, c.at<double2>(c.W.mv_part), c.s, p->hk()));
+                                          ldr, c.at<double2>(c.W.mv_part), c.s, p->hk(), &p->shapes));
     return BEM_OK;
 }
 
@@ -878,10 +887,9 @@ bem_status segment_graph(Solver& c, bemk::ArnoldiArgs arn, int sg, int S, int ri
 {
     bem_problem* p = c.p;
     auto& G = p->graphs;
-    const unsigned gen = bemk::tuning_generation();
     if (G.A != p->A || G.A32 != p->A32 || G.lda != p->lda || G.prec != p->prec || G.w != c.w ||
         G.ldv != c.W.ldv || G.n != c.n || G.nr != c.nr || G.m != c.m || G.S != S || G.maxit != arn.maxit ||
-        G.flags != p->pinned_dev || G.gen != gen || G.seg.empty()) {
+        G.flags != p->pinned_dev || std::memcmp(&G.shapes, &p->shapes, sizeof G.shapes) != 0 || G.seg.empty()) {
         drop_graphs(p);
         G.A = p->A;
         G.A32 = p->A32;
@@ -895,7 +903,7 @@ bem_status segment_graph(Solver& c, bemk::ArnoldiArgs arn, int sg, int S, int ri
         G.S = S;
         G.maxit = arn.maxit;
         G.flags = p->pinned_dev;
-        G.gen = gen;
+        G.shapes = p->shapes;
         G.seg.assign((size_t)(c.m + S) / S, nullptr);
     }
     if (!G.seg[sg]) {
@@ -1258,6 +1266,10 @@ void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, const hipEvent_
     for (int k = 0; k < FLAG_RING; ++k) p->flag_ev[k] = ev[k];
     p->lent = true;
 }
+
+// The request server's frozen shape sources: every request it runs resolves
+// its launch shapes from the copy taken when the server was created.
+void freeze_shapes(bem_problem* p, std::shared_ptr<const ShapeSnapshot> snap) { p->frozen = std::move(snap); }
 
 // bem_last_error() text for the calls of the request server.
 void set_last_error(const std::string& msg) { g_err = msg; }

@@ -1,6 +1,7 @@
 // launch.h -- host-side entry points of the gfx950 kernels.
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -62,36 +63,47 @@ size_t matvec_part_elems(int n, int nrhs);
 struct MvShape {
     int rt, u, splits, g3;
 };
-void force_shape(const MvShape* s);  // this thread's products use s (nullptr: the table again)
+// The shapes one problem's products run with, by [types][ng], resolved once
+// (at assembly) from a source of shapes: the process's tuned table and the
+// BEM_MV_CFG / BEM_MV_CFG_WIDE overrides as they are then, or a frozen copy
+// of both (the request server's, taken when it is created).  Products never
+// read the live table, so a later bem_tune / bem_tune_import or a changed
+// environment cannot change the numerics of a problem already assembled.
+struct MvShapes {
+    MvShape s[4][5];
+};
+struct ShapeSnapshot;
+std::shared_ptr<const ShapeSnapshot> snapshot_shapes();
+void resolve_shapes(const ShapeSnapshot* snap /* nullptr: the live table and environment */, int n, MvShapes& out);
+void force_shape(const MvShape* s);  // this thread's products use s (nullptr: the resolved shapes again)
 MvShape current_shape(int types, int ng, int n);
 std::vector<MvShape> candidate_shapes(int types, int ng, int n);
 void set_tuned_shape(int types, int ng, int n, const MvShape& c);
 void clear_tuned_shapes();
 std::string export_tuned_shapes();
 bool import_tuned_shapes(const char* text);
-unsigned tuning_generation();  // changes whenever the tuned table does (captured launches depend on it)
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s,
-                             const KernelHook* hook = nullptr);
+                             const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 // FP32 matrix and products with FP64 vectors: X is rounded to FP32 when packed,
 // Y widened when the split partial sums are added.
 hipError_t launch_matvec_f32x64(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                                 double2* Y, size_t ldy, float2* partial, hipStream_t s,
-                                const KernelHook* hook = nullptr);
+                                const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 // The same with an FP32 X (a complex64 Krylov basis vector); Y in FP64.
 hipError_t launch_matvec_f32v(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs,
                               double2* Y, size_t ldy, float2* partial, hipStream_t s,
-                              const KernelHook* hook = nullptr);
+                              const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
-                             size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr);
+                             size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 // R = B - A X (FP64)
 hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                               const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,
-                              const KernelHook* hook = nullptr);
+                              const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 // R = B - A X with an FP32 matrix, FP64 vectors and FP64 accumulation.
 hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                                 const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial,
-                                hipStream_t s, const KernelHook* hook = nullptr);
+                                hipStream_t s, const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 
 // GMRES building blocks (basis V[(i * nr + r) * ldv + q], FP64).
 hipError_t launch_col_norms(const double2* X, size_t ldx, int n, int nr, double* partial, double* out,

@@ -437,7 +437,6 @@ struct ShapeKey {
 };
 std::mutex g_tune_mu;
 std::map<ShapeKey, MvShape> g_tuned;
-unsigned g_tune_gen = 0;  // bumped whenever the table changes
 thread_local const MvShape* g_forced = nullptr;
 
 int size_class(int n)
@@ -455,36 +454,73 @@ int split_cap(int n, int ng)
     return std::max(cap, std::max(mfma_default(n, ng, true).splits, mfma_default(n, ng, false).splits));
 }
 
-// The shape a product of this class runs with: the tuner's forced candidate,
-// else BEM_MV_CFG / BEM_MV_CFG_WIDE ("rt,u,splits[,g3]", manual tuning), else
-// the tuned table, else the default; splits clamped to split_cap.
-MvShape mv_shape(int types, int ng, int n)
+// Environment overrides of the launch shape (manual tuning): BEM_MV_CFG for
+// one group of 16 right-hand sides, BEM_MV_CFG_WIDE for 2-4 groups,
+// "rt,u,splits[,g3]".
+bool env_shape(int ng, MvShape& out)
+{
+    const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE");
+    if (!e) return false;
+    MvShape t{0, 0, 0, 1};
+    const int got = sscanf(e, "%d,%d,%d,%d", &t.rt, &t.u, &t.splits, &t.g3);
+    if (ng > 1) t.g3 = 1;
+    t.g3 = t.g3 != 0;
+    if (got < 3 || !shape_valid(ng, t)) return false;
+    out = t;
+    return true;
+}
+
+}  // namespace
+
+// A frozen source of shapes: the tuned table and the environment overrides.
+struct ShapeSnapshot {
+    std::map<ShapeKey, MvShape> table;
+    bool have_env[2] = {false, false};  // [0]: one group, [1]: 2-4 groups
+    MvShape env[2] = {};
+};
+
+namespace {
+
+// The shape a product of this class runs with, from a snapshot (or the live
+// table and environment when snap is null): an environment override, else the
+// tuned table, else the default; splits clamped to split_cap.
+MvShape shape_from(const ShapeSnapshot* snap, int types, int ng, int n)
 {
     MvShape c = ng == 0 ? MvShape{0, 0, matvec_splits_valu(n), 0} : mfma_default(n, ng, types & 1);
     bool have = false;
-    if (g_forced && shape_valid(ng, *g_forced)) {
-        c = *g_forced;
-        have = true;
-    }
-    if (!have && ng > 0) {
-        if (const char* e = getenv(ng == 1 ? "BEM_MV_CFG" : "BEM_MV_CFG_WIDE")) {
-            MvShape t{0, 0, 0, 1};
-            const int got = sscanf(e, "%d,%d,%d,%d", &t.rt, &t.u, &t.splits, &t.g3);
-            if (ng > 1) t.g3 = 1;
-            t.g3 = t.g3 != 0;
-            if (got >= 3 && shape_valid(ng, t)) {
-                c = t;
-                have = true;
-            }
+    if (ng > 0) {
+        MvShape t{};
+        if (snap ? snap->have_env[ng > 1] : env_shape(ng, t)) {
+            c = snap ? snap->env[ng > 1] : t;
+            have = true;
         }
     }
     if (!have) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(ShapeKey{types, ng, size_class(n)});
-        if (it != g_tuned.end()) c = it->second;
+        const ShapeKey key{types, ng, size_class(n)};
+        if (snap) {
+            auto it = snap->table.find(key);
+            if (it != snap->table.end()) c = it->second;
+        } else {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) c = it->second;
+        }
     }
     c.splits = std::max(1, std::min({c.splits, split_cap(n, ng), std::max(1, n / 64)}));
     return c;
+}
+
+// The shape a launch uses: the tuner's forced candidate (this thread), else the
+// problem's resolved shapes, else the live table (callers without a problem).
+MvShape pick_shape(const MvShapes* shapes, int types, int ng, int n)
+{
+    if (g_forced && shape_valid(ng, *g_forced)) {
+        MvShape c = *g_forced;
+        c.splits = std::max(1, std::min({c.splits, split_cap(n, ng), std::max(1, n / 64)}));
+        return c;
+    }
+    if (shapes) return shapes->s[types][ng];
+    return shape_from(nullptr, types, ng, n);
 }
 
 constexpr int MFMA_MAX_RHS = 64;  // right-hand sides per pass over A
@@ -536,11 +572,12 @@ void launch_mfma_variant(const MvShape& c, int ng, dim3 grid, hipStream_t s, con
 
 template <class TA, class TX, class ACC, class TY>
 hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, int nrhs, TY* Y, size_t ldy,
-                      ACC* part, const double2* B, size_t ldb, hipStream_t s, const KernelHook* hook)
+                      ACC* part, const double2* B, size_t ldb, hipStream_t s, const KernelHook* hook,
+                      const MvShapes* shapes)
 {
     using S = decltype(ACC{}.x);
     constexpr int types = (sizeof(TA) == 16 ? 2 : 0) + (sizeof(S) == 8 ? 1 : 0);
-    const int splits = mv_shape(types, 0, n).splits;
+    const int splits = pick_shape(shapes, types, 0, n).splits;
     const int cps = (n + splits - 1) / splits;
     const int rowblocks = (n + 64 * MV_WAVES - 1) / (64 * MV_WAVES);
     const int kind = B ? KIND_RESIDUAL : KIND_MATVEC;
@@ -550,7 +587,7 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
         if (nr > 4) {
             // pack X right-hand-side fastest into the tail of the partial buffer
             const int ng = (nr + 15) / 16;
-            const MvShape cfg = mv_shape(types, ng, n);
+            const MvShape cfg = pick_shape(shapes, types, ng, n);
             const int ms = cfg.splits;
             const int mcps = ((n + ms - 1) / ms + 31) / 32 * 32;
             ACC* xt = part + (size_t)ms * nr * n;
@@ -610,42 +647,52 @@ size_t matvec_part_elems(int n, int nrhs)
 }
 
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
-                             double2* Y, size_t ldy, double2* partial, hipStream_t s, const KernelHook* hook)
+                             double2* Y, size_t ldy, double2* partial, hipStream_t s, const KernelHook* hook,
+                             const MvShapes* shapes)
 {
     return matvec_any<double2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s,
-                                                          hook);
+                                                          hook, shapes);
 }
 
 hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
-                             size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook)
+                             size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook,
+                             const MvShapes* shapes)
 {
-    return matvec_any<float2, float2, float2, float2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook);
+    return matvec_any<float2, float2, float2, float2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook,
+                                                      shapes);
 }
 
 hipError_t launch_matvec_f32x64(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
-                                double2* Y, size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook)
+                                double2* Y, size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook,
+                             const MvShapes* shapes)
 {
-    return matvec_any<float2, double2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook);
+    return matvec_any<float2, double2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook,
+                                                        shapes);
 }
 
 hipError_t launch_matvec_f32v(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs,
-                              double2* Y, size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook)
+                              double2* Y, size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook,
+                             const MvShapes* shapes)
 {
-    return matvec_any<float2, float2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook);
+    return matvec_any<float2, float2, float2, double2>(A, lda, n, X, ldx, nrhs, Y, ldy, partial, nullptr, 0, s, hook,
+                                                       shapes);
 }
 
 hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                               const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,
-                              const KernelHook* hook)
+                              const KernelHook* hook, const MvShapes* shapes)
 {
-    return matvec_any<double2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, R, ldr, partial, B, ldb, s, hook);
+    return matvec_any<double2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, R, ldr, partial, B, ldb, s, hook,
+                                                          shapes);
 }
 
 hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                                 const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial,
-                                hipStream_t s, const KernelHook* hook)
+                                hipStream_t s, const KernelHook* hook,
+                                const MvShapes* shapes)
 {
-    return matvec_any<float2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, R, ldr, partial, B, ldb, s, hook);
+    return matvec_any<float2, double2, double2, double2>(A, lda, n, X, ldx, nrhs, R, ldr, partial, B, ldb, s, hook,
+                                                         shapes);
 }
 
 
@@ -654,7 +701,22 @@ hipError_t launch_residual_f32A(const float2* A, size_t lda, int n, const double
 // ---------------------------------------------------------------------------
 void force_shape(const MvShape* s) { g_forced = s; }
 
-MvShape current_shape(int types, int ng, int n) { return mv_shape(types, ng, n); }
+MvShape current_shape(int types, int ng, int n) { return shape_from(nullptr, types, ng, n); }
+
+std::shared_ptr<const ShapeSnapshot> snapshot_shapes()
+{
+    auto snap = std::make_shared<ShapeSnapshot>();
+    for (int w = 0; w < 2; ++w) snap->have_env[w] = env_shape(w ? 2 : 1, snap->env[w]);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    snap->table = g_tuned;
+    return snap;
+}
+
+void resolve_shapes(const ShapeSnapshot* snap, int n, MvShapes& out)
+{
+    for (int t = 0; t < 4; ++t)
+        for (int ng = 0; ng <= 4; ++ng) out.s[t][ng] = shape_from(snap, t, ng, n);
+}
 
 std::vector<MvShape> candidate_shapes(int types, int ng, int n)
 {
@@ -685,20 +747,12 @@ void set_tuned_shape(int types, int ng, int n, const MvShape& c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[ShapeKey{types, ng, size_class(n)}] = c;
-    ++g_tune_gen;
 }
 
 void clear_tuned_shapes()
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
-    ++g_tune_gen;
-}
-
-unsigned tuning_generation()
-{
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    return g_tune_gen;
 }
 
 std::string export_tuned_shapes()
@@ -731,7 +785,6 @@ bool import_tuned_shapes(const char* text)
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : add) g_tuned[kv.first] = kv.second;
-    ++g_tune_gen;
     return true;
 }
 

@@ -24,6 +24,7 @@
 
 namespace bemk {
 void lend_flag_buffers(bem_problem* p, int* pinned, size_t ints, const hipEvent_t* ev);
+void freeze_shapes(bem_problem* p, std::shared_ptr<const ShapeSnapshot> snap);
 void set_last_error(const std::string& msg);
 }
 
@@ -124,6 +125,9 @@ bem_status sfail(bem_status s, const std::string& m)
 struct bem_server {
     bem_server_opts o{};
     std::vector<double> dirs;
+    // product launch shapes of every request: the tuned table and environment
+    // overrides as they were when the server was created
+    std::shared_ptr<const bemk::ShapeSnapshot> shapes;
     char* base = nullptr;
     Arena arena;
     std::mutex mu;
@@ -186,6 +190,7 @@ struct bem_server {
         const size_t n = (size_t)r->n;
         std::vector<bem_solve_info> info((size_t)r->nrhs);
         bemk::lend_flag_buffers(r->p, sl.pinned, FLAG_INTS, sl.ev);
+        bemk::freeze_shapes(r->p, shapes);
         bem_status st = bem_geometry(r->p, g, r->geom, sl.stream);
         if (!st) st = bem_assemble(r->p, (bem_prec)o.prec, A, r->lda, sl.stream);
         if (!st) st = bem_rhs(r->p, r->nrhs, r->angles.data(), B, n, sl.stream);
@@ -277,6 +282,7 @@ bem_status bem_server_create(const bem_server_opts* opts, bem_server** out)
     s->o = o;
     s->dirs.assign(o.dirs, o.dirs + o.ndir);
     s->o.dirs = nullptr;
+    s->shapes = bemk::snapshot_shapes();
     s->base = static_cast<char*>(o.arena_dev);
     s->arena.init(o.arena_bytes);
     s->t0 = std::chrono::steady_clock::now();

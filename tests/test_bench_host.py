@@ -22,24 +22,51 @@ def test_cpu_worker_prints_its_modelled_time():
     core = sorted(os.sched_getaffinity(0))[0]
     env = dict(os.environ, OMP_NUM_THREADS="1")
     p = subprocess.run([sys.executable, BENCH, "--cpu-worker", "--workload", "disk256", "--cpu-iters", "16",
-                        "--cpu-core", str(core)], capture_output=True, text=True, timeout=300, env=env)
+                        "--cpu-arn", "1e6", "--cpu-core", str(core)], capture_output=True, text=True, timeout=300,
+                       env=env)
     assert p.returncode == 0, p.stderr[-500:]
     rec = json.loads(p.stdout.strip().splitlines()[-1])
     assert rec["core"] == core
     assert rec["t_total"] > 0.0 and rec["spent"] > 0.0
 
 
-def test_oracle_sample_scales_with_the_product_count():
+def test_oracle_sample_scales_with_products_and_gram_schmidt_work():
     """The modelled time grows with the number of products the GPU solve
-    used (one timed product per case, scaled by the count)."""
+    used (one timed product per case, scaled by the count) and with the
+    Gram-Schmidt work of its Krylov steps (a measured cost per unit)."""
     sys.path.insert(0, ROOT)
     import bench
     import workloads as W
     wl = W.workload_disk256()
-    t1, spent1, rows, mv = bench.oracle_sample(wl, [1])
-    t100, _, _, _ = bench.oracle_sample(wl, [400])
+    t1, spent1, rows, mv, c = bench.oracle_sample(wl, [1], [0.0])
+    t100, _, _, _, _ = bench.oracle_sample(wl, [400], [0.0])
     assert rows == wl.problems[0].order and mv == wl.problems[0].order
-    assert t100 > t1 > 0.0 and spent1 > 0.0
+    assert t100 > t1 > 0.0 and spent1 > 0.0 and c > 0.0
+    units = 1e9
+    ta, _, _, _, ca = bench.oracle_sample(wl, [1], [units])
+    assert ta > t1 + 0.5 * ca * units
+
+
+def test_gram_schmidt_units_of_restarted_gmres():
+    """Step j of a cycle projects on j + 1 basis vectors: a run of s steps
+    with restart m is full cycles of m(m+1)/2 and a last one of r(r+1)/2
+    (r = s mod m), times n rows, summed over right-hand sides."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.arnoldi_units([3], 100, 10) == 6 * 10
+    assert bench.arnoldi_units([127, 92], 100, 8192) == (5050 + 27 * 28 // 2 + 92 * 93 // 2) * 8192
+    assert bench.arnoldi_units([200], 100, 1) == 2 * 5050
+    assert bench.arnoldi_units([0], 100, 5) == 0
+
+
+def test_oracle_full_solve_is_timed_end_to_end():
+    """The disk of 256 elements is solved by the oracle in full (assembly,
+    GMRES(50) to 1e-10, far field) and converges."""
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.oracle_full_solve()
+    assert r["converged"] and r["seconds_per_solve"] > 0.0 and r["value"] == 1.0 / r["seconds_per_solve"]
+    assert 5 <= r["gmres_iterations"] <= 50
 
 
 def test_benchmark_matrices_have_128_byte_aligned_columns():

@@ -103,3 +103,70 @@ def test_tuned_fp32_products_equal_builtin_products(nrhs):
         assert _rel(Y1, Y0) < 1e-5
     finally:
         P.tune_reset()
+
+
+# launch shapes unlike the built-in ones for the classes the small requests
+# below use (FP64 and FP32 sums, vector kernel and one group of 16, n of
+# 2^7 .. 2^11): other split counts and the four-product form change the
+# order of the sums, so results computed with them differ in their last bits
+_OTHER_SHAPES = "".join(f"{t} 0 {lg} 0 0 2 0\n{t} 1 {lg} 1 4 2 0\n" for t in (0, 1, 3) for lg in range(7, 12))
+
+
+def test_assembled_problem_keeps_its_shapes_after_a_table_import():
+    """A problem's products use the launch shapes resolved when it was
+    assembled: importing a table afterwards leaves them bit-identical; the
+    next assembly picks the imported shapes up (and the bits change)."""
+    P = _gpu()
+    try:
+        g = P.Problem(W.kite(500, 5.0, 7.5))
+        g.assemble(P.F64)
+        for nrhs in (2, 12):
+            X = _x(nrhs, g.n, 3)
+            Y0 = g.matvec(X).clone()
+            P.tune_import(_OTHER_SHAPES)
+            Y1 = g.matvec(X)
+            assert torch.equal(Y1, Y0)
+            g.assemble(P.F64)
+            Y2 = g.matvec(X)
+            print("nrhs", nrhs, "after re-assembly: max |dY| / max |Y|",
+                  float((Y2 - Y0).abs().max() / Y0.abs().max()), flush=True)
+            assert not torch.equal(Y2, Y0) and _rel(Y2.cpu().numpy(), Y0.cpu().numpy()) < 1e-13
+            P.tune_reset()
+            g.assemble(P.F64)
+    finally:
+        P.tune_reset()
+
+
+@pytest.mark.parametrize("prec", ["F64", "MIXED"])
+def test_running_server_is_unaffected_by_a_table_import(prec):
+    """Requests of a server created before a bem_tune_import give bit-identical
+    far fields to a run without the import, though the import lands while they
+    are queued and running; a server created after it uses the new shapes."""
+    P = _gpu()
+    from paper_2312_12787_amd import serve as S
+    pr = getattr(P, prec)
+    reqs = W.request_stream(12, seed=4, n_range=(64, 900), k0_range=(1.0, 10.0), max_rhs=14)
+    dirs = W.equispaced_angles(36)
+
+    def run(import_midway):
+        with S.Server(2 << 30, slots=3, prec=pr, dirs=dirs) as srv:
+            ids = {}
+            for i, r in enumerate(reqs):
+                ids[srv.submit(r["spec"], r["angles"])] = i
+                if import_midway and i == 3:
+                    P.tune_import(_OTHER_SHAPES)
+            out = srv.drain()
+        assert all(o.status == 0 for o in out)
+        return {ids[o.id]: o.far_field for o in out}
+
+    try:
+        base = run(False)
+        mid = run(True)
+        same = all(np.array_equal(mid[i], base[i]) for i in base)
+        after = run(False)  # created after the import: the imported shapes
+        changed = sum(not np.array_equal(after[i], base[i]) for i in base)
+        print(prec, "bit-identical with the import mid-run:", same, "requests changed by a later server:", changed,
+              flush=True)
+        assert same and changed > 0
+    finally:
+        P.tune_reset()
