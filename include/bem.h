@@ -30,8 +30,10 @@
  *     are interleaved (re, im) pairs: complex128 for BEM_F64, complex64 for
  *     BEM_F32;
  *   - the library never allocates device memory: the caller passes every
- *     device buffer (sizes from bem_sizes) and owns it; pointers named *_dev
- *     are device pointers, all others are host pointers;
+ *     device buffer (sizes from bem_sizes) and owns it (the one exception is
+ *     the fixed scratch array of bem_matvec_noalloc, part of the library's
+ *     code on each GPU); pointers named *_dev are device pointers, all others
+ *     are host pointers;
  *   - all device work of a call is ordered on the caller's stream; calls that
  *     return data to the host (bem_solve) synchronise that stream;
  *   - errors are returned as status codes; bem_last_error() gives a message
@@ -184,6 +186,26 @@ bem_status bem_rhs(const bem_problem *p, int nang, const double *angles, void *B
  * split-K partial sums (bem_sizes with this nrhs).                          */
 bem_status bem_matvec(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev,
                       size_t ldy, void *work_dev, size_t work_bytes, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bem_matvec
+ * without a workspace argument.  The split-K partial sums and the packed
+ * right-hand sides live in a device array of BEM_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends (its
+ * address is looked up once per device, on the first call with that device
+ * current; the current device must be the stream's).  Same kernels, launch
+ * shapes and summation order as bem_matvec, hence the same Y.  The call
+ * allocates nothing and never records timing events (bem_profile_enable does
+ * not apply).  BEM_E_ARG when the product's partial sums would exceed the
+ * array (FP64: about splits x nrhs x n x 16 bytes, e.g. n = 8192 with 16
+ * right-hand sides in the built-in shape takes 18.9 MB); every other error as
+ * bem_matvec.  All calls on one GPU share the array: calls that overlap in
+ * time on that GPU (other streams, other threads) race and give wrong
+ * results; calls ordered on one stream are safe.  Nothing in the array needs
+ * clearing between calls (every call writes what it reads).                 */
+#define BEM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+bem_status bem_matvec_noalloc(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev,
+                              size_t ldy, hipStream_t stream);
 
 typedef struct {
     int restart;        /* GMRES restart length m (>= 1)                                  */

@@ -25,8 +25,8 @@ CALDERON, CALDERON_BETA1, CONVENTIONAL, CALDERON_ORIG = 0, 1, 2, 3
 STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4: "BEM_E_DEVICE",
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
 EXPORTS = ["bem_create", "bem_destroy", "bem_n_elements", "bem_order", "bem_sizes", "bem_geometry",
-           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_solve", "bem_farfield",
-           "bem_nearfield",
+           "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_matvec_noalloc", "bem_solve",
+           "bem_farfield", "bem_nearfield",
            "bem_profile_enable", "bem_profile_read", "bem_tune", "bem_tune_export", "bem_tune_import",
            "bem_tune_reset", "bem_last_error"]
 
@@ -89,6 +89,7 @@ def lib():
         L.bem_assemble.argtypes = [vp, C.c_int, vp, sz, vp]
         L.bem_rhs.argtypes = [vp, C.c_int, C.POINTER(C.c_double), vp, sz, vp]
         L.bem_matvec.argtypes = [vp, C.c_int, vp, sz, vp, sz, vp, sz, vp]
+        L.bem_matvec_noalloc.argtypes = [vp, C.c_int, vp, sz, vp, sz, vp]
         L.bem_solve.argtypes = [vp, C.c_int, vp, sz, C.POINTER(bem_solve_opts), vp, sz, vp, sz,
                                 C.POINTER(bem_solve_info), vp]
         L.bem_farfield.argtypes = [vp, C.c_int, vp, sz, C.c_int, C.POINTER(C.c_double), vp, sz, vp, sz, vp]
@@ -102,7 +103,7 @@ def lib():
         L.bem_tune_reset.argtypes = []
         L.bem_tune_reset.restype = None
         L.bem_last_error.restype = C.c_char_p
-        for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec",
+        for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_matvec_noalloc",
                   "bem_solve", "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -304,6 +305,18 @@ class Problem:
         W = self._workspace(wb)
         _check(lib().bem_matvec(self._h, nrhs, C.c_void_p(X.data_ptr()), X.shape[1], C.c_void_p(Y.data_ptr()),
                                 Y.shape[1], C.c_void_p(W.data_ptr()), W.numel(), _stream(stream)))
+        return Y
+
+    def matvec_noalloc(self, X, Y=None, stream=None):
+        """Y = A X through bem_matvec_noalloc (no workspace: the library's own
+        device scratch).  Y (same shape and dtype as X) is allocated here if
+        None; pass it to keep the call free of allocations."""
+        import torch
+        X = X.contiguous()
+        if Y is None:
+            Y = torch.empty_like(X)
+        _check(lib().bem_matvec_noalloc(self._h, X.shape[0], C.c_void_p(X.data_ptr()), X.shape[1],
+                                        C.c_void_p(Y.data_ptr()), Y.shape[1], _stream(stream)))
         return Y
 
     def tune(self, nrhs: int, reps: int = 3, X=None, stream=None):

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -706,6 +707,67 @@ bem_status bem_matvec(const bem_problem* p, int nrhs, const void* X_dev, size_t 
         HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, n, static_cast<const float2*>(X_dev),
                                        ldx, nrhs, static_cast<float2*>(Y_dev), ldy,
                                        reinterpret_cast<float2*>(w), stream, p->hk(), &p->shapes));
+    return BEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of the allocation-free product: the split-K partial sums and
+// the packed right-hand sides of one product at a time per GPU.  Host code
+// uses the device address from hipGetSymbolAddress, looked up once per device.
+constexpr size_t SCRATCH_BYTES = BEM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+bem_status scratch_ptr(void** out)
+{
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(BEM_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(BEM_E_DEVICE, "hipGetSymbolAddress gave a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bem_status bem_matvec_noalloc(const bem_problem* p, int nrhs, const void* X_dev, size_t ldx, void* Y_dev, size_t ldy,
+                              hipStream_t stream)
+{
+    if (bem_status s = check_problem(p)) return s;
+    if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_matvec_noalloc");
+    const int n = 2 * p->N;
+    if (nrhs < 1 || !X_dev || !Y_dev) return fail(BEM_E_ARG, "bad matvec arguments");
+    if (ldx < (size_t)n || ldy < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+    const bool f64 = p->prec != BEM_F32;
+    const size_t need = bemk::matvec_part_elems_shaped(p->shapes, f64 ? 3 : 0, n, nrhs) *
+                        (f64 ? sizeof(double2) : sizeof(float2));
+    if (need > SCRATCH_BYTES)
+        return fail(BEM_E_ARG, "bem_matvec_noalloc: the product needs " + std::to_string(need) +
+                                   " bytes of partial sums, more than the library's " +
+                                   std::to_string(SCRATCH_BYTES) + "-byte device scratch; use bem_matvec");
+    void* w = nullptr;
+    if (bem_status s = scratch_ptr(&w)) return s;
+    if (f64)
+        HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, n,
+                                       static_cast<const double2*>(X_dev), ldx, nrhs, static_cast<double2*>(Y_dev),
+                                       ldy, static_cast<double2*>(w), stream, nullptr, &p->shapes));
+    else
+        HIP_OK(bemk::launch_matvec_f32(static_cast<const float2*>(p->A), p->lda, n, static_cast<const float2*>(X_dev),
+                                       ldx, nrhs, static_cast<float2*>(Y_dev), ldy, static_cast<float2*>(w), stream,
+                                       nullptr, &p->shapes));
     return BEM_OK;
 }
 

@@ -53,8 +53,12 @@ struct AngleChunk {
 hipError_t launch_rhs(const char* g, const GeomLayout& L, int N, const double* angles, int nang, double2* B,
                       size_t ldb, hipStream_t s);
 
-// Y = A X; partial holds matvec_part_elems(n, nrhs) complex values.
+// Y = A X; partial holds matvec_part_elems(n, nrhs) complex values (enough for
+// any launch shape), or matvec_part_elems_shaped(shapes, types, n, nrhs) for
+// the shapes given (types as in the shape classes below).
 size_t matvec_part_elems(int n, int nrhs);
+struct MvShapes;
+size_t matvec_part_elems_shaped(const MvShapes& sh, int types, int n, int nrhs);
 
 // Launch shape of a product: row tiles per wave, column steps in flight,
 // column splits, 3-product form (the vector kernel uses splits only).  Shape

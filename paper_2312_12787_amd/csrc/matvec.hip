@@ -646,6 +646,18 @@ size_t matvec_part_elems(int n, int nrhs)
     return e * (size_t)n;
 }
 
+size_t matvec_part_elems_shaped(const MvShapes& sh, int types, int n, int nrhs)
+{
+    size_t e = 0;
+    for (int r0 = 0; r0 < nrhs; r0 += MFMA_MAX_RHS) {
+        const int nr = std::min(MFMA_MAX_RHS, nrhs - r0);
+        const int ng = nr > 4 ? (nr + 15) / 16 : 0;
+        const size_t c = (size_t)sh.s[types][ng].splits * nr + (ng ? 16 * ng : 0);
+        e = std::max(e, c);
+    }
+    return e * (size_t)n;
+}
+
 hipError_t launch_matvec_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                              double2* Y, size_t ldy, double2* partial, hipStream_t s, const KernelHook* hook,
                              const MvShapes* shapes)
