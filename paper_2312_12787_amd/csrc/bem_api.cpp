@@ -881,12 +881,31 @@ struct Solver {
     float2* V32(int i) const { return at<float2>(W.V) + (size_t)i * nr * W.ldv; }
 };
 
-// Y = A v_j for basis vector j of every right-hand side: the FP64 product, or
-// the FP32 one on the complex64 basis (FP32 matrix, or the FP32 copy of a
-// BEM_MIXED one), Y in FP64 either way.
+// The Krylov step's product Y = A v_j: with more than 4 right-hand sides the
+// matrix-core kernel reads v_j packed (written by the kernel that produced
+// v_j: the cycle start or the previous step's normalisation), with up to 4
+// the vector kernel reads v_j itself.  FP64 product, or the FP32 one on the
+// complex64 basis (FP32 matrix, or the FP32 copy of a BEM_MIXED one), Y in
+// FP64 either way.
+bemk::ProductPlan step_plan(const Solver& c)
+{
+    return bemk::product_plan(&c.p->shapes, c.v32() ? 0 : 3, c.n, c.nr);
+}
+
 bem_status apply_basis(const Solver& c, int j, double2* Y, size_t ldy)
 {
     const bem_problem* p = c.p;
+    const bemk::ProductPlan pl = step_plan(c);
+    if (pl.ng > 0) {
+        if (!c.v32())
+            HIP_OK(bemk::launch_product_packed_f64(pl, static_cast<const double2*>(p->A), p->lda, c.n, c.nr,
+                                                   c.at<double2>(c.W.mv_part), Y, ldy, c.s, p->hk()));
+        else
+            HIP_OK(bemk::launch_product_packed_f32(
+                pl, static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A), p->lda, c.n, c.nr,
+                reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), Y, ldy, c.s, p->hk()));
+        return BEM_OK;
+    }
     if (!c.v32()) {
         HIP_OK(bemk::launch_matvec_f64(static_cast<const double2*>(p->A), p->lda, c.n, c.V(j), c.W.ldv, c.nr, Y, ldy,
                                        c.at<double2>(c.W.mv_part), c.s, p->hk(), &p->shapes));
@@ -1096,16 +1115,30 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     arn.iters = c.at<int>(c.W.iters);
     arn.kdim = c.at<int>(c.W.kdim);
     arn.active = c.at<int>(c.W.active);
+    const bemk::ProductPlan pl = step_plan(c);
+    // the products read v_j packed (more than 4 right-hand sides), written by
+    // the cycle start and the step's normalisation kernel
+    void* xt = nullptr;
+    if (pl.ng > 0) {
+        if (c.v32())
+            xt = reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)) + pl.xt_offset;
+        else
+            xt = c.at<double2>(c.W.mv_part) + pl.xt_offset;
+        arn.xt = xt;
+        arn.xw = pl.xw;
+    }
     std::vector<int> dev_iters(nr);
     while (std::count(alive.begin(), alive.end(), 1) > 0) {
         if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
         HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
         if (c.v32())
             HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V32(0), ldv,
-                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
+                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active),
+                                            static_cast<float2*>(xt), pl.xw, c.s));
         else
             HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
-                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active), c.s));
+                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active),
+                                            static_cast<double2*>(xt), pl.xw, c.s));
         for (int sg = 0; graphs && sg < (m + S) / S; ++sg) {
             hipGraphExec_t ex = nullptr;
             if (bem_status st = segment_graph(c, arn, sg, S, ring, ex)) return st;

@@ -100,6 +100,22 @@ hipError_t launch_matvec_f32v(const float2* A, size_t lda, int n, const float2* 
                               const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
 hipError_t launch_matvec_f32(const float2* A, size_t lda, int n, const float2* X, size_t ldx, int nrhs, float2* Y,
                              size_t ldy, float2* partial, hipStream_t s, const KernelHook* hook = nullptr, const MvShapes* shapes = nullptr);
+// The products of the Krylov steps with more than 4 right-hand sides: the
+// matrix-core kernel reads them packed at part + xt_offset (XT[c * xw + r],
+// zero for nr <= r < xw), written there by the kernel that produced the basis
+// vector (start of a cycle, end of the previous step), and its split partial
+// sums are added in split order into Y (FP64).
+struct ProductPlan {
+    MvShape shape;
+    int ng, splits, xw;
+    size_t xt_offset;  // in complex values of the accumulation type
+};
+ProductPlan product_plan(const MvShapes* shapes, int types, int n, int nr);
+hipError_t launch_product_packed_f64(const ProductPlan& pl, const double2* A, size_t lda, int n, int nr,
+                                     double2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook);
+// FP32 matrix and sums (complex64 basis), Y widened to FP64.
+hipError_t launch_product_packed_f32(const ProductPlan& pl, const float2* A, size_t lda, int n, int nr,
+                                     float2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook);
 // R = B - A X (FP64)
 hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                               const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,
@@ -133,16 +149,24 @@ struct ArnoldiArgs {
     int *iters, *kdim, *active;    // counters and flags (device)
     int* flags_out;                // copy of the stopping flags in pinned host memory (device address)
     bool v32;                      // basis stored as complex64 at V (same element offsets), else complex128
+    // where the next product reads its packed right-hand sides (xw columns;
+    // nullptr: the vector product reads V itself)
+    void* xt;
+    int xw;
 };
 hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s);
 
 // Host side (bem_api.cpp): bytes of a matrix buffer of order n and leading
 // dimension lda in precision prec (a bem_prec value).
 size_t matrix_bytes_ld(int prec, size_t n, size_t lda);
+// v_0 = R / |R| per active right-hand side (and its packed copy at xt, xw
+// columns, for the first product; xt may be nullptr), g = |R| e_0.
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
-                              double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
+                              double2* V, size_t ldv, double2* gvec, const int* active, double2* xt, int xw,
+                              hipStream_t s);
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
-                              float2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s);
+                              float2* V, size_t ldv, double2* gvec, const int* active, float2* xt, int xw,
+                              hipStream_t s);
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
                             hipStream_t s);
 hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,

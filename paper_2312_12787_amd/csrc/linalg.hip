@@ -205,18 +205,29 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
 // ---------------------------------------------------------------------------
 
 // Partial projections of the candidate (and of wt when HASW) on V_0..V_j for a
-// batch of BATCH basis vectors (grid x), one right-hand side (grid y) and one
-// chunk of rpt * BS rows (grid z): partP/partQ[(r * ns + chunk) * jc + i].
+// batch of BATCH basis vectors, one right-hand side r and one chunk of
+// rpt * BS rows: partP/partQ[(r * ns + chunk) * jc + i].  One-dimensional
+// grid of rcp * batches blocks, block b taking (right-hand side, chunk) pair
+// b % rcp and batch b / rcp, with rcp = nr * ns rounded up to a multiple of 8:
+// workgroups go to the eight XCDs in turn, so every batch of one (right-hand
+// side, chunk) runs on the same XCD and reads its candidate and wt rows from
+// that XCD's L2 after the first batch brought them in (ids >= nr * ns of a
+// padded row exit at once; measured on gfx950 for kite4096 with 16
+// right-hand sides: 534.9 against 530.7 solves/s with the batches of one pair
+// on consecutive ids).  Adding the product's split partial sums here instead
+// of in its own reduction pass was slower (525.9), every batch re-reading them.
 template <int BATCH, bool HASW, class TV>
 __global__ __launch_bounds__(BS) void k_dc_dots(const TV* __restrict__ V, size_t ldv, int nr, int jc,
-                                                const double2* __restrict__ W, size_t ldw, int n, int rpt,
-                                                double2* __restrict__ partP, double2* __restrict__ partQ,
+                                                const double2* __restrict__ W, size_t ldw, int n, int rpt, int ns,
+                                                int rcp, double2* __restrict__ partP, double2* __restrict__ partQ,
                                                 const int* __restrict__ active)
 {
     constexpr int NV = (HASW ? 4 : 2) * BATCH;
     __shared__ double lds[4 * NV];
-    const int r = blockIdx.y, chunk = blockIdx.z, ns = gridDim.z;
-    const int i0 = blockIdx.x * BATCH;
+    const int rc = (int)(blockIdx.x % (unsigned)rcp);
+    if (rc >= nr * ns) return;
+    const int r = rc % nr, chunk = rc / nr;
+    const int i0 = (int)(blockIdx.x / (unsigned)rcp) * BATCH;
     if (!active[r]) return;
     double acc[NV];
 #pragma unroll
@@ -289,8 +300,12 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
                                                         int* __restrict__ iters, int* __restrict__ kdim,
                                                         int* __restrict__ active, int* __restrict__ flags_out)
 {
+    // S, T and the column being completed stay in LDS for the whole step; the
+    // inputs of earlier steps (column j - 1 as produced, the rotations, the
+    // rotated right-hand side) are loaded first, alongside the partial sums
     __shared__ double2 col[1024 + 1];
     __shared__ double2 lc[1024], ls[1024];
+    __shared__ double2 Sl[1024 + 1], Tl[1024 + 1];
     __shared__ double2 zp[4][64];
     __shared__ double red[3 * 4];
     __shared__ int still_s;
@@ -304,6 +319,14 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
     const bool hasw = partQ != nullptr;
     double2* S = sc + (size_t)r * (m + 1);
     double2* T = tc + (size_t)r * (m + 1);
+    double2* Hc = Hraw + (size_t)r * (m + 1) * m + (size_t)(j >= 1 ? j - 1 : 0) * (m + 1);
+    if (j >= 1) {
+        for (int i = tid; i < j; i += DC_STEP_BS) col[i] = Hc[i];
+        for (int i = tid; i < j - 1; i += DC_STEP_BS) {
+            lc[i] = cs[(size_t)r * m + i];
+            ls[i] = sn[(size_t)r * m + i];
+        }
+    }
     for (int i = tid; i < jc; i += DC_STEP_BS) {
         double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
 #pragma unroll 8
@@ -318,18 +341,22 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
                 qi += t.y;
             }
         }
-        S[i] = make_double2(pr, pi);
-        if (hasw) T[i] = make_double2(qr, qi);
+        Sl[i] = make_double2(pr, pi);
+        S[i] = Sl[i];
+        if (hasw) {
+            Tl[i] = make_double2(qr, qi);
+            T[i] = Tl[i];
+        }
     }
     __syncthreads();
     const double beta = j >= 1 ? hnorm[r] : 1.0;
     const bool brk = !(beta > 0.0);  // previous step ended the Krylov space
     double ss = 0.0, str = 0.0, sti = 0.0;
     for (int i = tid; i < j; i += DC_STEP_BS) {
-        const double2 a = brk ? make_double2(0.0, 0.0) : S[i];
+        const double2 a = brk ? make_double2(0.0, 0.0) : Sl[i];
         ss = fma(a.x, a.x, fma(a.y, a.y, ss));
         if (hasw) {
-            const double2 t = T[i];
+            const double2 t = Tl[i];
             str = fma(a.x, t.x, fma(a.y, t.y, str));
             sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
         }
@@ -337,25 +364,20 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
     ss = block_sum4(ss, red, 0);
     str = block_sum4(str, red, 1);
     sti = block_sum4(sti, red, 2);
-    const double alpha = S[j].x;
+    const double alpha = Sl[j].x;
     const double gamma = brk ? 0.0 : sqrt(fmax(alpha - ss, 0.0));
     int still = 1;
     if (j >= 1) {
         // complete column j - 1
-        double2* Hc = Hraw + (size_t)r * (m + 1) * m + (size_t)(j - 1) * (m + 1);
         for (int i = tid; i < j; i += DC_STEP_BS) {
-            double2 h = Hc[i];
+            double2 h = col[i];
             if (!brk) {
-                const double2 a = S[i];
+                const double2 a = Sl[i];
                 h.x = fma(beta, a.x, h.x);
                 h.y = fma(beta, a.y, h.y);
             }
             Hc[i] = h;
             col[i] = h;
-        }
-        for (int i = tid; i < j - 1; i += DC_STEP_BS) {
-            lc[i] = cs[(size_t)r * m + i];
-            ls[i] = sn[(size_t)r * m + i];
         }
         if (tid == 0) {
             const double2 sub = make_double2(brk ? 0.0 : beta * gamma, 0.0);
@@ -423,7 +445,7 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
     if (flags_out && tid == 0) flags_out[r] = still;
     if (!still) return;
     // column j and the update coefficients
-    const double2 tau = T[j];
+    const double2 tau = Tl[j];
     const double ig = 1.0 / gamma;
     const double2 c = make_double2((tau.x - str) * ig, (tau.y - sti) * ig);
     const double2* Hr = Hraw + (size_t)r * (m + 1) * m;
@@ -440,7 +462,7 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
 #pragma unroll 8
             for (int l = first; l < j; l += 4) {
                 const double2 h = Hr[(size_t)l * (m + 1) + i];
-                const double2 a = S[l];
+                const double2 a = Sl[l];
                 zr += h.x * a.x - h.y * a.y;
                 zi += h.x * a.y + h.y * a.x;
             }
@@ -450,7 +472,7 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
         if (wv == 0 && i < jc) {
             const double zx = ((zp[0][lane].x + zp[1][lane].x) + zp[2][lane].x) + zp[3][lane].x;
             const double zy = ((zp[0][lane].y + zp[1][lane].y) + zp[2][lane].y) + zp[3][lane].y;
-            const double2 base = i < j ? T[i] : c;
+            const double2 base = i < j ? Tl[i] : c;
             Hj[i] = make_double2((base.x - zx) * ig, (base.y - zy) * ig);
         }
         __syncthreads();
@@ -509,15 +531,22 @@ __global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv
 }
 
 // beta = |w| from the update partials (every block sums them in the same
-// order), V_{j+1} = w / beta (0 if beta = 0: the Krylov space ended).
+// order), V_{j+1} = w / beta (0 if beta = 0: the Krylov space ended); with xt,
+// also the packed copy the next product reads (XT[q * xw + r], the stored
+// value), and zeros in its padding columns nr <= r < xw (grid rows).
 template <class TV>
 __global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, size_t ldw, int n,
                                                 const double* __restrict__ norm_part, int nu,
                                                 TV* __restrict__ V, size_t ldv, double* __restrict__ hnorm,
-                                                const int* __restrict__ active)
+                                                const int* __restrict__ active, int nr, TV* __restrict__ xt, int xw)
 {
     __shared__ double bsh;
     const int r = blockIdx.y;
+    const int q = blockIdx.x * BS + threadIdx.x;
+    if (r >= nr) {
+        if (q < n) st2(xt + (size_t)q * xw + r, make_double2(0.0, 0.0));
+        return;
+    }
     if (!active[r]) return;
     if (threadIdx.x < 64) {
         double v = 0.0;
@@ -528,26 +557,35 @@ __global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, s
     __syncthreads();
     const double beta = bsh;
     if (blockIdx.x == 0 && threadIdx.x == 0) hnorm[r] = beta;
-    const int q = blockIdx.x * BS + threadIdx.x;
     if (q >= n) return;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const double2 w = W[(size_t)r * ldw + q];
-    st2(V + (size_t)r * ldv + q, make_double2(w.x * inv, w.y * inv));
+    const double2 v = make_double2(w.x * inv, w.y * inv);
+    st2(V + (size_t)r * ldv + q, v);
+    if (xt) st2(xt + (size_t)q * xw + r, v);
 }
 
+// v_0 = r / |r| and g = |r| e_0 per active right-hand side; with xt, also the
+// packed copy of v_0 for the first product (as k_dc_next).
 template <class TV>
 __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, int nr,
                               const double* __restrict__ rnorm, int m, TV* __restrict__ V, size_t ldv,
-                              double2* __restrict__ gvec, const int* __restrict__ active)
+                              double2* __restrict__ gvec, const int* __restrict__ active, TV* __restrict__ xt, int xw)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
+    if (r >= nr) {
+        if (q < n) st2(xt + (size_t)q * xw + r, make_double2(0.0, 0.0));
+        return;
+    }
     if (!active[r]) return;
     const double nv = rnorm[r];
     const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
     if (q < n) {
         const double2 v = R[(size_t)r * ldr + q];
-        st2(V + (size_t)r * ldv + q, make_double2(v.x * inv, v.y * inv));
+        const double2 u = make_double2(v.x * inv, v.y * inv);
+        st2(V + (size_t)r * ldv + q, u);
+        if (xt) st2(xt + (size_t)q * xw + r, u);
     }
     if (q <= m) gvec[(size_t)r * (m + 1) + q] = make_double2(q == 0 ? nv : 0.0, 0.0);
 }
@@ -705,19 +743,21 @@ int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().ro
 namespace {
 
 template <bool HASW, class TV>
-void launch_dc_dots(const DotCfg& c, dim3 grid, hipStream_t s, const TV* V, size_t ldv, int nr, int jc,
+void launch_dc_dots(const DotCfg& c, int ns, hipStream_t s, const TV* V, size_t ldv, int nr, int jc,
                     const double2* W, size_t ldw, int n, double2* partP, double2* partQ, const int* active)
 {
     const int rpt = c.rows / BS;
+    const int rcp = (nr * ns + 7) / 8 * 8;
+    const dim3 grid(rcp * ((jc + c.batch - 1) / c.batch));
     if (c.batch == 4)
-        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
-                           partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
+                           partP, partQ, active);
     else if (c.batch == 16)
-        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
-                           partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
+                           partP, partQ, active);
     else
-        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, partP,
-                           partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
+                           partP, partQ, active);
 }
 
 template <class TV>
@@ -729,20 +769,20 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs& a, TV* V, int j, hipStream_t s)
     const int nu = (n + BS - 1) / BS;            // blocks of the update kernel
     const int jc = j + 1;
     const bool last = j == m;
-    dim3 gd((jc + dc.batch - 1) / dc.batch, nr, ns);
     dim3 gu(nu, nr);
+    TV* xt = static_cast<TV*>(a.xt);
     if (last)
-        launch_dc_dots<false, TV>(dc, gd, s, V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
+        launch_dc_dots<false, TV>(dc, ns, s, V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
     else
-        launch_dc_dots<true, TV>(dc, gd, s, V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
+        launch_dc_dots<true, TV>(dc, ns, s, V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
     hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(DC_STEP_BS), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
                        a.H, a.cs, a.sn, a.gvec, a.hnorm, a.sc, a.tc, a.scal, a.thr, a.maxit, a.iters, a.kdim, a.active,
                        a.flags_out);
     if (!last) {
         hipLaunchKernelGGL((k_dc_update<TV>), gu, dim3(BS), 0, s, V, a.ldv, nr, j, m, a.sc, a.tc, a.scal, a.W,
                            a.ldw, n, a.norm_part, a.active);
-        hipLaunchKernelGGL((k_dc_next<TV>), gu, dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
-                           V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active);
+        hipLaunchKernelGGL((k_dc_next<TV>), dim3(nu, xt ? a.xw : nr), dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
+                           V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active, nr, xt, a.xw);
     }
     return hipGetLastError();
 }
@@ -759,26 +799,28 @@ namespace {
 
 template <class TV>
 hipError_t start_cycle_t(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m, TV* V, size_t ldv,
-                         double2* gvec, const int* active, hipStream_t s)
+                         double2* gvec, const int* active, TV* xt, int xw, hipStream_t s)
 {
     const int len = std::max(n, m + 1);
-    hipLaunchKernelGGL((k_start_cycle<TV>), dim3((len + BS - 1) / BS, nr), dim3(BS), 0, s, R, ldr, n, nr, rnorm, m,
-                       V, ldv, gvec, active);
+    hipLaunchKernelGGL((k_start_cycle<TV>), dim3((len + BS - 1) / BS, xt ? xw : nr), dim3(BS), 0, s, R, ldr, n, nr,
+                       rnorm, m, V, ldv, gvec, active, xt, xw);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
-                              double2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s)
+                              double2* V, size_t ldv, double2* gvec, const int* active, double2* xt, int xw,
+                              hipStream_t s)
 {
-    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, s);
+    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, xt, xw, s);
 }
 
 hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const double* rnorm, int m,
-                              float2* V, size_t ldv, double2* gvec, const int* active, hipStream_t s)
+                              float2* V, size_t ldv, double2* gvec, const int* active, float2* xt, int xw,
+                              hipStream_t s)
 {
-    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, s);
+    return start_cycle_t(R, ldr, n, nr, rnorm, m, V, ldv, gvec, active, xt, xw, s);
 }
 
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,

@@ -617,7 +617,48 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
     return hipGetLastError();
 }
 
+// Products of the Krylov steps with 5-64 right-hand sides, packed by the
+// caller at part + xt_offset: the matrix-core kernel and the split reduction.
+template <class TA, class ACC>
+hipError_t product_packed(const ProductPlan& pl, const TA* A, size_t lda, int n, int nr, ACC* part, double2* Y,
+                          size_t ldy, hipStream_t s, const KernelHook* hook)
+{
+    using S = decltype(ACC{}.x);
+    const int rows_per_block = 16 * pl.shape.rt * MV_WAVES;
+    const int mcps = ((n + pl.splits - 1) / pl.splits + 31) / 32 * 32;
+    hook_call(hook, KIND_MATVEC, 0, s);
+    launch_mfma_variant<TA, S, ACC>(pl.shape, pl.ng, dim3((n + rows_per_block - 1) / rows_per_block, pl.splits), s, A,
+                                    lda, n, part + pl.xt_offset, nr, part, mcps);
+    hook_call(hook, KIND_MATVEC, 1, s);
+    hipLaunchKernelGGL((k_matvec_reduce<ACC, double2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, part, pl.splits,
+                       n, nr, Y, ldy, nullptr, 0);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+ProductPlan product_plan(const MvShapes* shapes, int types, int n, int nr)
+{
+    ProductPlan pl{};
+    pl.ng = nr > 4 ? (nr + 15) / 16 : 0;
+    pl.shape = pick_shape(shapes, types, pl.ng, n);
+    pl.splits = pl.shape.splits;
+    pl.xt_offset = pl.ng > 0 ? (size_t)pl.splits * nr * n : 0;
+    pl.xw = 16 * pl.ng;
+    return pl;
+}
+
+hipError_t launch_product_packed_f64(const ProductPlan& pl, const double2* A, size_t lda, int n, int nr,
+                                     double2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook)
+{
+    return product_packed<double2, double2>(pl, A, lda, n, nr, part, Y, ldy, s, hook);
+}
+
+hipError_t launch_product_packed_f32(const ProductPlan& pl, const float2* A, size_t lda, int n, int nr,
+                                     float2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook)
+{
+    return product_packed<float2, float2>(pl, A, lda, n, nr, part, Y, ldy, s, hook);
+}
 
 int matvec_splits_valu(int n)
 {
