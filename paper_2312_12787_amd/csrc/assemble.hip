@@ -660,24 +660,37 @@ __device__ __forceinline__ void element_entries_f32(const WaveConst& W64, const 
 // (the mixed path's inner products use that copy, its refinement residuals
 // the FP64 matrix).  F32 = true: FP32 entries into A (float2).
 // ---------------------------------------------------------------------------
+// sub < 0: the workgroup's ROW_TILE threads cover the row tile and share the
+// staged chunk (far launch).  sub >= 0: this wave alone covers rows
+// [64 sub, 64 sub + 64) of the tile and stages its own part of the chunk in
+// its own gp / ell (near launch: one list item per wave, so that waves whose
+// rows have no near element are not launched at all).  Every wave of the
+// workgroup reaches the one barrier, item or not (act).
 template <int Q, bool CPLX, bool BM, bool F32, bool NEAR>
 __device__ __forceinline__ void assemble_chunk(const char* __restrict__ g, const GeomLayout& L, int N, int n_if,
-                                               int q_rt, int tile, int chunk, int part, int side, void* Av,
+                                               int q_rt, int tile, int sub, int chunk, int part, int side, void* Av,
                                                size_t lda, float2* __restrict__ A32, size_t lda32,
-                                               GaussL* __restrict__ gp, ElemL* __restrict__ ell)
+                                               GaussL* __restrict__ gp, ElemL* __restrict__ ell, bool act)
 {
     static_assert(COL_CHUNK <= 32, "the near-element mask is one 32-bit word");
     constexpr int QS = Q > 0 ? Q : QMAX;
-    const Tile rt = tab<Tile>(g, L.rtiles)[tile];
-    Tile cc = tab<Tile>(g, L.cchunks)[chunk];
-    if (part >= 0) {  // near launch: NEAR_PART elements of the chunk
-        cc.start += part * NEAR_PART;
-        cc.count = min(NEAR_PART, cc.count - part * NEAR_PART);
+    const int nst = sub < 0 ? ROW_TILE : 64;
+    const int li_st = sub < 0 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    const int li = sub < 0 ? (int)threadIdx.x : sub * 64 + (int)(threadIdx.x & 63);
+    Tile rt{}, cc{};
+    int d = 0, sg = 0;
+    IfacePlan P{};
+    if (act) {
+        rt = tab<Tile>(g, L.rtiles)[tile];
+        cc = tab<Tile>(g, L.cchunks)[chunk];
+        if (part >= 0) {  // near launch: NEAR_PART elements of the chunk
+            cc.start += part * NEAR_PART;
+            cc.count = min(NEAR_PART, cc.count - part * NEAR_PART);
+        }
+        P = tab<IfacePlan>(g, L.iface)[rt.iface];
+        d = side ? P.dr : P.dl;
+        sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
     }
-    const int li = threadIdx.x;
-    const IfacePlan P = tab<IfacePlan>(g, L.iface)[rt.iface];
-    const int d = side ? P.dr : P.dl;
-    const int sg = tab<int>(g, L.sigma)[d * n_if + cc.iface];
     const int i = rt.start + li;
     const size_t row = (size_t)((side ? P.row_r : P.row_l) + (i - P.off));
     const int cnt = cc.count;
@@ -696,28 +709,29 @@ __device__ __forceinline__ void assemble_chunk(const char* __restrict__ g, const
             }
         }
     };
-    if (sg == 0) {  // uniform over the workgroup; the far launch writes the zero block
-        if (NEAR || li >= rt.count) return;
+    if (!NEAR && sg == 0) {  // uniform over the workgroup; the far launch writes the zero block
+        if (li >= rt.count) return;
         for (int jj = 0; jj < cnt; ++jj) store(cc.start + jj, {0.0, 0.0}, {0.0, 0.0});
         return;
     }
+    act = act && sg != 0;
     // stage the chunk: Gauss points (x, y, weight) and element data
-    {
+    if (act) {
         const int q = Q > 0 ? Q : q_rt;
         const GaussRec* gq = tab<GaussRec>(g, L.gauss);
-        for (int t = li; t < cnt * q; t += ROW_TILE) {
+        for (int t = li_st; t < cnt * q; t += nst) {
             const int e = t / q, gg = t - e * q;
             const GaussRec& G = gq[cc.start + e];
             gp[e * QS + gg] = GaussL{G.x[gg], G.y[gg], G.w[gg], 0.0};
         }
         const ElemRec* el = tab<ElemRec>(g, L.elem);
-        for (int t = li; t < cnt; t += ROW_TILE) {
+        for (int t = li_st; t < cnt; t += nst) {
             const ElemRec& E = el[cc.start + t];
             ell[t] = ElemL{E.nx, E.ny, E.ax, E.ay, E.bx, E.by, E.cx, E.cy, 0.5 * E.h, 0.0};
         }
     }
     __syncthreads();
-    if (li >= rt.count) return;
+    if (!act || li >= rt.count) return;
     const WaveConst& W = tab<WaveConst>(g, L.wave)[d];
     const DomConst Dm = tab<DomConst>(g, L.dom)[d];
     const ElemRec Ei = tab<ElemRec>(g, L.elem)[i];
@@ -789,9 +803,9 @@ __device__ __forceinline__ void assemble_chunk(const char* __restrict__ g, const
 
 // Far elements (the bulk; no series code, so two waves fit per SIMD) over the
 // grid (row tiles of the variant) x (column chunks), and near elements (the
-// general per-lane evaluation) over the variant's list of (row tile, column
-// chunk, part of NEAR_PART elements) whose bounding boxes come within the
-// series radius: small workgroups that spread the uneven near work.
+// general per-lane evaluation) over the variant's list of (row tile and its
+// 64-row wave, column chunk, part of NEAR_PART elements) items whose bounding
+// boxes come within the series radius, one item per wave.
 template <int Q, bool CPLX, bool BM>
 __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f64(const char* __restrict__ g, GeomLayout L,
                                                                            int N, int n_if, int q_rt,
@@ -801,20 +815,40 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f64(const 
 {
     __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
     __shared__ ElemL ell[COL_CHUNK];
-    assemble_chunk<Q, CPLX, BM, false, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], blockIdx.y, -1, side, A, lda,
-                                              A32, lda32, gp, ell);
+    assemble_chunk<Q, CPLX, BM, false, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], -1, blockIdx.y, -1, side, A, lda,
+                                              A32, lda32, gp, ell, true);
+}
+
+constexpr int NEAR_WAVES = ROW_TILE / 64;  // list items per near-element workgroup
+static_assert(NEAR_WAVES == 4, "a near item packs the wave of its row tile in two bits");
+
+// The list item of this wave: (row tile * 4 + wave of the tile, chunk, part).
+__device__ __forceinline__ bool near_item(const int* __restrict__ items, int count, int& tile, int& sub, int& chunk,
+                                          int& part)
+{
+    const int k = blockIdx.x * NEAR_WAVES + (int)(threadIdx.x >> 6);
+    if (k >= count) return false;
+    const int tw = items[3 * k];
+    tile = tw >> 2;
+    sub = tw & 3;
+    chunk = items[3 * k + 1];
+    part = items[3 * k + 2];
+    return true;
 }
 
 template <int Q, bool CPLX, bool BM>
 __global__ __launch_bounds__(ROW_TILE, ASM_NEAR_WAVES) void k_assemble_near_f64(const char* __restrict__ g, GeomLayout L, int N,
-                                                                   int n_if, int q_rt, const int* __restrict__ pairs,
-                                                                   int side, double2* __restrict__ A, size_t lda,
-                                                                   float2* __restrict__ A32, size_t lda32)
+                                                                   int n_if, int q_rt, const int* __restrict__ items,
+                                                                   int count, int side, double2* __restrict__ A,
+                                                                   size_t lda, float2* __restrict__ A32, size_t lda32)
 {
-    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
-    __shared__ ElemL ell[COL_CHUNK];
-    assemble_chunk<Q, CPLX, BM, false, true>(g, L, N, n_if, q_rt, pairs[3 * blockIdx.x], pairs[3 * blockIdx.x + 1],
-                                             pairs[3 * blockIdx.x + 2], side, A, lda, A32, lda32, gp, ell);
+    __shared__ GaussL gp[NEAR_WAVES][NEAR_PART * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[NEAR_WAVES][NEAR_PART];
+    int tile = 0, sub = 0, chunk = 0, part = 0;
+    const bool act = near_item(items, count, tile, sub, chunk, part);
+    const int w = threadIdx.x >> 6;
+    assemble_chunk<Q, CPLX, BM, false, true>(g, L, N, n_if, q_rt, tile, sub, chunk, part, side, A, lda, A32, lda32,
+                                             gp[w], ell[w], act);
 }
 
 template <int Q, bool CPLX, bool BM>
@@ -825,19 +859,23 @@ __global__ __launch_bounds__(ROW_TILE, ASM_FAR_WAVES) void k_assemble_f32(const 
 {
     __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
     __shared__ ElemL ell[COL_CHUNK];
-    assemble_chunk<Q, CPLX, BM, true, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], blockIdx.y, -1, side, A, lda,
-                                             nullptr, 0, gp, ell);
+    assemble_chunk<Q, CPLX, BM, true, false>(g, L, N, n_if, q_rt, tiles[blockIdx.x], -1, blockIdx.y, -1, side, A, lda,
+                                             nullptr, 0, gp, ell, true);
 }
 
 template <int Q, bool CPLX, bool BM>
 __global__ __launch_bounds__(ROW_TILE, ASM_NEAR_WAVES) void k_assemble_near_f32(const char* __restrict__ g, GeomLayout L, int N,
-                                                                   int n_if, int q_rt, const int* __restrict__ pairs,
-                                                                   int side, float2* __restrict__ A, size_t lda)
+                                                                   int n_if, int q_rt, const int* __restrict__ items,
+                                                                   int count, int side, float2* __restrict__ A,
+                                                                   size_t lda)
 {
-    __shared__ GaussL gp[COL_CHUNK * (Q > 0 ? Q : QMAX)];
-    __shared__ ElemL ell[COL_CHUNK];
-    assemble_chunk<Q, CPLX, BM, true, true>(g, L, N, n_if, q_rt, pairs[3 * blockIdx.x], pairs[3 * blockIdx.x + 1],
-                                            pairs[3 * blockIdx.x + 2], side, A, lda, nullptr, 0, gp, ell);
+    __shared__ GaussL gp[NEAR_WAVES][NEAR_PART * (Q > 0 ? Q : QMAX)];
+    __shared__ ElemL ell[NEAR_WAVES][NEAR_PART];
+    int tile = 0, sub = 0, chunk = 0, part = 0;
+    const bool act = near_item(items, count, tile, sub, chunk, part);
+    const int w = threadIdx.x >> 6;
+    assemble_chunk<Q, CPLX, BM, true, true>(g, L, N, n_if, q_rt, tile, sub, chunk, part, side, A, lda, nullptr, 0,
+                                            gp[w], ell[w], act);
 }
 }  // namespace
 
@@ -865,7 +903,7 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
         if (counts[v] == 0) continue;
         const hipStream_t s = (k++ & 1) ? s1 : s0;
         const int side = v >> 2 & 1, bm = v >> 1 & 1, cplx = v & 1;
-        const dim3 grid(counts[v], n_cchunks, 1), ngrid(pair_counts[v], 1, 1);
+        const dim3 grid(counts[v], n_cchunks, 1), ngrid((pair_counts[v] + NEAR_WAVES - 1) / NEAR_WAVES, 1, 1);
 #define BEM_ASM_LAUNCH(C_, B_)                                                                                    \
     if (cplx == C_ && bm == B_) {                                                                                 \
         if constexpr (F64) {                                                                                      \
@@ -873,13 +911,13 @@ void launch_variants(const char* g, const GeomLayout& L, int N, int n_if, int n_
                                side, reinterpret_cast<double2*>(A), lda, A32, lda32);                              \
             if (pair_counts[v] > 0)                                                                               \
                 hipLaunchKernelGGL((k_assemble_near_f64<Q, C_, B_>), ngrid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q,   \
-                                   pairs[v], side, reinterpret_cast<double2*>(A), lda, A32, lda32);                \
+                                   pairs[v], pair_counts[v], side, reinterpret_cast<double2*>(A), lda, A32, lda32);\
         } else {                                                                                                  \
             hipLaunchKernelGGL((k_assemble_f32<Q, C_, B_>), grid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q, lists[v],   \
                                side, reinterpret_cast<float2*>(A), lda);                                           \
             if (pair_counts[v] > 0)                                                                               \
                 hipLaunchKernelGGL((k_assemble_near_f32<Q, C_, B_>), ngrid, dim3(ROW_TILE), 0, s, g, L, N, n_if, q,   \
-                                   pairs[v], side, reinterpret_cast<float2*>(A), lda);                             \
+                                   pairs[v], pair_counts[v], side, reinterpret_cast<float2*>(A), lda);             \
         }                                                                                                         \
     }
         BEM_ASM_LAUNCH(false, false)

@@ -103,7 +103,7 @@ struct bem_problem {
     std::vector<Tile> rtiles, cchunks;
     std::vector<int> vtiles;                     // row-tile ids grouped by assembly variant
     int vcount[bemk::ASM_VARIANTS] = {0}, voff[bemk::ASM_VARIANTS] = {0};
-    std::vector<int> npairs;  // (row tile, column chunk, part) triples that may hold near element pairs, by variant
+    std::vector<int> npairs;  // (row tile * 4 + wave, column chunk, part) items that may hold near pairs, by variant
     int ncount[bemk::ASM_VARIANTS] = {0}, noff[bemk::ASM_VARIANTS] = {0};
     std::vector<int> elif;          // interface of each element
     std::vector<int> elnodes;       // (a, b) node indices per element
@@ -424,13 +424,14 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
             p->vcount[v] = (int)lists[v].size();
             p->vtiles.insert(p->vtiles.end(), lists[v].begin(), lists[v].end());
         }
-        // Near list of each variant: (row tile, column chunk, part) triples --
-        // a part being NEAR_PART consecutive elements of the chunk -- whose
-        // bounding boxes (collocation points; element midpoints widened by the
-        // largest half length) come within the series radius XS/|k_d| of the
-        // rows' domain (the larger FP64 radius; relative margin 1e-6).  Only
-        // these can hold an element the assembly's per-wave test calls near,
-        // so the near-element launch runs over them alone, in small blocks.
+        // Near list of each variant: (row tile * 4 + 64-row wave of the tile,
+        // column chunk, part) triples -- a part being NEAR_PART consecutive
+        // elements of the chunk -- whose bounding boxes (collocation points;
+        // element midpoints widened by the largest half length) come within
+        // the series radius XS/|k_d| of the rows' domain (the larger FP64
+        // radius; relative margin 1e-6).  Only these can hold an element the
+        // assembly's per-wave test calls near, so the near-element launch runs
+        // over them alone, one wave per item.
         struct Box {
             double x0, x1, y0, y1, hh;
         };
@@ -449,8 +450,13 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
             return b;
         };
         constexpr int NP = bemk::COL_CHUNK / bemk::NEAR_PART;
-        std::vector<Box> rb(p->rtiles.size()), cb(p->cchunks.size() * NP);
-        for (size_t t = 0; t < p->rtiles.size(); ++t) rb[t] = box(p->rtiles[t].start, p->rtiles[t].count);
+        constexpr int NW = bemk::ROW_TILE / 64;
+        std::vector<Box> rb(p->rtiles.size() * NW), cb(p->cchunks.size() * NP);
+        for (size_t t = 0; t < p->rtiles.size(); ++t)
+            for (int w = 0; w < NW; ++w) {
+                const int s0 = 64 * w, cnt = std::min(64, p->rtiles[t].count - s0);
+                rb[t * NW + w] = cnt > 0 ? box(p->rtiles[t].start + s0, cnt) : Box{1e300, 1e300, 1e300, 1e300, 0.0};
+            }
         for (size_t c = 0; c < p->cchunks.size(); ++c)
             for (int q = 0; q < NP; ++q) {
                 const int s0 = q * bemk::NEAR_PART, cnt = std::min(bemk::NEAR_PART, p->cchunks[c].count - s0);
@@ -463,21 +469,22 @@ bem_status bem_create(const bem_desc* desc, bem_problem** out)
                 const IfacePlan& P = p->iface[p->rtiles[t].iface];
                 const int d = side ? P.dr : P.dl;
                 const double rs = std::max(bemk::XS_SERIES_F64, bemk::XS_SERIES_F32) / std::abs(p->k[d]);
-                for (size_t c = 0; c < p->cchunks.size(); ++c) {
-                    if (p->sigma[(size_t)d * p->n_if + p->cchunks[c].iface] == 0) continue;
-                    for (int q = 0; q < NP; ++q) {
-                        if (q * bemk::NEAR_PART >= p->cchunks[c].count) break;
-                        const Box &a = rb[t], &b = cb[c * NP + q];
-                        const double dx = std::max(0.0, std::max(a.x0 - b.x1, b.x0 - a.x1));
-                        const double dy = std::max(0.0, std::max(a.y0 - b.y1, b.y0 - a.y1));
-                        const double lim = (rs + b.hh) * (1.0 + 1e-6) + 1e-12;
-                        if (dx * dx + dy * dy < lim * lim) {
-                            p->npairs.push_back(t);
-                            p->npairs.push_back((int)c);
-                            p->npairs.push_back(q);
+                for (int w = 0; w < NW && 64 * w < p->rtiles[t].count; ++w)
+                    for (size_t c = 0; c < p->cchunks.size(); ++c) {
+                        if (p->sigma[(size_t)d * p->n_if + p->cchunks[c].iface] == 0) continue;
+                        for (int q = 0; q < NP; ++q) {
+                            if (q * bemk::NEAR_PART >= p->cchunks[c].count) break;
+                            const Box &a = rb[t * NW + w], &b = cb[c * NP + q];
+                            const double dx = std::max(0.0, std::max(a.x0 - b.x1, b.x0 - a.x1));
+                            const double dy = std::max(0.0, std::max(a.y0 - b.y1, b.y0 - a.y1));
+                            const double lim = (rs + b.hh) * (1.0 + 1e-6) + 1e-12;
+                            if (dx * dx + dy * dy < lim * lim) {
+                                p->npairs.push_back(t * NW + w);
+                                p->npairs.push_back((int)c);
+                                p->npairs.push_back(q);
+                            }
                         }
                     }
-                }
             }
             p->ncount[v] = (int)p->npairs.size() / 3 - p->noff[v];
         }
