@@ -812,20 +812,24 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
         g.profile(True)
         g.profile_read(reset=True)
     torch.cuda.synchronize()
+    w0 = time.monotonic_ns()  # the clock of rocprofv3's timestamps: lets a trace pick out the timed launches
     t0 = time.perf_counter()
     for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    windows = {"timed": [w0, time.monotonic_ns()]}
     prof = [g.profile_read(reset=True) for g in probs]
     iso = None
     if concurrent:
         # the product kernel on its own: two more steps with the cases one
         # after the other (outside the timed region), timed by the same events
         mode["concurrent"] = False
+        w1 = time.monotonic_ns()
         for _ in range(2):
             step(False)
         torch.cuda.synchronize()
+        windows["isolated"] = [w1, time.monotonic_ns()]
         iso = [g.profile_read(reset=True) for g in probs]
         mode["concurrent"] = True
     for g in probs:
@@ -905,6 +909,7 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
         "tuning": tuning,
         "graph_steps": graph_steps,
         "roofline": roofline,
+        "monotonic_ns": windows,
     }
     if mixed:
         out["refinement_steps_per_rhs"] = [r / (steps * nr) for r in refine]
