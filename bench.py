@@ -337,6 +337,7 @@ def matvec_mode(args, wl, P, torch, prec):
     A = matrix_buffer(g, prec, P, torch)
     g.assemble(prec, out=A, lda=A.shape[1])
     tuning = tune_or_import(args, P, g, len(wl.angles))
+    g.assemble(prec, out=A, lda=A.shape[1])  # a problem takes the table's shapes when it is assembled
     X = g.rhs(wl.angles)
     if prec == P.F32:
         X = X.to(torch.complex64)
@@ -871,7 +872,14 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
                     if nr > 4 else f"k_matvec (FP64 VALU split-K product, {nr} right-hand side(s))",
                     "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_record(wl.name)}
+    assembly_rec = assembly_record(wl, as_launch, as_avg_ms, evals)
     if iso:
+        # the cases' assemblies overlap in the timed region (each then takes
+        # about twice as long); the rate is that of one assembly at a time
+        ia = sum(p["assemble_launches"] for p in iso)
+        assembly_rec = assembly_record(wl, ia, sum(p["assemble_ms"] for p in iso) / max(1, ia), evals)
+        assembly_rec["timing"] = "cases one after another, two steps after the timed region (library HIP events)"
+        assembly_rec["avg_ms_in_timed_region"] = as_avg_ms
         iso_ms = sum(p["matvec_ms"] for p in iso) / max(1, sum(p["matvec_launches"] for p in iso))
         achieved = (mv_tfs if mixed else mv_gbs) * mv_avg_ms / iso_ms
         roofline["isolated"] = {
@@ -902,7 +910,7 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
                                  f"+ {nr} solves + far field (served latency: the served record)"},
         "cases_concurrent": concurrent,
         "gmres_iterations_per_rhs": [it / (steps * nr) for it in iters],
-        "assembly": assembly_record(wl, as_launch, as_avg_ms, evals),
+        "assembly": assembly_rec,
         "matvec": {"launches": mv_launch, "avg_ms": mv_avg_ms, "GB_per_s": mv_gbs, "TFLOP_per_s": mv_tfs,
                    "share_of_step_time": mv_ms / (T * 1e3)},
         "residual": {"launches": rs_launch, "avg_ms": rs_ms / max(1, rs_launch)},
