@@ -508,7 +508,7 @@ def served_record(args, P, torch, n_requests, open_loop=True):
 
     def closed_loop(prec, tol):
         with S.Server(arena, slots=args.slots, prec=prec, tol=tol, restart=args.serve_restart, dirs=dirs,
-                      graph_steps=args.graph_steps) as srv:
+                      graph_steps=args.graph_steps, fuse=args.fuse) as srv:
             for r in reqs[:8]:  # warm-up: code objects, host paths
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -534,7 +534,7 @@ def served_record(args, P, torch, n_requests, open_loop=True):
     log(f"  {T64:.1f} s; FP64 reference to 1e-12 on every 10th request ...")
     sample = list(range(0, len(reqs), 10))
     with S.Server(arena, slots=args.slots, prec=P.F64, tol=1e-12, restart=args.serve_restart, dirs=dirs,
-                  graph_steps=args.graph_steps) as srv:
+                  graph_steps=args.graph_steps, fuse=args.fuse) as srv:
         ids = {srv.submit(reqs[i]["spec"], reqs[i]["angles"]): i for i in sample}
         ref = {ids[o.id]: o for o in srv.drain()}
     bad = [i for i in range(len(reqs)) if r32[i].status != 0 or r64[i].status != 0]
@@ -545,7 +545,7 @@ def served_record(args, P, torch, n_requests, open_loop=True):
     if open_loop:
         log("  open loop at the arrival times ...")
         with S.Server(arena, slots=args.slots, prec=P.MIXED, tol=args.serve_tol, restart=args.serve_restart,
-                      dirs=dirs, graph_steps=args.graph_steps) as srv:
+                      dirs=dirs, graph_steps=args.graph_steps, fuse=args.fuse) as srv:
             for r in reqs[:8]:
                 srv.submit(r["spec"], r["angles"])
             srv.drain()
@@ -570,7 +570,7 @@ def served_record(args, P, torch, n_requests, open_loop=True):
                     f"circles N 512-8192 log-uniform, k0 U[1,50], k1/k0 U[1.2,3], 1-32 angles",
         "requests": len(reqs), "solves": solves, "slots": args.slots, "arena_GiB": args.arena_gb,
         "tol": args.serve_tol, "restart": args.serve_restart, "far_field_dirs": len(dirs),
-        "graph_steps": args.graph_steps,
+        "graph_steps": args.graph_steps, "fuse": args.fuse,
         "capacity": {"mixed_solves_per_s": solves / T32, "fp64_solves_per_s": solves / T64,
                      "mixed_over_fp64": T64 / T32,
                      "mixed_requests_per_s": len(reqs) / T32, "fp64_requests_per_s": len(reqs) / T64,
@@ -613,7 +613,7 @@ def serve_mode(args, P, torch):
         "config": {"workload": rec["workload"], "requests": rec["requests"], "solves": rec["solves"],
                    "slots": rec["slots"], "arena_GiB": rec["arena_GiB"], "tol": rec["tol"],
                    "restart": rec["restart"], "far_field_dirs": rec["far_field_dirs"],
-                   "graph_steps": rec["graph_steps"]},
+                   "graph_steps": rec["graph_steps"], "fuse": rec["fuse"]},
         "roofline": None,
     }
     out.update({k: rec[k] for k in ("capacity", "accuracy", "precision", "gmres_iterations_max_per_request")})
@@ -947,6 +947,8 @@ def main():
     ap.add_argument("--serve-restart", type=int, default=300,
                     help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
+    ap.add_argument("--fuse", type=int, default=1,
+                    help="serve: requests a slot admits together and solves as one batch with fused Krylov launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the precision-path, served-prefix and disk256 records")

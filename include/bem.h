@@ -251,6 +251,25 @@ bem_status bem_solve(bem_problem *p, int nrhs, const void *B_dev, size_t ldb, co
                      void *X_dev, size_t ldx, void *work_dev, size_t work_bytes, bem_solve_info *info,
                      hipStream_t stream);
 
+/* bem_solve for np (1..8) distinct problems at once, on one stream, with the
+ * same options: their restart cycles run in step, each Krylov step launching
+ * every problem's product and then one fused set of orthogonalisation
+ * kernels (projections, Arnoldi step, update, normalisation) for all of them;
+ * a problem whose columns have all stopped drops out of the steps, and at a
+ * cycle end each problem restarts or finishes on its own (mixed precision:
+ * the outer refinement steps run in step as well).  Every argument is an
+ * array over the problems (host arrays of np entries; ps[k], B_dev[k],
+ * X_dev[k], work_dev[k], info[k] as the same arguments of bem_solve).  The
+ * problems must all be BEM_F64 or all FP32-product (BEM_F32 / BEM_MIXED).
+ * Each problem's X and info are bit-identical to those of bem_solve on it
+ * alone (the fused kernels run each problem's arithmetic in the same order);
+ * graph_steps is ignored for np > 1.  Returns the first error met, or
+ * BEM_E_NONFINITE / BEM_E_NOCONV if any column of any problem met it.      */
+bem_status bem_solve_batch(int np, bem_problem *const *ps, const int *nrhs, const void *const *B_dev,
+                           const size_t *ldb, const bem_solve_opts *opts, void *const *X_dev, const size_t *ldx,
+                           void *const *work_dev, const size_t *work_bytes, bem_solve_info *const *info,
+                           hipStream_t stream);
+
 /* Far-field pattern of the scattered field in the host medium for nrhs
  * solutions (complex128 X_dev, ldx >= n): u_sc ~ e^{i k0 |x|} / sqrt|x| F,
  *   F(th) = e^{i pi/4} / sqrt(8 pi k0) sum_j sigma_j [w_j + i k0 (xh.n_j) u_j]

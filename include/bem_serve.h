@@ -14,7 +14,8 @@
  * Scheduling:
  *   - the server owns `slots` worker threads, each with its own non-blocking
  *     HIP stream at the default priority; a request runs entirely on one
- *     slot's stream, so the device work of up to `slots` requests overlaps;
+ *     slot's stream, so the device work of up to `slots` requests overlaps
+ *     (up to slots * fuse with fused batches, bem_server_opts.fuse);
  *   - every request's device buffers (geometry tables, matrix, solver
  *     workspace, right-hand sides, solution, far field) are one contiguous
  *     block of the caller-owned arena; the block is the request's footprint
@@ -31,7 +32,7 @@
  *     the process makes meanwhile.
  *
  * The server allocates no device memory.  Host memory: request copies and
- * one pinned flag buffer per slot.
+ * one pinned flag buffer per slot (fuse parts of it with fused batches).
  */
 #ifndef BEM_SERVE_H
 #define BEM_SERVE_H
@@ -53,6 +54,12 @@ typedef struct {
     bem_solve_opts solve;   /* GMRES options of every request (bem_solve)              */
     int ndir;               /* far-field directions reported per right-hand side, >= 1 */
     const double *dirs;     /* [ndir] direction angles (host; copied at create)        */
+    int fuse;               /* 0 or 1: a slot runs one request at a time; 2..8: a slot
+                               that admits a request also admits up to fuse - 1 more
+                               waiting ones that fit and solves them together
+                               (bem_solve_batch: restart cycles in step, one fused set
+                               of orthogonalisation launches per Krylov step for all
+                               of them); their results are posted when the batch ends */
 } bem_server_opts;
 
 /* Outcome of one request. */
@@ -73,8 +80,8 @@ typedef struct {
 
 /* Validate the options, copy the directions, create the slot streams and
  * threads.  BEM_E_ARG: slots outside 1..16, a null or unaligned arena, ndir < 1,
- * prec not a bem_prec, restart < 1.  BEM_E_DEVICE: stream or thread set-up
- * failed.                                                                    */
+ * prec not a bem_prec, restart < 1, fuse outside 0..8.  BEM_E_DEVICE: stream
+ * or thread set-up failed.                                                   */
 bem_status bem_server_create(const bem_server_opts *opts, bem_server **out);
 
 /* Arena bytes a request would hold (plus bem_create's validation errors). */

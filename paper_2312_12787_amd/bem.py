@@ -26,7 +26,7 @@ STATUS = {0: "BEM_OK", 1: "BEM_E_ARG", 2: "BEM_E_GEOMETRY", 3: "BEM_E_STATE", 4:
           5: "BEM_E_NOMEM", 6: "BEM_E_NOCONV", 7: "BEM_E_NONFINITE"}
 EXPORTS = ["bem_create", "bem_destroy", "bem_n_elements", "bem_order", "bem_sizes", "bem_geometry",
            "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_matvec_noalloc", "bem_solve",
-           "bem_farfield", "bem_nearfield",
+           "bem_solve_batch", "bem_farfield", "bem_nearfield",
            "bem_profile_enable", "bem_profile_read", "bem_tune", "bem_tune_export", "bem_tune_import",
            "bem_tune_reset", "bem_last_error"]
 
@@ -92,6 +92,9 @@ def lib():
         L.bem_matvec_noalloc.argtypes = [vp, C.c_int, vp, sz, vp, sz, vp]
         L.bem_solve.argtypes = [vp, C.c_int, vp, sz, C.POINTER(bem_solve_opts), vp, sz, vp, sz,
                                 C.POINTER(bem_solve_info), vp]
+        L.bem_solve_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(C.c_int), C.POINTER(vp), C.POINTER(sz),
+                                      C.POINTER(bem_solve_opts), C.POINTER(vp), C.POINTER(sz), C.POINTER(vp),
+                                      C.POINTER(sz), C.POINTER(C.POINTER(bem_solve_info)), vp]
         L.bem_farfield.argtypes = [vp, C.c_int, vp, sz, C.c_int, C.POINTER(C.c_double), vp, sz, vp, sz, vp]
         L.bem_nearfield.argtypes = [vp, C.c_int, vp, sz, C.POINTER(C.c_double), C.c_int, vp, vp, vp, sz, vp]
         L.bem_profile_enable.argtypes = [vp, C.c_int]
@@ -104,7 +107,7 @@ def lib():
         L.bem_tune_reset.restype = None
         L.bem_last_error.restype = C.c_char_p
         for f in ["bem_tune", "bem_tune_import", "bem_create", "bem_sizes", "bem_geometry", "bem_geometry_update", "bem_assemble", "bem_rhs", "bem_matvec", "bem_matvec_noalloc",
-                  "bem_solve", "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
+                  "bem_solve", "bem_solve_batch", "bem_farfield", "bem_nearfield", "bem_profile_enable", "bem_profile_read"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -401,3 +404,32 @@ class Problem:
                                    C.c_void_p(pts.data_ptr()), C.c_void_p(dm.data_ptr()), C.c_void_p(U.data_ptr()),
                                    U.shape[1], _stream(stream)))
         return U[:, :npts]
+
+
+def solve_batch(problems, Bs, restart: int = 100, tol: float = 1e-10, max_iter: int = 10000, inner_tol: float = 0.0,
+                max_refine: int = 0, stream=None):
+    """bem_solve_batch: solve A_k X_k = B_k for up to 8 assembled problems at
+    once (restart cycles in step, fused orthogonalisation launches); returns
+    [(X_k, SolveInfo_k)].  Bs[k]: complex128 (nrhs_k, n_k)."""
+    import torch
+    npb = len(problems)
+    Bs = [B.contiguous() for B in Bs]
+    Xs = [torch.empty_like(B) for B in Bs]
+    Ws = []
+    for g, B in zip(problems, Bs):
+        _, _, wb = g.sizes(g.prec if g.prec is not None else F64, B.shape[0], restart)
+        Ws.append(g._workspace(wb))
+    infos = [(bem_solve_info * B.shape[0])() for B in Bs]
+    vp = C.c_void_p
+    arr = lambda t, vals: (t * npb)(*vals)
+    opts = bem_solve_opts(restart, max_iter, tol, inner_tol, max_refine, 0)
+    info_ptrs = (C.POINTER(bem_solve_info) * npb)(*[C.cast(i, C.POINTER(bem_solve_info)) for i in infos])
+    st = lib().bem_solve_batch(npb, arr(vp, [g._h.value for g in problems]), arr(C.c_int, [B.shape[0] for B in Bs]),
+                               arr(vp, [B.data_ptr() for B in Bs]), arr(C.c_size_t, [B.shape[1] for B in Bs]),
+                               C.byref(opts), arr(vp, [X.data_ptr() for X in Xs]),
+                               arr(C.c_size_t, [X.shape[1] for X in Xs]), arr(vp, [W.data_ptr() for W in Ws]),
+                               arr(C.c_size_t, [W.numel() for W in Ws]), info_ptrs, _stream(stream))
+    _check(st, allow=(6,))
+    return [(X, SolveInfo(np.array([i.iters for i in inf]), np.array([i.restarts for i in inf]),
+                          np.array([i.converged for i in inf]), np.array([i.rel_residual for i in inf]), st))
+            for X, inf in zip(Xs, infos)]

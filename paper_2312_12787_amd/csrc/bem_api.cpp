@@ -1029,81 +1029,96 @@ bem_status segment_graph(Solver& c, bemk::ArnoldiArgs arn, int sg, int S, int ri
 // each cycle with FP64 accumulation.  Columns with want[r] == 0 are left
 // untouched.  iters[r] counts completed Krylov steps; tol[r] is the relative
 // tolerance of column r.
+//
+// A batch runs several problems (same restart length and basis precision, one
+// stream) in step: each step launches every running problem's product, then
+// one fused set of orthogonalisation launches for all of them
+// (launch_arnoldi_set); a problem whose columns have all stopped leaves the
+// step loop, and at the end of a cycle each problem restarts or finishes on
+// its own.  A problem's results do not depend on the batch it runs in.
+struct GmItem {
+    Solver* c = nullptr;
+    const double2* B = nullptr;
+    size_t ldb = 0;
+    double2* X = nullptr;
+    size_t ldx = 0;
+    std::vector<double> tol;
+    int maxit = 0;
+    std::vector<int> want;
+    std::vector<int>* iters = nullptr;
+    std::vector<int>* conv = nullptr;
+    std::vector<double>* rel = nullptr;
+    std::vector<int>* cycles = nullptr;
+    bool nonfinite = false;
+    // run state
+    std::vector<double> bnorm, rnorm;
+    std::vector<int> alive;
+    bemk::ArnoldiArgs arn{};
+    bemk::ProductPlan pl{};
+    void* xt = nullptr;
+    bool run = false;  // still stepping in the current cycle
+    bool any_alive() const { return std::count(alive.begin(), alive.end(), 1) > 0; }
+};
 
-bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx, const std::vector<double>& tol,
-                 int maxit,
-                 const std::vector<int>& want, std::vector<int>& iters, std::vector<int>& conv,
-                 std::vector<double>& rel, std::vector<int>& cycles, bool& nonfinite)
+// Start of a GMRES run: X = 0 on the wanted columns, R = B, norms, stopping
+// thresholds, the flag ring (ring slots per column) and the step arguments.
+bem_status gmres_begin(GmItem& g, int ring, int nev)
 {
+    Solver& c = *g.c;
     const int n = c.n, nr = c.nr, m = c.m;
     const size_t ldv = c.W.ldv;
     double2* R = c.at<double2>(c.W.R);
-    double2* Wv = c.at<double2>(c.W.W);
     for (int r = 0; r < nr; ++r)
-        if (want[r]) HIP_OK(hipMemsetAsync(X + (size_t)r * ldx, 0, (size_t)n * sizeof(double2), c.s));
-    HIP_OK(hipMemcpy2DAsync(R, ldv * sizeof(double2), B, ldb * sizeof(double2), (size_t)n * sizeof(double2), nr,
+        if (g.want[r]) HIP_OK(hipMemsetAsync(g.X + (size_t)r * g.ldx, 0, (size_t)n * sizeof(double2), c.s));
+    HIP_OK(hipMemcpy2DAsync(R, ldv * sizeof(double2), g.B, g.ldb * sizeof(double2), (size_t)n * sizeof(double2), nr,
                             hipMemcpyDeviceToDevice, c.s));
-    std::vector<double> bnorm, rnorm;
-    if (bem_status st = col_norms(c, B, ldb, c.at<double>(c.W.bnorm), bnorm)) return st;
-    rnorm = bnorm;
-    HIP_OK(hipMemcpyAsync(c.at<double>(c.W.rnorm), rnorm.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
-    std::vector<int> alive(nr, 0);
+    if (bem_status st = col_norms(c, g.B, g.ldb, c.at<double>(c.W.bnorm), g.bnorm)) return st;
+    g.rnorm = g.bnorm;
+    HIP_OK(hipMemcpyAsync(c.at<double>(c.W.rnorm), g.rnorm.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
+    g.alive.assign(nr, 0);
     for (int r = 0; r < nr; ++r) {
-        if (!want[r]) continue;
-        if (!std::isfinite(bnorm[r])) {
-            nonfinite = true;
+        if (!g.want[r]) continue;
+        if (!std::isfinite(g.bnorm[r])) {
+            g.nonfinite = true;
             continue;
         }
-        if (bnorm[r] == 0.0) {
-            conv[r] = 1;
-            rel[r] = 0.0;
+        if (g.bnorm[r] == 0.0) {
+            (*g.conv)[r] = 1;
+            (*g.rel)[r] = 0.0;
             continue;
         }
-        alive[r] = 1;
+        g.alive[r] = 1;
     }
     // device-side stopping thresholds and counters
     std::vector<double> thr(nr);
-    for (int r = 0; r < nr; ++r) thr[r] = tol[(size_t)r] * bnorm[r];
+    for (int r = 0; r < nr; ++r) thr[r] = g.tol[(size_t)r] * g.bnorm[r];
     HIP_OK(hipMemcpyAsync(c.at<double>(c.W.thr), thr.data(), nr * sizeof(double), hipMemcpyHostToDevice, c.s));
-    HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), iters.data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
-    // The GPU decides per right-hand side when to stop (k_dc_step, which also
-    // writes the decision into a ring of pinned host slots); the host reads
-    // the flags `lag` steps behind, so the queue never drains.  A
-    // small matrix gets a longer lag (its steps are shorter than the host's
-    // launch work); steps enqueued after every column stopped do nothing but
-    // an unused product.
-    // With captured segments of S steps the host reads the flags of a
-    // segment's last step one segment late: S + 1 slots keep that slot clear
-    // of the segment running meanwhile; two events mark segment ends.
-    const bool graphs = c.graph > 0 && !c.p->prof.on;
-    const int S = graphs ? c.graph : 0;
-    const int lag = graphs ? 1 : flag_lag(n, c.p->prec);
-    const int ring = graphs ? S + 1 : lag + 1;
-    const int nev = graphs ? 2 : ring;
-    if (c.p->pinned_ints < (size_t)ring * nr) {
-        if (c.p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than the flag ring times nrhs");
-        if (c.p->pinned) HIP_OK(hipHostFree(c.p->pinned));
-        c.p->pinned = nullptr;
-        c.p->pinned_dev = nullptr;
-        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&c.p->pinned), (size_t)ring * nr * sizeof(int),
+    HIP_OK(hipMemcpyAsync(c.at<int>(c.W.iters), g.iters->data(), nr * sizeof(int), hipMemcpyHostToDevice, c.s));
+    bem_problem* p = c.p;
+    if (p->pinned_ints < (size_t)ring * nr) {
+        if (p->lent) return fail(BEM_E_ARG, "lent flag buffer smaller than the flag ring times nrhs");
+        if (p->pinned) HIP_OK(hipHostFree(p->pinned));
+        p->pinned = nullptr;
+        p->pinned_dev = nullptr;
+        HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p->pinned), (size_t)ring * nr * sizeof(int),
                              hipHostMallocMapped | hipHostMallocCoherent));
-        c.p->pinned_ints = (size_t)ring * nr;
+        p->pinned_ints = (size_t)ring * nr;
     }
-    if (!c.p->pinned_dev)
-        HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.p->pinned_dev), c.p->pinned, 0));
+    if (!p->pinned_dev) HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&p->pinned_dev), p->pinned, 0));
     for (int k = 0; k < nev; ++k)
-        if (!c.p->flag_ev[k]) {
-            if (c.p->lent) return fail(BEM_E_ARG, "lent flag events fewer than the flag ring");
-            HIP_OK(hipEventCreateWithFlags(&c.p->flag_ev[k], hipEventDisableTiming));
+        if (!p->flag_ev[k]) {
+            if (p->lent) return fail(BEM_E_ARG, "lent flag events fewer than the flag ring");
+            HIP_OK(hipEventCreateWithFlags(&p->flag_ev[k], hipEventDisableTiming));
         }
-    bemk::ArnoldiArgs arn{};
+    bemk::ArnoldiArgs& arn = g.arn;
+    arn = bemk::ArnoldiArgs{};
     arn.V = c.V(0);
     arn.v32 = c.v32();
     arn.ldv = ldv;
     arn.nr = nr;
     arn.m = m;
     arn.n = n;
-    arn.W = Wv;
+    arn.W = c.at<double2>(c.W.W);
     arn.ldw = ldv;
     arn.partP = c.at<double2>(c.W.dot_part);
     arn.partQ = c.at<double2>(c.W.dot_part2);
@@ -1118,94 +1133,174 @@ bem_status gmres(Solver& c, const double2* B, size_t ldb, double2* X, size_t ldx
     arn.hnorm = c.at<double>(c.W.hnorm);
     arn.norm_part = c.at<double>(c.W.upd_part);
     arn.thr = c.at<double>(c.W.thr);
-    arn.maxit = maxit;
+    arn.maxit = g.maxit;
     arn.iters = c.at<int>(c.W.iters);
     arn.kdim = c.at<int>(c.W.kdim);
     arn.active = c.at<int>(c.W.active);
-    const bemk::ProductPlan pl = step_plan(c);
+    g.pl = step_plan(c);
     // the products read v_j packed (more than 4 right-hand sides), written by
     // the cycle start and the step's normalisation kernel
-    void* xt = nullptr;
-    if (pl.ng > 0) {
+    g.xt = nullptr;
+    if (g.pl.ng > 0) {
         if (c.v32())
-            xt = reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)) + pl.xt_offset;
+            g.xt = reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)) + g.pl.xt_offset;
         else
-            xt = c.at<double2>(c.W.mv_part) + pl.xt_offset;
-        arn.xt = xt;
-        arn.xw = pl.xw;
+            g.xt = c.at<double2>(c.W.mv_part) + g.pl.xt_offset;
+        arn.xt = g.xt;
+        arn.xw = g.pl.xw;
     }
+    return BEM_OK;
+}
+
+// Start of a cycle: the active flags, v_0 = r / |r| (and its packed copy), g.
+bem_status gmres_cycle_start(GmItem& g)
+{
+    Solver& c = *g.c;
+    const size_t ldv = c.W.ldv;
+    double2* R = c.at<double2>(c.W.R);
+    if (bem_status st = upload_ints(c, c.W.active, g.alive)) return st;
+    HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, c.nr * sizeof(int), c.s));
+    if (c.v32())
+        HIP_OK(bemk::launch_start_cycle(R, ldv, c.n, c.nr, c.at<double>(c.W.rnorm), c.m, c.V32(0), ldv,
+                                        c.at<double2>(c.W.gvec), c.at<int>(c.W.active), static_cast<float2*>(g.xt),
+                                        g.pl.xw, c.s));
+    else
+        HIP_OK(bemk::launch_start_cycle(R, ldv, c.n, c.nr, c.at<double>(c.W.rnorm), c.m, c.V(0), ldv,
+                                        c.at<double2>(c.W.gvec), c.at<int>(c.W.active), static_cast<double2*>(g.xt),
+                                        g.pl.xw, c.s));
+    return BEM_OK;
+}
+
+// End of a cycle: the least-squares solution, X update, true residual and its
+// norms, and each column's fate.
+bem_status gmres_cycle_end(GmItem& g)
+{
+    Solver& c = *g.c;
+    const int n = c.n, nr = c.nr, m = c.m;
+    const size_t ldv = c.W.ldv;
+    double2* R = c.at<double2>(c.W.R);
+    HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
+                                  c.at<double2>(c.W.y), c.s));
+    if (c.v32())
+        HIP_OK(bemk::launch_xupdate(c.V32(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx,
+                                    c.s));
+    else
+        HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx, c.s));
+    // FP64 accumulation also inside the refinement: with FP32 products the
+    // rounding of the restart residual (about 1e-7 kappa ||b||) can exceed
+    // the inner tolerance of an ill-conditioned problem, which then never
+    // stops
+    if (bem_status st = residual(c, g.B, g.ldb, g.X, g.ldx, R, ldv)) return st;
     std::vector<int> dev_iters(nr);
-    while (std::count(alive.begin(), alive.end(), 1) > 0) {
-        if (bem_status st = upload_ints(c, c.W.active, alive)) return st;
-        HIP_OK(hipMemsetAsync(c.at<int>(c.W.kdim), 0, nr * sizeof(int), c.s));
-        if (c.v32())
-            HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V32(0), ldv,
-                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active),
-                                            static_cast<float2*>(xt), pl.xw, c.s));
-        else
-            HIP_OK(bemk::launch_start_cycle(R, ldv, n, nr, c.at<double>(c.W.rnorm), m, c.V(0), ldv,
-                                            c.at<double2>(c.W.gvec), c.at<int>(c.W.active),
-                                            static_cast<double2*>(xt), pl.xw, c.s));
-        for (int sg = 0; graphs && sg < (m + S) / S; ++sg) {
-            hipGraphExec_t ex = nullptr;
-            if (bem_status st = segment_graph(c, arn, sg, S, ring, ex)) return st;
-            HIP_OK(hipGraphLaunch(ex, c.s));
-            HIP_OK(hipEventRecord(c.p->flag_ev[sg & 1], c.s));
-            if (sg >= 1) {
-                HIP_OK(hipEventSynchronize(c.p->flag_ev[(sg - 1) & 1]));
-                const int jl = sg * S - 1;  // last step of the previous segment
-                const int* prev = c.p->pinned + (size_t)(jl % ring) * nr;
-                bool any = false;
-                for (int r = 0; r < nr; ++r) any = any || prev[r];
-                if (!any) break;
+    HIP_OK(hipMemcpyAsync(dev_iters.data(), c.at<int>(c.W.iters), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
+    if (bem_status st = col_norms(c, R, ldv, c.at<double>(c.W.rnorm), g.rnorm)) return st;
+    std::vector<int>& iters = *g.iters;
+    for (int r = 0; r < nr; ++r)
+        if (g.alive[r]) iters[r] = dev_iters[r];
+    for (int r = 0; r < nr; ++r) {
+        if (!g.alive[r]) continue;
+        double& rel = (*g.rel)[r];
+        rel = g.rnorm[r] / g.bnorm[r];
+        if (!std::isfinite(rel)) {
+            g.nonfinite = true;
+            g.alive[r] = 0;
+        } else if (rel <= g.tol[(size_t)r]) {
+            (*g.conv)[r] = 1;
+            g.alive[r] = 0;
+        } else if (iters[r] >= g.maxit) {
+            g.alive[r] = 0;
+        } else {
+            ++(*g.cycles)[r];
+        }
+    }
+    return BEM_OK;
+}
+
+bem_status gmres_batch(const std::vector<GmItem*>& items)
+{
+    Solver& c0 = *items[0]->c;
+    const int m = c0.m;
+    // The GPU decides per right-hand side when to stop (k_dc_step, which also
+    // writes the decision into a ring of pinned host slots); the host reads
+    // the flags `lag` steps behind, so the queue never drains.  A
+    // small matrix gets a longer lag (its steps are shorter than the host's
+    // launch work); steps enqueued after every column stopped do nothing but
+    // an unused product.  A batch takes the lag of its largest matrix and the
+    // events of its first problem.
+    // With captured segments of S steps (one problem) the host reads the
+    // flags of a segment's last step one segment late: S + 1 slots keep that
+    // slot clear of the segment running meanwhile; two events mark segment
+    // ends.
+    const bool graphs = items.size() == 1 && c0.graph > 0 && !c0.p->prof.on;
+    const int S = graphs ? c0.graph : 0;
+    int nmax = 0;
+    for (GmItem* g : items) nmax = std::max(nmax, g->c->n);
+    const int lag = graphs ? 1 : flag_lag(nmax, c0.p->prec);
+    const int ring = graphs ? S + 1 : lag + 1;
+    const int nev = graphs ? 2 : ring;
+    for (GmItem* g : items)
+        if (bem_status st = gmres_begin(*g, ring, g == items[0] ? nev : 0)) return st;
+    hipEvent_t* ev = c0.p->flag_ev;
+    hipStream_t s = c0.s;
+    std::vector<bemk::ArnoldiArgs> set;
+    for (;;) {
+        std::vector<GmItem*> cyc;
+        for (GmItem* g : items)
+            if (g->any_alive()) cyc.push_back(g);
+        if (cyc.empty()) break;
+        for (GmItem* g : cyc) {
+            if (bem_status st = gmres_cycle_start(*g)) return st;
+            g->run = true;
+        }
+        if (graphs) {
+            GmItem& g = *cyc[0];
+            Solver& c = *g.c;
+            for (int sg = 0; sg < (m + S) / S; ++sg) {
+                hipGraphExec_t ex = nullptr;
+                if (bem_status st = segment_graph(c, g.arn, sg, S, ring, ex)) return st;
+                HIP_OK(hipGraphLaunch(ex, s));
+                HIP_OK(hipEventRecord(ev[sg & 1], s));
+                if (sg >= 1) {
+                    HIP_OK(hipEventSynchronize(ev[(sg - 1) & 1]));
+                    const int jl = sg * S - 1;  // last step of the previous segment
+                    const int* prev = c.p->pinned + (size_t)(jl % ring) * c.nr;
+                    bool any = false;
+                    for (int r = 0; r < c.nr; ++r) any = any || prev[r];
+                    if (!any) break;
+                }
             }
         }
         for (int j = 0; !graphs && j <= m; ++j) {
-            if (j < m)
-                if (bem_status st = apply_basis(c, j, Wv, ldv)) return st;
-            arn.flags_out = c.p->pinned_dev + (size_t)(j % ring) * nr;
-            HIP_OK(bemk::launch_arnoldi(arn, j, c.s));
-            HIP_OK(hipEventRecord(c.p->flag_ev[j % ring], c.s));
+            set.clear();
+            for (GmItem* g : cyc) {
+                if (!g->run) continue;
+                Solver& c = *g->c;
+                if (j < m)
+                    if (bem_status st = apply_basis(c, j, c.at<double2>(c.W.W), c.W.ldv)) return st;
+                g->arn.flags_out = c.p->pinned_dev + (size_t)(j % ring) * c.nr;
+                set.push_back(g->arn);
+            }
+            for (size_t k = 0; k < set.size(); k += bemk::MAX_FUSED)
+                HIP_OK(bemk::launch_arnoldi_set(set.data() + k, (int)std::min(set.size() - k, (size_t)bemk::MAX_FUSED), j,
+                                                s));
+            HIP_OK(hipEventRecord(ev[j % ring], s));
             if (j >= lag) {
-                HIP_OK(hipEventSynchronize(c.p->flag_ev[(j - lag) % ring]));
-                const int* prev = c.p->pinned + (size_t)((j - lag) % ring) * nr;
-                bool any = false;
-                for (int r = 0; r < nr; ++r) any = any || prev[r];
-                if (!any) break;
+                HIP_OK(hipEventSynchronize(ev[(j - lag) % ring]));
+                bool any_run = false;
+                for (GmItem* g : cyc) {
+                    if (!g->run) continue;
+                    const int* prev = g->c->p->pinned + (size_t)((j - lag) % ring) * g->c->nr;
+                    bool any = false;
+                    for (int r = 0; r < g->c->nr; ++r) any = any || prev[r];
+                    // every column stopped at step j - lag: the later steps were no-ops for it
+                    if (!any) g->run = false;
+                    any_run = any_run || g->run;
+                }
+                if (!any_run) break;
             }
         }
-        HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
-                                      c.at<double2>(c.W.y), c.s));
-        if (c.v32())
-            HIP_OK(bemk::launch_xupdate(c.V32(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx,
-                                        c.s));
-        else
-            HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), X, ldx,
-                                        c.s));
-        // FP64 accumulation also inside the refinement: with FP32 products the
-        // rounding of the restart residual (about 1e-7 kappa ||b||) can exceed
-        // the inner tolerance of an ill-conditioned problem, which then never
-        // stops
-        if (bem_status st = residual(c, B, ldb, X, ldx, R, ldv)) return st;
-        HIP_OK(hipMemcpyAsync(dev_iters.data(), c.at<int>(c.W.iters), nr * sizeof(int), hipMemcpyDeviceToHost, c.s));
-        if (bem_status st = col_norms(c, R, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;
-        for (int r = 0; r < nr; ++r)
-            if (alive[r]) iters[r] = dev_iters[r];
-        for (int r = 0; r < nr; ++r) {
-            if (!alive[r]) continue;
-            rel[r] = rnorm[r] / bnorm[r];
-            if (!std::isfinite(rel[r])) {
-                nonfinite = true;
-                alive[r] = 0;
-            } else if (rel[r] <= tol[(size_t)r]) {
-                conv[r] = 1;
-                alive[r] = 0;
-            } else if (iters[r] >= maxit) {
-                alive[r] = 0;
-            } else {
-                ++cycles[r];
-            }
-        }
+        for (GmItem* g : cyc)
+            if (bem_status st = gmres_cycle_end(*g)) return st;
     }
     return BEM_OK;
 }
@@ -1218,92 +1313,188 @@ bem_status bem_solve(bem_problem* p, int nrhs, const void* B_dev, size_t ldb, co
                      void* X_dev, size_t ldx, void* work_dev, size_t work_bytes, bem_solve_info* info,
                      hipStream_t stream)
 {
-    if (bem_status s = check_problem(p)) return s;
-    if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_solve");
-    if (nrhs < 1 || !B_dev || !X_dev || !work_dev || !opts || !info) return fail(BEM_E_ARG, "bad solve arguments");
-    const int n = 2 * p->N;
-    if (ldb < (size_t)n || ldx < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+    return bem_solve_batch(1, &p, &nrhs, &B_dev, &ldb, opts, &X_dev, &ldx, &work_dev, &work_bytes, &info, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// One problem of bem_solve_batch: its solver state and per-column results.
+struct SolveItem {
+    Solver c;
+    const double2* B;
+    size_t ldb;
+    double2* X;
+    size_t ldx;
+    std::vector<int> iters, conv, cycles, want;
+    std::vector<double> rel;
+    bool nonfinite = false;
+    // mixed precision: outer refinement state
+    std::vector<double> bnorm, rnorm;
+    std::vector<int> active;
+    std::vector<int> it2, conv2, cyc2;
+    std::vector<double> rel2;
+};
+
+}  // namespace
+
+extern "C" {
+
+bem_status bem_solve_batch(int np, bem_problem* const* ps, const int* nrhs_v, const void* const* B_dev,
+                           const size_t* ldb_v, const bem_solve_opts* opts, void* const* X_dev, const size_t* ldx_v,
+                           void* const* work_dev, const size_t* work_bytes, bem_solve_info* const* info,
+                           hipStream_t stream)
+{
+    if (np < 1 || np > bemk::MAX_FUSED) return fail(BEM_E_ARG, "np must be in [1, 8]");
+    if (!ps || !nrhs_v || !B_dev || !ldb_v || !opts || !X_dev || !ldx_v || !work_dev || !work_bytes || !info)
+        return fail(BEM_E_ARG, "bad solve arguments");
     if (opts->restart < 1 || opts->restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
     if (!(opts->tol > 0.0) || opts->max_iter < 1) return fail(BEM_E_ARG, "tol must be > 0 and max_iter >= 1");
     if (opts->graph_steps < 0 || opts->graph_steps > bemk::GRAPH_MAX_STEPS)
         return fail(BEM_E_ARG, "graph_steps must be in [0, " + std::to_string(bemk::GRAPH_MAX_STEPS) + "]");
-    Solver c{p, make_work(n, nrhs, opts->restart), static_cast<char*>(work_dev), stream, n, nrhs, opts->restart,
-             opts->graph_steps};
-    if (work_bytes < c.W.total) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
-    const double2* B = static_cast<const double2*>(B_dev);
-    double2* X = static_cast<double2*>(X_dev);
-    std::vector<int> iters(nrhs, 0), conv(nrhs, 0), cycles(nrhs, 0), want(nrhs, 1);
-    std::vector<double> rel(nrhs, 1.0);
-    bool nonfinite = false;
-    if (p->prec == BEM_F64) {
-        const std::vector<double> tols((size_t)nrhs, opts->tol);
-        if (bem_status st = gmres(c, B, ldb, X, ldx, tols, opts->max_iter, want, iters, conv, rel, cycles,
-                                  nonfinite))
-            return st;
+    std::vector<SolveItem> it((size_t)np);
+    for (int k = 0; k < np; ++k) {
+        bem_problem* p = ps[k];
+        if (bem_status s = check_problem(p)) return s;
+        if (!p->A) return fail(BEM_E_STATE, "bem_assemble must run before bem_solve");
+        const int nrhs = nrhs_v[k];
+        if (nrhs < 1 || !B_dev[k] || !X_dev[k] || !work_dev[k] || !info[k]) return fail(BEM_E_ARG, "bad solve arguments");
+        const int n = 2 * p->N;
+        if (ldb_v[k] < (size_t)n || ldx_v[k] < (size_t)n) return fail(BEM_E_ARG, "leading dimension < n");
+        if ((p->prec == BEM_F64) != (ps[0]->prec == BEM_F64))
+            return fail(BEM_E_ARG, "a batch mixes FP64 and FP32-product problems");
+        for (int q = 0; q < k; ++q)
+            if (ps[q] == p) return fail(BEM_E_ARG, "a problem appears twice in the batch");
+        SolveItem& t = it[(size_t)k];
+        t.c = Solver{p, make_work(n, nrhs, opts->restart), static_cast<char*>(work_dev[k]), stream, n, nrhs,
+                     opts->restart, np == 1 ? opts->graph_steps : 0};
+        if (work_bytes[k] < t.c.W.total) return fail(BEM_E_NOMEM, "work buffer smaller than bem_sizes asked for");
+        t.B = static_cast<const double2*>(B_dev[k]);
+        t.ldb = ldb_v[k];
+        t.X = static_cast<double2*>(X_dev[k]);
+        t.ldx = ldx_v[k];
+        t.iters.assign(nrhs, 0);
+        t.conv.assign(nrhs, 0);
+        t.cycles.assign(nrhs, 0);
+        t.want.assign(nrhs, 1);
+        t.rel.assign(nrhs, 1.0);
+    }
+    auto item = [&](SolveItem& t, const double2* B, size_t ldb, double2* X, size_t ldx, const std::vector<double>& tol,
+                    const std::vector<int>& want, std::vector<int>& iters, std::vector<int>& conv,
+                    std::vector<double>& rel, std::vector<int>& cycles) {
+        GmItem g;
+        g.c = &t.c;
+        g.B = B;
+        g.ldb = ldb;
+        g.X = X;
+        g.ldx = ldx;
+        g.tol = tol;
+        g.maxit = opts->max_iter;
+        g.want = want;
+        g.iters = &iters;
+        g.conv = &conv;
+        g.rel = &rel;
+        g.cycles = &cycles;
+        return g;
+    };
+    if (ps[0]->prec == BEM_F64) {
+        std::vector<GmItem> gs;
+        gs.reserve((size_t)np);
+        for (SolveItem& t : it)
+            gs.push_back(item(t, t.B, t.ldb, t.X, t.ldx, std::vector<double>((size_t)t.c.nr, opts->tol), t.want,
+                              t.iters, t.conv, t.rel, t.cycles));
+        std::vector<GmItem*> gp;
+        for (GmItem& g : gs) gp.push_back(&g);
+        if (bem_status st = gmres_batch(gp)) return st;
+        for (size_t k = 0; k < gs.size(); ++k)
+            if (gs[k].nonfinite) it[k].nonfinite = true;
     } else {
         // FP32 products inside GMRES, FP64 outer iterative refinement:
         //   r = b - A x (FP64 accumulation), solve A d = r loosely, x += d.
         const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
         const int max_refine = opts->max_refine > 0 ? opts->max_refine : 20;
-        const size_t ldv = c.W.ldv;
-        double2* Ro = c.at<double2>(c.W.Ro);
-        double2* D = c.at<double2>(c.W.D);
-        for (int r = 0; r < nrhs; ++r)
-            HIP_OK(hipMemsetAsync(X + (size_t)r * ldx, 0, (size_t)n * sizeof(double2), stream));
-        std::vector<double> bnorm, rnorm;
-        if (bem_status st = col_norms(c, B, ldb, c.at<double>(c.W.bnorm), bnorm)) return st;
-        HIP_OK(hipMemcpy2DAsync(Ro, ldv * sizeof(double2), B, ldb * sizeof(double2), (size_t)n * sizeof(double2),
-                                nrhs, hipMemcpyDeviceToDevice, stream));
-        rnorm = bnorm;
-        std::vector<int> active(nrhs, 1);
+        for (SolveItem& t : it) {
+            Solver& c = t.c;
+            const size_t ldv = c.W.ldv;
+            for (int r = 0; r < c.nr; ++r)
+                HIP_OK(hipMemsetAsync(t.X + (size_t)r * t.ldx, 0, (size_t)c.n * sizeof(double2), stream));
+            if (bem_status st = col_norms(c, t.B, t.ldb, c.at<double>(c.W.bnorm), t.bnorm)) return st;
+            HIP_OK(hipMemcpy2DAsync(c.at<double2>(c.W.Ro), ldv * sizeof(double2), t.B, t.ldb * sizeof(double2),
+                                    (size_t)c.n * sizeof(double2), c.nr, hipMemcpyDeviceToDevice, stream));
+            t.rnorm = t.bnorm;
+            t.active.assign(c.nr, 1);
+        }
         for (int step = 0; step <= max_refine; ++step) {
-            bool any = false;
-            for (int r = 0; r < nrhs; ++r) {
-                if (!active[r]) continue;
-                rel[r] = bnorm[r] > 0.0 ? rnorm[r] / bnorm[r] : 0.0;
-                if (!std::isfinite(rel[r])) {
-                    nonfinite = true;
-                    active[r] = 0;
-                } else if (rel[r] <= opts->tol) {
-                    conv[r] = 1;
-                    active[r] = 0;
-                } else if (iters[r] >= opts->max_iter || step == max_refine) {
-                    active[r] = 0;
-                } else {
-                    any = true;
+            std::vector<GmItem> gs;
+            std::vector<SolveItem*> in;
+            gs.reserve((size_t)np);
+            for (SolveItem& t : it) {
+                bool any = false;
+                for (int r = 0; r < t.c.nr; ++r) {
+                    if (!t.active[r]) continue;
+                    t.rel[r] = t.bnorm[r] > 0.0 ? t.rnorm[r] / t.bnorm[r] : 0.0;
+                    if (!std::isfinite(t.rel[r])) {
+                        t.nonfinite = true;
+                        t.active[r] = 0;
+                    } else if (t.rel[r] <= opts->tol) {
+                        t.conv[r] = 1;
+                        t.active[r] = 0;
+                    } else if (t.iters[r] >= opts->max_iter || step == max_refine) {
+                        t.active[r] = 0;
+                    } else {
+                        any = true;
+                    }
                 }
+                if (!any) continue;
+                // inner tolerance: inner_tol, or less if that already takes the
+                // outer residual below half the target
+                std::vector<double> tols((size_t)t.c.nr, inner_tol);
+                for (int r = 0; r < t.c.nr; ++r)
+                    if (t.active[r] && t.rnorm[r] > 0.0)
+                        tols[(size_t)r] = std::max(inner_tol, 0.5 * opts->tol * t.bnorm[r] / t.rnorm[r]);
+                t.it2.assign(t.c.nr, 0);
+                t.conv2.assign(t.c.nr, 0);
+                t.cyc2.assign(t.c.nr, 0);
+                t.rel2.assign(t.c.nr, 1.0);
+                const size_t ldv = t.c.W.ldv;
+                gs.push_back(item(t, t.c.at<double2>(t.c.W.Ro), ldv, t.c.at<double2>(t.c.W.D), ldv, tols, t.active,
+                                  t.it2, t.conv2, t.rel2, t.cyc2));
+                in.push_back(&t);
             }
-            if (!any) break;
-            // inner tolerance: inner_tol, or less if that already takes the
-            // outer residual below half the target
-            std::vector<double> tols((size_t)nrhs, inner_tol);
-            for (int r = 0; r < nrhs; ++r)
-                if (active[r] && rnorm[r] > 0.0)
-                    tols[(size_t)r] = std::max(inner_tol, 0.5 * opts->tol * bnorm[r] / rnorm[r]);
-            std::vector<int> it2(nrhs, 0), conv2(nrhs, 0), cyc2(nrhs, 0);
-            std::vector<double> rel2(nrhs, 1.0);
-            bool nf2 = false;
-            if (bem_status st = gmres(c, Ro, ldv, D, ldv, tols, opts->max_iter, active, it2, conv2, rel2, cyc2,
-                                      nf2))
-                return st;
-            if (nf2) nonfinite = true;
-            for (int r = 0; r < nrhs; ++r) {
-                iters[r] += it2[r];
-                if (active[r]) ++cycles[r];
+            if (in.empty()) break;
+            std::vector<GmItem*> gp;
+            for (GmItem& g : gs) gp.push_back(&g);
+            if (bem_status st = gmres_batch(gp)) return st;
+            for (size_t k = 0; k < in.size(); ++k) {
+                SolveItem& t = *in[k];
+                Solver& c = t.c;
+                const size_t ldv = c.W.ldv;
+                if (gs[k].nonfinite) t.nonfinite = true;
+                for (int r = 0; r < c.nr; ++r) {
+                    t.iters[r] += t.it2[r];
+                    if (t.active[r]) ++t.cycles[r];
+                }
+                if (bem_status st = upload_ints(c, c.W.active, t.active)) return st;
+                HIP_OK(bemk::launch_add_f64(c.at<double2>(c.W.D), ldv, c.n, c.nr, t.X, t.ldx, c.at<int>(c.W.active),
+                                            stream));
+                if (bem_status st = residual(c, t.B, t.ldb, t.X, t.ldx, c.at<double2>(c.W.Ro), ldv)) return st;
+                if (bem_status st = col_norms(c, c.at<double2>(c.W.Ro), ldv, c.at<double>(c.W.rnorm), t.rnorm))
+                    return st;
             }
-            if (bem_status st = upload_ints(c, c.W.active, active)) return st;
-            HIP_OK(bemk::launch_add_f64(D, ldv, n, nrhs, X, ldx, c.at<int>(c.W.active), stream));
-            if (bem_status st = residual(c, B, ldb, X, ldx, Ro, ldv)) return st;
-            if (bem_status st = col_norms(c, Ro, ldv, c.at<double>(c.W.rnorm), rnorm)) return st;
         }
     }
-    bool all = true;
-    for (int r = 0; r < nrhs; ++r) {
-        info[r].iters = iters[r];
-        info[r].restarts = cycles[r];
-        info[r].converged = conv[r];
-        info[r].rel_residual = rel[r];
-        all = all && conv[r];
+    bool all = true, nonfinite = false;
+    for (int k = 0; k < np; ++k) {
+        const SolveItem& t = it[(size_t)k];
+        for (int r = 0; r < t.c.nr; ++r) {
+            info[k][r].iters = t.iters[r];
+            info[k][r].restarts = t.cycles[r];
+            info[k][r].converged = t.conv[r];
+            info[k][r].rel_residual = t.rel[r];
+            all = all && t.conv[r];
+        }
+        nonfinite = nonfinite || t.nonfinite;
     }
     if (nonfinite) return fail(BEM_E_NONFINITE, "non-finite residual");
     if (!all) return fail(BEM_E_NOCONV, "GMRES reached max_iter before tol on some right-hand side");

@@ -155,6 +155,11 @@ struct ArnoldiArgs {
     int xw;
 };
 hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s);
+// The same step j for np (<= MAX_FUSED) problems in one set of launches (all
+// with the same restart length and basis precision); each problem's results
+// are those of launch_arnoldi on it alone.
+constexpr int MAX_FUSED = 8;
+hipError_t launch_arnoldi_set(const ArnoldiArgs* a, int np, int j, hipStream_t s);
 
 // Host side (bem_api.cpp): bytes of a matrix buffer of order n and leading
 // dimension lda in precision prec (a bem_prec value).

@@ -217,17 +217,17 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
 // on consecutive ids).  Adding the product's split partial sums here instead
 // of in its own reduction pass was slower (525.9), every batch re-reading them.
 template <int BATCH, bool HASW, class TV>
-__global__ __launch_bounds__(BS) void k_dc_dots(const TV* __restrict__ V, size_t ldv, int nr, int jc,
-                                                const double2* __restrict__ W, size_t ldw, int n, int rpt, int ns,
-                                                int rcp, double2* __restrict__ partP, double2* __restrict__ partQ,
-                                                const int* __restrict__ active)
+__device__ __forceinline__ void dc_dots(int bid, const TV* __restrict__ V, size_t ldv, int nr, int jc,
+                                        const double2* __restrict__ W, size_t ldw, int n, int rpt, int ns, int rcp,
+                                        double2* __restrict__ partP, double2* __restrict__ partQ,
+                                        const int* __restrict__ active)
 {
     constexpr int NV = (HASW ? 4 : 2) * BATCH;
     __shared__ double lds[4 * NV];
-    const int rc = (int)(blockIdx.x % (unsigned)rcp);
+    const int rc = (int)((unsigned)bid % (unsigned)rcp);
     if (rc >= nr * ns) return;
     const int r = rc % nr, chunk = rc / nr;
-    const int i0 = (int)(blockIdx.x / (unsigned)rcp) * BATCH;
+    const int i0 = (int)((unsigned)bid / (unsigned)rcp) * BATCH;
     if (!active[r]) return;
     double acc[NV];
 #pragma unroll
@@ -290,7 +290,7 @@ __device__ __forceinline__ double block_sum4(double v, double* red, int slot)
     return ((red[slot * 4] + red[slot * 4 + 1]) + red[slot * 4 + 2]) + red[slot * 4 + 3];
 }
 
-__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, int ns, const double2* __restrict__ partP,
+__device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, const double2* __restrict__ partP,
                                                         const double2* __restrict__ partQ, double2* __restrict__ Hraw,
                                                         double2* __restrict__ H, double2* __restrict__ cs,
                                                         double2* __restrict__ sn, double2* __restrict__ gvec,
@@ -309,7 +309,6 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
     __shared__ double2 zp[4][64];
     __shared__ double red[3 * 4];
     __shared__ int still_s;
-    const int r = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (!active[r]) {
         if (flags_out && tid == 0) flags_out[r] = 0;
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(int nr, int j, int m, in
 // candidate) and w = (wt - V t - v_j c) / gamma; norm_out gets the partial of
 // |w|^2 of each block.
 template <class TV>
-__global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv, int nr, int j, int m,
+__device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict__ V, size_t ldv, int nr, int j, int m,
                                                   const double2* __restrict__ sc, const double2* __restrict__ tc,
                                                   const double2* __restrict__ scal, double2* __restrict__ W,
                                                   size_t ldw, int n, double* __restrict__ norm_out,
@@ -495,8 +494,6 @@ __global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv
 {
     __shared__ double2 sl[1024], tl[1024];
     __shared__ double lds[4];
-    const int r = blockIdx.y;
-    const int nu = gridDim.x;
     if (!active[r]) return;
     for (int i = threadIdx.x; i < j; i += BS) {
         sl[i] = sc[(size_t)r * (m + 1) + i];
@@ -506,7 +503,7 @@ __global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv
     const double ig = 1.0 / scal[(size_t)r * 2].x;
     const double2 c = scal[(size_t)r * 2 + 1];
     double nn[1] = {0.0};
-    const int q = blockIdx.x * BS + threadIdx.x;
+    const int q = bx * BS + threadIdx.x;
     if (q < n) {
         TV* vj = V + ((size_t)j * nr + r) * ldv;
         double2 v = ld2(vj + q);
@@ -527,7 +524,7 @@ __global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv
         nn[0] = fma(w.x, w.x, w.y * w.y);
     }
     block_sum<1>(nn, lds);
-    if (threadIdx.x == 0) norm_out[r * nu + blockIdx.x] = nn[0];
+    if (threadIdx.x == 0) norm_out[r * nu + bx] = nn[0];
 }
 
 // beta = |w| from the update partials (every block sums them in the same
@@ -535,14 +532,13 @@ __global__ __launch_bounds__(BS) void k_dc_update(TV* __restrict__ V, size_t ldv
 // also the packed copy the next product reads (XT[q * xw + r], the stored
 // value), and zeros in its padding columns nr <= r < xw (grid rows).
 template <class TV>
-__global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, size_t ldw, int n,
-                                                const double* __restrict__ norm_part, int nu,
-                                                TV* __restrict__ V, size_t ldv, double* __restrict__ hnorm,
-                                                const int* __restrict__ active, int nr, TV* __restrict__ xt, int xw)
+__device__ __forceinline__ void dc_next(int r, int bx, const double2* __restrict__ W, size_t ldw, int n,
+                                        const double* __restrict__ norm_part, int nu, TV* __restrict__ V, size_t ldv,
+                                        double* __restrict__ hnorm, const int* __restrict__ active, int nr,
+                                        TV* __restrict__ xt, int xw)
 {
     __shared__ double bsh;
-    const int r = blockIdx.y;
-    const int q = blockIdx.x * BS + threadIdx.x;
+    const int q = bx * BS + threadIdx.x;
     if (r >= nr) {
         if (q < n) st2(xt + (size_t)q * xw + r, make_double2(0.0, 0.0));
         return;
@@ -556,7 +552,7 @@ __global__ __launch_bounds__(BS) void k_dc_next(const double2* __restrict__ W, s
     }
     __syncthreads();
     const double beta = bsh;
-    if (blockIdx.x == 0 && threadIdx.x == 0) hnorm[r] = beta;
+    if (bx == 0 && threadIdx.x == 0) hnorm[r] = beta;
     if (q >= n) return;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const double2 w = W[(size_t)r * ldw + q];
@@ -693,6 +689,75 @@ __global__ __launch_bounds__(BS) void k_farfield(const char* __restrict__ g, Geo
     }
 }
 
+// ---------------------------------------------------------------------------
+// One Arnoldi step of up to MAX_FUSED problems in each launch (fused
+// multi-instance steps): the problems' block ranges follow each other in a
+// one-dimensional grid, and every block runs the single-problem body above
+// with its problem's buffers, so each problem's arithmetic and reduction order
+// are the same alone or fused.  All problems share the step index j and the
+// restart length m (they run their cycles in step); a problem absent from a
+// launch is simply not in the set.
+// ---------------------------------------------------------------------------
+struct ArnProb {
+    void* V;
+    double2* W;
+    size_t ldv, ldw;
+    double2 *partP, *partQ, *Hraw, *H, *cs, *sn, *gvec, *sc, *tc, *scal;
+    double *hnorm, *norm_part;
+    const double* thr;
+    int *iters, *kdim, *active, *flags_out;
+    void* xt;
+    int nr, n, maxit, xw;
+    int ns, rcp, nu;  // projection row chunks, padded (right-hand side, chunk) pairs, update blocks
+    int b0[4];        // first block of this problem in the projection, step, update and next launches
+};
+struct ArnSet {
+    int np;
+    ArnProb p[MAX_FUSED];
+};
+
+// the problem whose block range of launch k holds block b
+__device__ __forceinline__ int set_problem(const ArnSet& S, int k, int b)
+{
+    int i = 0;
+    while (i + 1 < S.np && b >= S.p[i + 1].b0[k]) ++i;
+    return i;
+}
+
+template <int BATCH, bool HASW, class TV>
+__global__ __launch_bounds__(BS) void k_dc_dots(const ArnSet S, int jc, int rpt)
+{
+    const ArnProb& P = S.p[set_problem(S, 0, blockIdx.x)];
+    dc_dots<BATCH, HASW, TV>((int)blockIdx.x - P.b0[0], static_cast<const TV*>(P.V), P.ldv, P.nr, jc, P.W, P.ldw, P.n,
+                             rpt, P.ns, P.rcp, P.partP, HASW ? P.partQ : nullptr, P.active);
+}
+
+__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(const ArnSet S, int j, int m, bool last)
+{
+    const ArnProb& P = S.p[set_problem(S, 1, blockIdx.x)];
+    dc_step((int)blockIdx.x - P.b0[1], P.nr, j, m, P.ns, P.partP, last ? nullptr : P.partQ, P.Hraw, P.H, P.cs, P.sn,
+            P.gvec, P.hnorm, P.sc, P.tc, P.scal, P.thr, P.maxit, P.iters, P.kdim, P.active, P.flags_out);
+}
+
+template <class TV>
+__global__ __launch_bounds__(BS) void k_dc_update(const ArnSet S, int j, int m)
+{
+    const ArnProb& P = S.p[set_problem(S, 2, blockIdx.x)];
+    const int b = (int)blockIdx.x - P.b0[2];
+    dc_update<TV>(b / P.nu, b % P.nu, P.nu, static_cast<TV*>(P.V), P.ldv, P.nr, j, m, P.sc, P.tc, P.scal, P.W, P.ldw,
+                  P.n, P.norm_part, P.active);
+}
+
+template <class TV>
+__global__ __launch_bounds__(BS) void k_dc_next(const ArnSet S, int jc)
+{
+    const ArnProb& P = S.p[set_problem(S, 3, blockIdx.x)];
+    const int b = (int)blockIdx.x - P.b0[3];
+    dc_next<TV>(b / P.nu, b % P.nu, P.W, P.ldw, P.n, P.norm_part, P.nu,
+                static_cast<TV*>(P.V) + (size_t)jc * P.nr * P.ldv, P.ldv, P.hnorm, P.active, P.nr,
+                static_cast<TV*>(P.xt), P.xw);
+}
+
 }  // namespace
 
 hipError_t launch_rhs(const char* g, const GeomLayout& L, int N, const double* angles, int nang, double2* B,
@@ -743,56 +808,89 @@ int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().ro
 namespace {
 
 template <bool HASW, class TV>
-void launch_dc_dots(const DotCfg& c, int ns, hipStream_t s, const TV* V, size_t ldv, int nr, int jc,
-                    const double2* W, size_t ldw, int n, double2* partP, double2* partQ, const int* active)
+void launch_dc_dots(const DotCfg& c, const ArnSet& S, int nblocks, int jc, hipStream_t s)
 {
     const int rpt = c.rows / BS;
-    const int rcp = (nr * ns + 7) / 8 * 8;
-    const dim3 grid(rcp * ((jc + c.batch - 1) / c.batch));
     if (c.batch == 4)
-        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
-                           partP, partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
     else if (c.batch == 16)
-        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
-                           partP, partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
     else
-        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), grid, dim3(BS), 0, s, V, ldv, nr, jc, W, ldw, n, rpt, ns, rcp,
-                           partP, partQ, active);
+        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
 }
 
 template <class TV>
-hipError_t launch_arnoldi_t(const ArnoldiArgs& a, TV* V, int j, hipStream_t s)
+hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
 {
     const DotCfg dc = dot_cfg();
-    const int n = a.n, nr = a.nr, m = a.m;
-    const int ns = (n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
-    const int nu = (n + BS - 1) / BS;            // blocks of the update kernel
+    const int m = a[0].m;
     const int jc = j + 1;
     const bool last = j == m;
-    dim3 gu(nu, nr);
-    TV* xt = static_cast<TV*>(a.xt);
+    ArnSet S{};
+    S.np = np;
+    int nb[4] = {0, 0, 0, 0};
+    for (int k = 0; k < np; ++k) {
+        const ArnoldiArgs& A = a[k];
+        ArnProb& P = S.p[k];
+        P.V = A.V;
+        P.W = A.W;
+        P.ldv = A.ldv;
+        P.ldw = A.ldw;
+        P.partP = A.partP;
+        P.partQ = A.partQ;
+        P.Hraw = A.Hraw;
+        P.H = A.H;
+        P.cs = A.cs;
+        P.sn = A.sn;
+        P.gvec = A.gvec;
+        P.sc = A.sc;
+        P.tc = A.tc;
+        P.scal = A.scal;
+        P.hnorm = A.hnorm;
+        P.norm_part = A.norm_part;
+        P.thr = A.thr;
+        P.iters = A.iters;
+        P.kdim = A.kdim;
+        P.active = A.active;
+        P.flags_out = A.flags_out;
+        P.xt = A.xt;
+        P.nr = A.nr;
+        P.n = A.n;
+        P.maxit = A.maxit;
+        P.xw = A.xw;
+        P.ns = (A.n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
+        P.rcp = (A.nr * P.ns + 7) / 8 * 8;
+        P.nu = (A.n + BS - 1) / BS;             // blocks of the update kernel
+        const int counts[4] = {P.rcp * ((jc + dc.batch - 1) / dc.batch), A.nr, P.nu * A.nr,
+                               P.nu * (A.xt ? A.xw : A.nr)};
+        for (int q = 0; q < 4; ++q) {
+            P.b0[q] = nb[q];
+            nb[q] += counts[q];
+        }
+    }
     if (last)
-        launch_dc_dots<false, TV>(dc, ns, s, V, a.ldv, nr, jc, nullptr, 0, n, a.partP, nullptr, a.active);
+        launch_dc_dots<false, TV>(dc, S, nb[0], jc, s);
     else
-        launch_dc_dots<true, TV>(dc, ns, s, V, a.ldv, nr, jc, a.W, a.ldw, n, a.partP, a.partQ, a.active);
-    hipLaunchKernelGGL(k_dc_step, dim3(nr), dim3(DC_STEP_BS), 0, s, nr, j, m, ns, a.partP, last ? nullptr : a.partQ, a.Hraw,
-                       a.H, a.cs, a.sn, a.gvec, a.hnorm, a.sc, a.tc, a.scal, a.thr, a.maxit, a.iters, a.kdim, a.active,
-                       a.flags_out);
+        launch_dc_dots<true, TV>(dc, S, nb[0], jc, s);
+    hipLaunchKernelGGL(k_dc_step, dim3(nb[1]), dim3(DC_STEP_BS), 0, s, S, j, m, last);
     if (!last) {
-        hipLaunchKernelGGL((k_dc_update<TV>), gu, dim3(BS), 0, s, V, a.ldv, nr, j, m, a.sc, a.tc, a.scal, a.W,
-                           a.ldw, n, a.norm_part, a.active);
-        hipLaunchKernelGGL((k_dc_next<TV>), dim3(nu, xt ? a.xw : nr), dim3(BS), 0, s, a.W, a.ldw, n, a.norm_part, nu,
-                           V + (size_t)jc * nr * a.ldv, a.ldv, a.hnorm, a.active, nr, xt, a.xw);
+        hipLaunchKernelGGL((k_dc_update<TV>), dim3(nb[2]), dim3(BS), 0, s, S, j, m);
+        hipLaunchKernelGGL((k_dc_next<TV>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s)
+hipError_t launch_arnoldi(const ArnoldiArgs& a, int j, hipStream_t s) { return launch_arnoldi_set(&a, 1, j, s); }
+
+hipError_t launch_arnoldi_set(const ArnoldiArgs* a, int np, int j, hipStream_t s)
 {
-    if (a.v32) return launch_arnoldi_t<float2>(a, reinterpret_cast<float2*>(a.V), j, s);
-    return launch_arnoldi_t<double2>(a, a.V, j, s);
+    if (np < 1 || np > MAX_FUSED) return hipErrorInvalidValue;
+    for (int k = 1; k < np; ++k)
+        if (a[k].v32 != a[0].v32 || a[k].m != a[0].m) return hipErrorInvalidValue;
+    if (a[0].v32) return launch_arnoldi_t<float2>(a, np, j, s);
+    return launch_arnoldi_t<double2>(a, np, j, s);
 }
 
 namespace {

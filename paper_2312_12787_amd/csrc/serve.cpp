@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
@@ -179,48 +180,103 @@ struct bem_server {
         return nullptr;
     }
 
-    void run(Request* r, size_t off, Slot& sl, bem_server_result& res)
+    // Run the admitted requests of one slot (one, or up to o.fuse with fused
+    // Krylov steps): each one's device tables, matrix and right-hand sides,
+    // then one bem_solve_batch over those that got that far, then each far
+    // field and its copy to the caller.  Every request lends its own part of
+    // the slot's pinned flag buffer; the slot's events serve the batch.
+    void run_batch(std::vector<Request*>& rs, const std::vector<size_t>& offs, Slot& sl,
+                   std::vector<bem_server_result>& res)
     {
-        char* g = base + off;
-        char* A = g + r->geom;
-        char* W = A + r->mat;
-        char* B = W + r->work;
-        char* X = B + r->vec;
-        char* F = X + r->vec;
-        const size_t n = (size_t)r->n;
-        std::vector<bem_solve_info> info((size_t)r->nrhs);
-        bemk::lend_flag_buffers(r->p, sl.pinned, FLAG_INTS, sl.ev);
-        bemk::freeze_shapes(r->p, shapes);
-        bem_status st = bem_geometry(r->p, g, r->geom, sl.stream);
-        if (!st) st = bem_assemble(r->p, (bem_prec)o.prec, A, r->lda, sl.stream);
-        if (!st) st = bem_rhs(r->p, r->nrhs, r->angles.data(), B, n, sl.stream);
-        bem_status solve_st = BEM_OK;
-        if (!st) {
-            solve_st = bem_solve(r->p, r->nrhs, B, n, &o.solve, X, n, W, r->work, info.data(), sl.stream);
-            if (solve_st != BEM_OK && solve_st != BEM_E_NOCONV) st = solve_st;
+        const size_t nb = rs.size();
+        std::vector<bem_status> st(nb, BEM_OK);
+        std::vector<std::vector<bem_solve_info>> info(nb);
+        std::vector<char*> g(nb), A(nb), W(nb), B(nb), X(nb), F(nb);
+        for (size_t k = 0; k < nb; ++k) {
+            Request* r = rs[k];
+            g[k] = base + offs[k];
+            A[k] = g[k] + r->geom;
+            W[k] = A[k] + r->mat;
+            B[k] = W[k] + r->work;
+            X[k] = B[k] + r->vec;
+            F[k] = X[k] + r->vec;
+            info[k].resize((size_t)r->nrhs);
+            bemk::lend_flag_buffers(r->p, sl.pinned + k * FLAG_INTS, FLAG_INTS, sl.ev);
+            bemk::freeze_shapes(r->p, shapes);
+            st[k] = bem_geometry(r->p, g[k], r->geom, sl.stream);
+            if (!st[k]) st[k] = bem_assemble(r->p, (bem_prec)o.prec, A[k], r->lda, sl.stream);
+            if (!st[k]) st[k] = bem_rhs(r->p, r->nrhs, r->angles.data(), B[k], (size_t)r->n, sl.stream);
+            if (st[k]) std::snprintf(res[k].message, sizeof res[k].message, "%s", bem_last_error());
         }
-        if (!st) st = bem_farfield(r->p, r->nrhs, X, n, o.ndir, dirs.data(), F, (size_t)o.ndir, nullptr, 0, sl.stream);
-        if (!st) {
-            hipError_t e = hipMemcpyAsync(r->out, F, (size_t)o.ndir * r->nrhs * sizeof(bem_z), hipMemcpyDeviceToHost,
-                                          sl.stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
-            if (e != hipSuccess) {
-                st = BEM_E_DEVICE;
-                std::snprintf(res.message, sizeof res.message, "far-field copy: %s", hipGetErrorString(e));
+        // the batch: every request whose set-up succeeded
+        std::vector<size_t> in;
+        std::vector<bem_problem*> ps;
+        std::vector<int> nr;
+        std::vector<const void*> Bp;
+        std::vector<void*> Xp, Wp;
+        std::vector<size_t> ld, wb;
+        std::vector<bem_solve_info*> ip;
+        for (size_t k = 0; k < nb; ++k) {
+            if (st[k]) continue;
+            in.push_back(k);
+            ps.push_back(rs[k]->p);
+            nr.push_back(rs[k]->nrhs);
+            Bp.push_back(B[k]);
+            Xp.push_back(X[k]);
+            Wp.push_back(W[k]);
+            ld.push_back((size_t)rs[k]->n);
+            wb.push_back(rs[k]->work);
+            ip.push_back(info[k].data());
+        }
+        if (!in.empty()) {
+            const bem_status sst = bem_solve_batch((int)in.size(), ps.data(), nr.data(), Bp.data(), ld.data(), &o.solve,
+                                                   Xp.data(), ld.data(), Wp.data(), wb.data(), ip.data(), sl.stream);
+            const std::string msg = sst ? bem_last_error() : "";
+            for (size_t k : in) {
+                bool conv = true, finite = true;
+                for (const auto& i : info[k]) {
+                    conv = conv && i.converged;
+                    finite = finite && std::isfinite(i.rel_residual);
+                }
+                // BEM_E_NOCONV / BEM_E_NONFINITE belong to the requests whose
+                // columns met them; another error to the whole batch
+                if (sst == BEM_E_NONFINITE || sst == BEM_E_NOCONV)
+                    st[k] = !finite ? BEM_E_NONFINITE : (!conv ? BEM_E_NOCONV : BEM_OK);
+                else
+                    st[k] = sst;
+                if (st[k] && st[k] != BEM_E_NOCONV)
+                    std::snprintf(res[k].message, sizeof res[k].message, "%s", msg.c_str());
             }
-        } else {
-            std::snprintf(res.message, sizeof res.message, "%s", bem_last_error());
-            (void)hipStreamSynchronize(sl.stream);
         }
-        if (!st && solve_st == BEM_E_NOCONV) {
-            st = BEM_E_NOCONV;
-            std::snprintf(res.message, sizeof res.message, "%s", "GMRES stopped at max_iter");
-        }
-        res.status = st;
-        for (const auto& i : info) {
-            res.iters_max = std::max(res.iters_max, i.iters);
-            res.refine_max = std::max(res.refine_max, i.restarts);
-            res.rel_residual_max = std::max(res.rel_residual_max, i.rel_residual);
+        for (size_t k = 0; k < nb; ++k) {
+            Request* r = rs[k];
+            bem_status s = st[k];
+            const bool noconv = s == BEM_E_NOCONV;
+            if (!s || noconv)
+                s = bem_farfield(r->p, r->nrhs, X[k], (size_t)r->n, o.ndir, dirs.data(), F[k], (size_t)o.ndir, nullptr,
+                                 0, sl.stream);
+            if (!s) {
+                hipError_t e = hipMemcpyAsync(r->out, F[k], (size_t)o.ndir * r->nrhs * sizeof(bem_z),
+                                              hipMemcpyDeviceToHost, sl.stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
+                if (e != hipSuccess) {
+                    s = BEM_E_DEVICE;
+                    std::snprintf(res[k].message, sizeof res[k].message, "far-field copy: %s", hipGetErrorString(e));
+                }
+            } else {
+                if (!res[k].message[0]) std::snprintf(res[k].message, sizeof res[k].message, "%s", bem_last_error());
+                (void)hipStreamSynchronize(sl.stream);
+            }
+            if (!s && noconv) {
+                s = BEM_E_NOCONV;
+                std::snprintf(res[k].message, sizeof res[k].message, "%s", "GMRES stopped at max_iter");
+            }
+            res[k].status = s;
+            for (const auto& i : info[k]) {
+                res[k].iters_max = std::max(res[k].iters_max, i.iters);
+                res[k].refine_max = std::max(res[k].refine_max, i.restarts);
+                res[k].rel_residual_max = std::max(res[k].rel_residual_max, i.rel_residual);
+            }
         }
     }
 
@@ -228,36 +284,54 @@ struct bem_server {
     {
         Slot& sl = slots[(size_t)k];
         (void)hipSetDevice(o.device);
+        const size_t fuse = (size_t)std::max(1, o.fuse);
         for (;;) {
-            Request* r = nullptr;
-            size_t off = 0;
+            std::vector<Request*> rs;
+            std::vector<size_t> offs;
             {
                 std::unique_lock<std::mutex> lk(mu);
+                size_t off = 0;
+                Request* r = nullptr;
                 for (;;) {
                     if (!queue.empty() && (r = pick(&off)) != nullptr) break;
                     if (stop && queue.empty()) return;
                     cv_work.wait(lk);
                 }
-                running++;
-                r->t_admit = now();
+                rs.push_back(r);
+                offs.push_back(off);
+                // more waiting requests that fit join the slot's batch now
+                while (rs.size() < fuse && !queue.empty() && (r = pick(&off)) != nullptr) {
+                    rs.push_back(r);
+                    offs.push_back(off);
+                }
+                running += (int)rs.size();
+                const double t = now();
+                for (Request* q : rs) q->t_admit = t;
             }
-            bem_server_result res{};
-            res.id = r->id;
-            res.n = r->n;
-            res.nrhs = r->nrhs;
-            res.footprint = r->footprint;
-            res.t_submit = r->t_submit;
-            res.t_admit = r->t_admit;
-            run(r, off, sl, res);
-            res.t_done = now();
-            bem_destroy(r->p);
+            std::vector<bem_server_result> res(rs.size());
+            for (size_t q = 0; q < rs.size(); ++q) {
+                res[q].id = rs[q]->id;
+                res[q].n = rs[q]->n;
+                res[q].nrhs = rs[q]->nrhs;
+                res[q].footprint = rs[q]->footprint;
+                res[q].t_submit = rs[q]->t_submit;
+                res[q].t_admit = rs[q]->t_admit;
+            }
+            run_batch(rs, offs, sl, res);
+            const double t = now();
+            for (size_t q = 0; q < rs.size(); ++q) {
+                res[q].t_done = t;
+                bem_destroy(rs[q]->p);
+            }
             {
                 std::lock_guard<std::mutex> lk(mu);
-                arena.release(off, r->footprint);
-                running--;
-                done.push_back(res);
+                for (size_t q = 0; q < rs.size(); ++q) {
+                    arena.release(offs[q], rs[q]->footprint);
+                    done.push_back(res[q]);
+                }
+                running -= (int)rs.size();
             }
-            delete r;
+            for (Request* q : rs) delete q;
             cv_work.notify_all();
             cv_done.notify_all();
         }
@@ -278,6 +352,7 @@ bem_status bem_server_create(const bem_server_opts* opts, bem_server** out)
     if (o.prec != BEM_F64 && o.prec != BEM_F32 && o.prec != BEM_MIXED) return sfail(BEM_E_ARG, "unknown precision");
     if (o.solve.restart < 1 || o.solve.max_iter < 1 || !(o.solve.tol > 0.0))
         return sfail(BEM_E_ARG, "bad solve options");
+    if (o.fuse < 0 || o.fuse > bemk::MAX_FUSED) return sfail(BEM_E_ARG, "fuse outside 0..8");
     auto* s = new bem_server();
     s->o = o;
     s->dirs.assign(o.dirs, o.dirs + o.ndir);
@@ -290,8 +365,10 @@ bem_status bem_server_create(const bem_server_opts* opts, bem_server** out)
     s->slots.resize((size_t)o.slots);
     for (Slot& sl : s->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), FLAG_INTS * sizeof(int),
-                                               hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&sl.pinned),
+                              (size_t)std::max(1, o.fuse) * FLAG_INTS * sizeof(int),
+                              hipHostMallocMapped | hipHostMallocCoherent);
         for (auto& ev : sl.ev)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     }

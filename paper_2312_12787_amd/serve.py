@@ -20,7 +20,8 @@ SERVE_EXPORTS = ["bem_server_create", "bem_server_footprint", "bem_server_submit
 
 class bem_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int), ("device", C.c_int), ("arena_dev", C.c_void_p), ("arena_bytes", C.c_size_t),
-                ("prec", C.c_int), ("solve", bem_solve_opts), ("ndir", C.c_int), ("dirs", C.POINTER(C.c_double))]
+                ("prec", C.c_int), ("solve", bem_solve_opts), ("ndir", C.c_int), ("dirs", C.POINTER(C.c_double)),
+                ("fuse", C.c_int)]
 
 
 class bem_server_result(C.Structure):
@@ -76,12 +77,14 @@ class Server:
     sub-allocates per request (admission by footprint); prec: F32 (FP32 matrix
     and products with FP64 refinement) or F64; dirs: far-field directions
     returned for every right-hand side; graph_steps: Krylov steps per captured
-    HIP graph in every request's solve (0: launched kernel by kernel).
+    HIP graph in every request's solve (0: launched kernel by kernel); fuse: up
+    to this many requests admitted together by a slot are solved as one batch
+    with fused Krylov launches (1: one request per slot).
     """
 
     def __init__(self, arena_bytes: int, slots: int = 4, prec: int = F32, restart: int = 100, tol: float = 1e-8,
                  inner_tol: float = 1e-5, max_iter: int = 20000, max_refine: int = 0,
-                 dirs: Sequence[float] = (0.0,), device: str = "cuda", graph_steps: int = 0):
+                 dirs: Sequence[float] = (0.0,), device: str = "cuda", graph_steps: int = 0, fuse: int = 1):
         import torch
         L = _serve_lib()
         self.device = torch.device(device)
@@ -99,6 +102,7 @@ class Server:
                                 int(graph_steps))
         o.ndir = len(self.dirs)
         o.dirs = self.dirs.ctypes.data_as(C.POINTER(C.c_double))
+        o.fuse = int(fuse)
         h = C.c_void_p()
         _check(L.bem_server_create(C.byref(o), C.byref(h)))
         self._h = h

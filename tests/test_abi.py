@@ -52,7 +52,7 @@ def test_server_option_validation_before_any_device_work():
         return o
 
     for bad in (dict(slots=0), dict(slots=17), dict(arena_dev=None), dict(arena_dev=(1 << 20) + 8),
-                dict(ndir=0), dict(ndir=5000), dict(prec=7), dict(dirs=None)):
+                dict(ndir=0), dict(ndir=5000), dict(prec=7), dict(dirs=None), dict(fuse=9), dict(fuse=-1)):
         h = C.c_void_p()
         st = L.bem_server_create(C.byref(opts(**bad)), C.byref(h))
         assert P.STATUS[st] == "BEM_E_ARG", bad

@@ -39,10 +39,11 @@ def test_oracle_sample_scales_with_products_and_gram_schmidt_work():
     import workloads as W
     wl = W.workload_disk256()
     t1, spent1, rows, mv, c = bench.oracle_sample(wl, [1], [0.0])
-    t100, _, _, _, _ = bench.oracle_sample(wl, [400], [0.0])
+    # modelled counts far above the timing noise of the sampled rows
+    t100, _, _, _, _ = bench.oracle_sample(wl, [100000], [0.0])
     assert rows == wl.problems[0].order and mv == wl.problems[0].order
     assert t100 > t1 > 0.0 and spent1 > 0.0 and c > 0.0
-    units = 1e9
+    units = 1e11
     ta, _, _, _, ca = bench.oracle_sample(wl, [1], [units])
     assert ta > t1 + 0.5 * ca * units
 
