@@ -936,8 +936,8 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="kite4096",
                     choices=["kite4096", "disk256", "sectors", "kite16384_mixed", "serve"])
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")

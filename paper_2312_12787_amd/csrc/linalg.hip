@@ -711,36 +711,46 @@ struct ArnProb {
     int ns, rcp, nu;  // projection row chunks, padded (right-hand side, chunk) pairs, update blocks
     int b0[4];        // first block of this problem in the projection, step, update and next launches
 };
+// NP: capacity of the set.  A lone problem launches with NP = 1, whose
+// descriptor (about 220 bytes of kernel arguments) is an eighth of the fused
+// one's, and whose blocks need no search for their problem.
+template <int NP>
 struct ArnSet {
     int np;
-    ArnProb p[MAX_FUSED];
+    ArnProb p[NP];
 };
 
 // the problem whose block range of launch k holds block b
-__device__ __forceinline__ int set_problem(const ArnSet& S, int k, int b)
+template <int NP>
+__device__ __forceinline__ int set_problem(const ArnSet<NP>& S, int k, int b)
 {
-    int i = 0;
-    while (i + 1 < S.np && b >= S.p[i + 1].b0[k]) ++i;
-    return i;
+    if constexpr (NP == 1) {
+        return 0;
+    } else {
+        int i = 0;
+        while (i + 1 < S.np && b >= S.p[i + 1].b0[k]) ++i;
+        return i;
+    }
 }
 
-template <int BATCH, bool HASW, class TV>
-__global__ __launch_bounds__(BS) void k_dc_dots(const ArnSet S, int jc, int rpt)
+template <int BATCH, bool HASW, class TV, int NP>
+__global__ __launch_bounds__(BS) void k_dc_dots(const ArnSet<NP> S, int jc, int rpt)
 {
     const ArnProb& P = S.p[set_problem(S, 0, blockIdx.x)];
     dc_dots<BATCH, HASW, TV>((int)blockIdx.x - P.b0[0], static_cast<const TV*>(P.V), P.ldv, P.nr, jc, P.W, P.ldw, P.n,
                              rpt, P.ns, P.rcp, P.partP, HASW ? P.partQ : nullptr, P.active);
 }
 
-__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(const ArnSet S, int j, int m, bool last)
+template <int NP>
+__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(const ArnSet<NP> S, int j, int m, bool last)
 {
     const ArnProb& P = S.p[set_problem(S, 1, blockIdx.x)];
     dc_step((int)blockIdx.x - P.b0[1], P.nr, j, m, P.ns, P.partP, last ? nullptr : P.partQ, P.Hraw, P.H, P.cs, P.sn,
             P.gvec, P.hnorm, P.sc, P.tc, P.scal, P.thr, P.maxit, P.iters, P.kdim, P.active, P.flags_out);
 }
 
-template <class TV>
-__global__ __launch_bounds__(BS) void k_dc_update(const ArnSet S, int j, int m)
+template <class TV, int NP>
+__global__ __launch_bounds__(BS) void k_dc_update(const ArnSet<NP> S, int j, int m)
 {
     const ArnProb& P = S.p[set_problem(S, 2, blockIdx.x)];
     const int b = (int)blockIdx.x - P.b0[2];
@@ -748,8 +758,8 @@ __global__ __launch_bounds__(BS) void k_dc_update(const ArnSet S, int j, int m)
                   P.n, P.norm_part, P.active);
 }
 
-template <class TV>
-__global__ __launch_bounds__(BS) void k_dc_next(const ArnSet S, int jc)
+template <class TV, int NP>
+__global__ __launch_bounds__(BS) void k_dc_next(const ArnSet<NP> S, int jc)
 {
     const ArnProb& P = S.p[set_problem(S, 3, blockIdx.x)];
     const int b = (int)blockIdx.x - P.b0[3];
@@ -807,16 +817,34 @@ int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().ro
 
 namespace {
 
-template <bool HASW, class TV>
-void launch_dc_dots(const DotCfg& c, const ArnSet& S, int nblocks, int jc, hipStream_t s)
+template <bool HASW, class TV, int NP>
+void launch_dc_dots(const DotCfg& c, const ArnSet<NP>& S, int nblocks, int jc, hipStream_t s)
 {
     const int rpt = c.rows / BS;
     if (c.batch == 4)
-        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
+        hipLaunchKernelGGL((k_dc_dots<4, HASW, TV, NP>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
     else if (c.batch == 16)
-        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
+        hipLaunchKernelGGL((k_dc_dots<16, HASW, TV, NP>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
     else
-        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
+        hipLaunchKernelGGL((k_dc_dots<8, HASW, TV, NP>), dim3(nblocks), dim3(BS), 0, s, S, jc, rpt);
+}
+
+template <class TV, int NP>
+hipError_t launch_arnoldi_kernels(const DotCfg& dc, const ArnSet<NP>& S, const int nb[4], int j, int m,
+                                  hipStream_t s)
+{
+    const int jc = j + 1;
+    const bool last = j == m;
+    if (last)
+        launch_dc_dots<false, TV>(dc, S, nb[0], jc, s);
+    else
+        launch_dc_dots<true, TV>(dc, S, nb[0], jc, s);
+    hipLaunchKernelGGL((k_dc_step<NP>), dim3(nb[1]), dim3(DC_STEP_BS), 0, s, S, j, m, last);
+    if (!last) {
+        hipLaunchKernelGGL((k_dc_update<TV, NP>), dim3(nb[2]), dim3(BS), 0, s, S, j, m);
+        hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
+    }
+    return hipGetLastError();
 }
 
 template <class TV>
@@ -825,8 +853,7 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
     const DotCfg dc = dot_cfg();
     const int m = a[0].m;
     const int jc = j + 1;
-    const bool last = j == m;
-    ArnSet S{};
+    ArnSet<MAX_FUSED> S{};
     S.np = np;
     int nb[4] = {0, 0, 0, 0};
     for (int k = 0; k < np; ++k) {
@@ -868,16 +895,13 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
             nb[q] += counts[q];
         }
     }
-    if (last)
-        launch_dc_dots<false, TV>(dc, S, nb[0], jc, s);
-    else
-        launch_dc_dots<true, TV>(dc, S, nb[0], jc, s);
-    hipLaunchKernelGGL(k_dc_step, dim3(nb[1]), dim3(DC_STEP_BS), 0, s, S, j, m, last);
-    if (!last) {
-        hipLaunchKernelGGL((k_dc_update<TV>), dim3(nb[2]), dim3(BS), 0, s, S, j, m);
-        hipLaunchKernelGGL((k_dc_next<TV>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
+    if (np == 1) {
+        ArnSet<1> S1{};
+        S1.np = 1;
+        S1.p[0] = S.p[0];
+        return launch_arnoldi_kernels<TV>(dc, S1, nb, j, m, s);
     }
-    return hipGetLastError();
+    return launch_arnoldi_kernels<TV>(dc, S, nb, j, m, s);
 }
 
 }  // namespace
