@@ -197,8 +197,8 @@ GeomLayout make_layout(const bem_problem* p)
 
 // Workspace of the solver and products (byte offsets into work_dev).
 struct WorkLayout {
-    size_t V, W, R, Ro, D, mv_part, dot_part, dot_part2, upd_part, y, H, Hraw, cs, sn, gvec, sc, tc, scal,
-        norm_part, hnorm, rnorm, bnorm, thr, active, kdim, iters, total;
+    size_t V, W, R, Ro, D, mv_part, dot_part, dot_part2, upd_part, y, H, Hraw, cs, sn, gvec, norm_part, hnorm,
+        rnorm, bnorm, thr, active, kdim, iters, total;
     int ldv, nblk, anblk;
 };
 
@@ -232,9 +232,6 @@ WorkLayout make_work(int n, int nr, int m)
     W.cs = take((size_t)nr * m * sizeof(double2));
     W.sn = take((size_t)nr * m * sizeof(double2));
     W.gvec = take((size_t)nr * (m + 1) * sizeof(double2));
-    W.sc = take((size_t)nr * (m + 1) * sizeof(double2));
-    W.tc = take((size_t)nr * (m + 1) * sizeof(double2));
-    W.scal = take((size_t)nr * 2 * sizeof(double2));
     W.norm_part = take((size_t)nr * std::max(W.nblk, 64) * sizeof(double));
     W.hnorm = take((size_t)nr * sizeof(double));
     W.rnorm = take((size_t)nr * sizeof(double));
@@ -1127,9 +1124,6 @@ bem_status gmres_begin(GmItem& g, int ring, int nev)
     arn.cs = c.at<double2>(c.W.cs);
     arn.sn = c.at<double2>(c.W.sn);
     arn.gvec = c.at<double2>(c.W.gvec);
-    arn.sc = c.at<double2>(c.W.sc);
-    arn.tc = c.at<double2>(c.W.tc);
-    arn.scal = c.at<double2>(c.W.scal);
     arn.hnorm = c.at<double>(c.W.hnorm);
     arn.norm_part = c.at<double>(c.W.upd_part);
     arn.thr = c.at<double>(c.W.thr);
@@ -1220,7 +1214,7 @@ bem_status gmres_batch(const std::vector<GmItem*>& items)
 {
     Solver& c0 = *items[0]->c;
     const int m = c0.m;
-    // The GPU decides per right-hand side when to stop (k_dc_step, which also
+    // The GPU decides per right-hand side when to stop (the step blocks, which also
     // writes the decision into a ring of pinned host slots); the host reads
     // the flags `lag` steps behind, so the queue never drains.  A
     // small matrix gets a longer lag (its steps are shorter than the host's

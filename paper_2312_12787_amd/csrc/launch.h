@@ -142,7 +142,6 @@ struct ArnoldiArgs {
     double2 *partP, *partQ;        // projection partials [nr][ns][m + 1]
     double2 *Hraw, *H;             // Hessenberg as produced / rotated, [nr][m][m + 1]
     double2 *cs, *sn, *gvec;       // Givens rotations, rotated right-hand side
-    double2 *sc, *tc, *scal;       // step coefficients [nr][m + 1], [nr][2]
     double *hnorm, *norm_part;     // |w| of the last step, its partials [nr][nu]
     const double* thr;             // absolute stopping thresholds
     int maxit;

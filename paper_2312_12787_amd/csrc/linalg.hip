@@ -239,21 +239,65 @@ __device__ __forceinline__ void dc_dots(int bid, const TV* __restrict__ V, size_
     const int nb = min(BATCH, jc - i0);
     const int q0 = chunk * rpt * BS + threadIdx.x;
     const int q1 = min(n, (chunk + 1) * rpt * BS);
-    for (int q = q0; q < q1; q += BS) {
-        const double2 a = ld2(vt + q);
-        double2 w = make_double2(0.0, 0.0);
-        if (HASW) w = wr[q];
+    // one row's contribution to every accumulator, in the same order for
+    // both loops below
+    auto row = [&](const double2 a, const double2 w, const double2* v, int cnt) {
 #pragma unroll
         for (int b = 0; b < BATCH; ++b) {
-            if (b < nb) {
-                const double2 v = ld2(vb + b * vstride + q);
-                acc[2 * b] = fma(v.x, a.x, fma(v.y, a.y, acc[2 * b]));
-                acc[2 * b + 1] = fma(v.x, a.y, fma(-v.y, a.x, acc[2 * b + 1]));
+            if (b < cnt) {
+                acc[2 * b] = fma(v[b].x, a.x, fma(v[b].y, a.y, acc[2 * b]));
+                acc[2 * b + 1] = fma(v[b].x, a.y, fma(-v[b].y, a.x, acc[2 * b + 1]));
                 if (HASW) {
-                    acc[2 * BATCH + 2 * b] = fma(v.x, w.x, fma(v.y, w.y, acc[2 * BATCH + 2 * b]));
-                    acc[2 * BATCH + 2 * b + 1] = fma(v.x, w.y, fma(-v.y, w.x, acc[2 * BATCH + 2 * b + 1]));
+                    acc[2 * BATCH + 2 * b] = fma(v[b].x, w.x, fma(v[b].y, w.y, acc[2 * BATCH + 2 * b]));
+                    acc[2 * BATCH + 2 * b + 1] = fma(v[b].x, w.y, fma(-v[b].y, w.x, acc[2 * BATCH + 2 * b + 1]));
                 }
             }
+        }
+    };
+    if (nb == BATCH) {
+        // full batch: every load of two rows is issued before the first use
+        // (the per-vector guard of the partial batch below makes the compiler
+        // wait for each load in turn); the loads share one 32-bit byte offset
+        // from wave-uniform bases, so they take no per-load address registers
+        const char* bv[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) bv[b] = reinterpret_cast<const char*>(vb + b * vstride);
+        const char* bt = reinterpret_cast<const char*>(vt);
+        const char* bw = reinterpret_cast<const char*>(wr);
+        auto at = [](const char* base, unsigned off) { return ld2(reinterpret_cast<const TV*>(base + off)); };
+        auto aw = [](const char* base, unsigned off) { return *reinterpret_cast<const double2*>(base + off); };
+        int q = q0;
+        for (; q + BS < q1; q += 2 * BS) {
+            double2 a[2], w[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)}, v[2][BATCH];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const unsigned qo = (unsigned)(q + u * BS);
+                a[u] = at(bt, qo * (unsigned)sizeof(TV));
+                if (HASW) w[u] = aw(bw, qo * (unsigned)sizeof(double2));
+#pragma unroll
+                for (int b = 0; b < BATCH; ++b) v[u][b] = at(bv[b], qo * (unsigned)sizeof(TV));
+            }
+            row(a[0], w[0], v[0], BATCH);
+            row(a[1], w[1], v[1], BATCH);
+        }
+        if (q < q1) {
+            double2 v[BATCH];
+            const unsigned qo = (unsigned)q;
+            const double2 a = at(bt, qo * (unsigned)sizeof(TV));
+            const double2 w = HASW ? aw(bw, qo * (unsigned)sizeof(double2)) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) v[b] = at(bv[b], qo * (unsigned)sizeof(TV));
+            row(a, w, v, BATCH);
+        }
+    } else {
+        for (int q = q0; q < q1; q += BS) {
+            double2 v[BATCH];
+            const double2 a = ld2(vt + q);
+            const double2 w = HASW ? wr[q] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b)
+                if (b < nb) v[b] = ld2(vb + b * vstride + q);
+            row(a, w, v, nb);
         }
     }
     block_sum<NV>(acc, lds);
@@ -274,12 +318,13 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// The small work of step j for one right-hand side (one wave): sum the
-// projection partials into S = [s, alpha] and T = [t, tau] (kept for the update
-// kernel), complete column j-1 (Givens, residual, decision), form column j and
-// the update coefficients scal = {(gamma, 0), c}.  Hraw holds the Hessenberg
-// matrix as produced, H its rotated (triangular) form for the back-solve.
-constexpr int DC_STEP_BS = 256;  // threads per right-hand side in k_dc_step
+// The small work of step j for one right-hand side (one block): sum the
+// projection partials into S = [s, alpha] and T = [t, tau], complete column
+// j-1 (Givens, residual, decision) and form column j.  Hraw holds the
+// Hessenberg matrix as produced, H its rotated (triangular) form for the
+// back-solve.  It runs in the update launch, beside the blocks that apply
+// the update (which form the same S, T, gamma and c themselves).
+constexpr int DC_STEP_BS = 256;  // threads of a step block
 
 // sum over the workgroup in a fixed order: each wave's DPP sum, then waves 0..3
 __device__ __forceinline__ double block_sum4(double v, double* red, int slot)
@@ -290,34 +335,46 @@ __device__ __forceinline__ double block_sum4(double v, double* red, int slot)
     return ((red[slot * 4] + red[slot * 4 + 1]) + red[slot * 4 + 2]) + red[slot * 4 + 3];
 }
 
+// LDS of the step and update blocks (double2 units): five arrays of m + 1
+// entries, the wave partials zp[4][64], then reduction slots and a flag.
+__host__ __device__ constexpr size_t arn_lds_elems(int m) { return 5 * ((size_t)m + 1) + 4 * 64 + 16; }
+
+// A column that stops at step j of a cycle (convergence, spent budget, end of
+// the Krylov space) is marked 2 in `active` while the update blocks of the same
+// launch may still read it (they update columns marked 1 or 2; the update of a
+// stopping column is never used), and the normalisation kernel that follows
+// clears the mark; at the last step of a cycle it is cleared at once.
+constexpr int STOPPING = 2;
+
 __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, const double2* __restrict__ partP,
-                                                        const double2* __restrict__ partQ, double2* __restrict__ Hraw,
-                                                        double2* __restrict__ H, double2* __restrict__ cs,
-                                                        double2* __restrict__ sn, double2* __restrict__ gvec,
-                                                        const double* __restrict__ hnorm, double2* __restrict__ sc,
-                                                        double2* __restrict__ tc, double2* __restrict__ scal,
-                                                        const double* __restrict__ thr, int maxit,
-                                                        int* __restrict__ iters, int* __restrict__ kdim,
-                                                        int* __restrict__ active, int* __restrict__ flags_out)
+                                        const double2* __restrict__ partQ, double2* __restrict__ Hraw,
+                                        double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
+                                        double2* __restrict__ gvec, const double* __restrict__ hnorm,
+                                        const double* __restrict__ thr, int maxit, int* __restrict__ iters,
+                                        int* __restrict__ kdim, int* __restrict__ active,
+                                        int* __restrict__ flags_out, double2* __restrict__ lds)
 {
     // S, T and the column being completed stay in LDS for the whole step; the
     // inputs of earlier steps (column j - 1 as produced, the rotations, the
     // rotated right-hand side) are loaded first, alongside the partial sums
-    __shared__ double2 col[1024 + 1];
-    __shared__ double2 lc[1024], ls[1024];
-    __shared__ double2 Sl[1024 + 1], Tl[1024 + 1];
-    __shared__ double2 zp[4][64];
-    __shared__ double red[3 * 4];
-    __shared__ int still_s;
+    const size_t L = (size_t)m + 1;
+    double2* col = lds;
+    double2* lc = lds + L;
+    double2* ls = lds + 2 * L;
+    double2* Sl = lds + 3 * L;
+    double2* Tl = lds + 4 * L;
+    double2(*zp)[64] = reinterpret_cast<double2(*)[64]>(lds + 5 * L);
+    double* red = reinterpret_cast<double*>(lds + 5 * L + 4 * 64);
+    int* still_p = reinterpret_cast<int*>(red + 16);
+    int& still_s = *still_p;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int stop_mark = j == m ? 0 : STOPPING;
     if (!active[r]) {
         if (flags_out && tid == 0) flags_out[r] = 0;
         return;
     }
     const int jc = j + 1;
     const bool hasw = partQ != nullptr;
-    double2* S = sc + (size_t)r * (m + 1);
-    double2* T = tc + (size_t)r * (m + 1);
     double2* Hc = Hraw + (size_t)r * (m + 1) * m + (size_t)(j >= 1 ? j - 1 : 0) * (m + 1);
     if (j >= 1) {
         for (int i = tid; i < j; i += DC_STEP_BS) col[i] = Hc[i];
@@ -341,11 +398,7 @@ __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, con
             }
         }
         Sl[i] = make_double2(pr, pi);
-        S[i] = Sl[i];
-        if (hasw) {
-            Tl[i] = make_double2(qr, qi);
-            T[i] = Tl[i];
-        }
+        if (hasw) Tl[i] = make_double2(qr, qi);
     }
     __syncthreads();
     const double beta = j >= 1 ? hnorm[r] : 1.0;
@@ -429,7 +482,7 @@ __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, con
             kdim[r] = j;
             // stop on convergence, a spent budget, the end of the Krylov space or a non-finite value
             still = (res > thr[r]) && it < maxit && (gamma > 0.0) && !brk;
-            if (!still) active[r] = 0;
+            if (!still) active[r] = stop_mark;
             still_s = still;
         }
         __syncthreads();
@@ -438,7 +491,7 @@ __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, con
         for (int i = tid; i <= j; i += DC_STEP_BS) Rc[i] = col[i];
     } else if (!(gamma > 0.0)) {
         still = 0;
-        if (tid == 0) active[r] = 0;
+        if (tid == 0) active[r] = stop_mark;
     }
     if (j == m) still = 0;  // end of the cycle
     if (flags_out && tid == 0) flags_out[r] = still;
@@ -476,32 +529,59 @@ __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, con
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        scal[(size_t)r * 2] = make_double2(gamma, 0.0);
-        scal[(size_t)r * 2 + 1] = c;
-    }
 }
 
 // One pass over V_0..V_{j-1}: v_j = (vt - V s) / gamma (in place of the
 // candidate) and w = (wt - V t - v_j c) / gamma; norm_out gets the partial of
-// |w|^2 of each block.
+// |w|^2 of each block.  Every block forms S, T, gamma and c itself from the
+// projection partials, with the step block's sums in the step block's order,
+// so the step's Hessenberg work runs beside the update instead of before it.
 template <class TV>
 __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict__ V, size_t ldv, int nr, int j, int m,
-                                                  const double2* __restrict__ sc, const double2* __restrict__ tc,
-                                                  const double2* __restrict__ scal, double2* __restrict__ W,
-                                                  size_t ldw, int n, double* __restrict__ norm_out,
-                                                  const int* __restrict__ active)
+                                          int ns, const double2* __restrict__ partP,
+                                          const double2* __restrict__ partQ, const double* __restrict__ hnorm,
+                                          double2* __restrict__ W, size_t ldw, int n, double* __restrict__ norm_out,
+                                          const int* __restrict__ active, double2* __restrict__ lds)
 {
-    __shared__ double2 sl[1024], tl[1024];
-    __shared__ double lds[4];
     if (!active[r]) return;
-    for (int i = threadIdx.x; i < j; i += BS) {
-        sl[i] = sc[(size_t)r * (m + 1) + i];
-        tl[i] = tc[(size_t)r * (m + 1) + i];
+    const size_t L = (size_t)m + 1;
+    double2* sl = lds;
+    double2* tl = lds + L;
+    double* red = reinterpret_cast<double*>(lds + 2 * L);
+    const int jc = j + 1, tid = threadIdx.x;
+    for (int i = tid; i < jc; i += BS) {
+        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll 8
+        for (int b = 0; b < ns; ++b) {
+            const size_t o = ((size_t)r * ns + b) * jc + i;
+            const double2 p = partP[o];
+            pr += p.x;
+            pi += p.y;
+            const double2 t = partQ[o];
+            qr += t.x;
+            qi += t.y;
+        }
+        sl[i] = make_double2(pr, pi);
+        tl[i] = make_double2(qr, qi);
     }
+    const double beta = j >= 1 ? hnorm[r] : 1.0;
     __syncthreads();
-    const double ig = 1.0 / scal[(size_t)r * 2].x;
-    const double2 c = scal[(size_t)r * 2 + 1];
+    if (!(beta > 0.0)) return;  // the previous step ended the Krylov space
+    double ss = 0.0, str = 0.0, sti = 0.0;
+    for (int i = tid; i < j; i += BS) {
+        const double2 a = sl[i], t = tl[i];
+        ss = fma(a.x, a.x, fma(a.y, a.y, ss));
+        str = fma(a.x, t.x, fma(a.y, t.y, str));
+        sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
+    }
+    ss = block_sum4(ss, red, 0);
+    str = block_sum4(str, red, 1);
+    sti = block_sum4(sti, red, 2);
+    const double gamma = sqrt(fmax(sl[j].x - ss, 0.0));
+    if (!(gamma > 0.0)) return;
+    const double ig = 1.0 / gamma;
+    const double2 tau = tl[j];
+    const double2 c = make_double2((tau.x - str) * ig, (tau.y - sti) * ig);
     double nn[1] = {0.0};
     const int q = bx * BS + threadIdx.x;
     if (q < n) {
@@ -523,7 +603,7 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
         W[(size_t)r * ldw + q] = w;
         nn[0] = fma(w.x, w.x, w.y * w.y);
     }
-    block_sum<1>(nn, lds);
+    block_sum<1>(nn, red + 12);
     if (threadIdx.x == 0) norm_out[r * nu + bx] = nn[0];
 }
 
@@ -534,7 +614,7 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
 template <class TV>
 __device__ __forceinline__ void dc_next(int r, int bx, const double2* __restrict__ W, size_t ldw, int n,
                                         const double* __restrict__ norm_part, int nu, TV* __restrict__ V, size_t ldv,
-                                        double* __restrict__ hnorm, const int* __restrict__ active, int nr,
+                                        double* __restrict__ hnorm, int* __restrict__ active, int nr,
                                         TV* __restrict__ xt, int xw)
 {
     __shared__ double bsh;
@@ -543,7 +623,13 @@ __device__ __forceinline__ void dc_next(int r, int bx, const double2* __restrict
         if (q < n) st2(xt + (size_t)q * xw + r, make_double2(0.0, 0.0));
         return;
     }
-    if (!active[r]) return;
+    const int act = active[r];
+    if (act != 1) {
+        // a column marked stopping at this step: clear the mark (every block
+        // of the column returns here, whether it reads the mark or the zero)
+        if (act == STOPPING && bx == 0 && threadIdx.x == 0) active[r] = 0;
+        return;
+    }
     if (threadIdx.x < 64) {
         double v = 0.0;
         for (int b = threadIdx.x; b < nu; b += 64) v += norm_part[r * nu + b];
@@ -702,7 +788,7 @@ struct ArnProb {
     void* V;
     double2* W;
     size_t ldv, ldw;
-    double2 *partP, *partQ, *Hraw, *H, *cs, *sn, *gvec, *sc, *tc, *scal;
+    double2 *partP, *partQ, *Hraw, *H, *cs, *sn, *gvec;
     double *hnorm, *norm_part;
     const double* thr;
     int *iters, *kdim, *active, *flags_out;
@@ -741,21 +827,24 @@ __global__ __launch_bounds__(BS) void k_dc_dots(const ArnSet<NP> S, int jc, int 
                              rpt, P.ns, P.rcp, P.partP, HASW ? P.partQ : nullptr, P.active);
 }
 
-template <int NP>
-__global__ __launch_bounds__(DC_STEP_BS) void k_dc_step(const ArnSet<NP> S, int j, int m, bool last)
-{
-    const ArnProb& P = S.p[set_problem(S, 1, blockIdx.x)];
-    dc_step((int)blockIdx.x - P.b0[1], P.nr, j, m, P.ns, P.partP, last ? nullptr : P.partQ, P.Hraw, P.H, P.cs, P.sn,
-            P.gvec, P.hnorm, P.sc, P.tc, P.scal, P.thr, P.maxit, P.iters, P.kdim, P.active, P.flags_out);
-}
-
+// Step blocks first (one per right-hand side: the Hessenberg column, the
+// rotations, the stopping decision), then the update blocks (nu per
+// right-hand side); at the last step of a cycle only the step blocks.
+static_assert(DC_STEP_BS == BS, "step and update blocks share one launch");
 template <class TV, int NP>
-__global__ __launch_bounds__(BS) void k_dc_update(const ArnSet<NP> S, int j, int m)
+__global__ __launch_bounds__(BS) void k_dc_update(const ArnSet<NP> S, int j, int m, bool last)
 {
+    extern __shared__ double2 arn_lds[];
     const ArnProb& P = S.p[set_problem(S, 2, blockIdx.x)];
     const int b = (int)blockIdx.x - P.b0[2];
-    dc_update<TV>(b / P.nu, b % P.nu, P.nu, static_cast<TV*>(P.V), P.ldv, P.nr, j, m, P.sc, P.tc, P.scal, P.W, P.ldw,
-                  P.n, P.norm_part, P.active);
+    if (b < P.nr) {
+        dc_step(b, P.nr, j, m, P.ns, P.partP, last ? nullptr : P.partQ, P.Hraw, P.H, P.cs, P.sn, P.gvec, P.hnorm,
+                P.thr, P.maxit, P.iters, P.kdim, P.active, P.flags_out, arn_lds);
+        return;
+    }
+    const int u = b - P.nr;
+    dc_update<TV>(u / P.nu, u % P.nu, P.nu, static_cast<TV*>(P.V), P.ldv, P.nr, j, m, P.ns, P.partP, P.partQ,
+                  P.hnorm, P.W, P.ldw, P.n, P.norm_part, P.active, arn_lds);
 }
 
 template <class TV, int NP>
@@ -839,11 +928,9 @@ hipError_t launch_arnoldi_kernels(const DotCfg& dc, const ArnSet<NP>& S, const i
         launch_dc_dots<false, TV>(dc, S, nb[0], jc, s);
     else
         launch_dc_dots<true, TV>(dc, S, nb[0], jc, s);
-    hipLaunchKernelGGL((k_dc_step<NP>), dim3(nb[1]), dim3(DC_STEP_BS), 0, s, S, j, m, last);
-    if (!last) {
-        hipLaunchKernelGGL((k_dc_update<TV, NP>), dim3(nb[2]), dim3(BS), 0, s, S, j, m);
-        hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
-    }
+    hipLaunchKernelGGL((k_dc_update<TV, NP>), dim3(nb[2]), dim3(BS), arn_lds_elems(m) * sizeof(double2), s, S, j, m,
+                       last);
+    if (!last) hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
     return hipGetLastError();
 }
 
@@ -870,9 +957,6 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
         P.cs = A.cs;
         P.sn = A.sn;
         P.gvec = A.gvec;
-        P.sc = A.sc;
-        P.tc = A.tc;
-        P.scal = A.scal;
         P.hnorm = A.hnorm;
         P.norm_part = A.norm_part;
         P.thr = A.thr;
@@ -888,7 +972,8 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
         P.ns = (A.n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
         P.rcp = (A.nr * P.ns + 7) / 8 * 8;
         P.nu = (A.n + BS - 1) / BS;             // blocks of the update kernel
-        const int counts[4] = {P.rcp * ((jc + dc.batch - 1) / dc.batch), A.nr, P.nu * A.nr,
+        // projection, (unused), step + update, normalisation blocks
+        const int counts[4] = {P.rcp * ((jc + dc.batch - 1) / dc.batch), 0, A.nr + (j == m ? 0 : P.nu * A.nr),
                                P.nu * (A.xt ? A.xw : A.nr)};
         for (int q = 0; q < 4; ++q) {
             P.b0[q] = nb[q];
