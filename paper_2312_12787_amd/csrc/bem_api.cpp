@@ -901,13 +901,26 @@ bem_status apply_basis(const Solver& c, int j, double2* Y, size_t ldy)
     const bem_problem* p = c.p;
     const bemk::ProductPlan pl = step_plan(c);
     if (pl.ng > 0) {
+        // from step 1 on the packed inputs are w of the previous step, and the
+        // product normalises them (the Arnoldi launches skip the normalisation)
+        bemk::StepNorm sn{};
+        if (j >= 1) {
+            sn.norm_part = c.at<double>(c.W.upd_part);
+            sn.nu = bemk::update_blocks(c.n);
+            sn.V = c.v32() ? static_cast<void*>(c.V32(j)) : static_cast<void*>(c.V(j));
+            sn.ldv = c.W.ldv;
+            sn.v32 = c.v32();
+            sn.hnorm = c.at<double>(c.W.hnorm);
+            sn.active = c.at<int>(c.W.active);
+        }
+        const bemk::StepNorm* snp = j >= 1 ? &sn : nullptr;
         if (!c.v32())
             HIP_OK(bemk::launch_product_packed_f64(pl, static_cast<const double2*>(p->A), p->lda, c.n, c.nr,
-                                                   c.at<double2>(c.W.mv_part), Y, ldy, c.s, p->hk()));
+                                                   c.at<double2>(c.W.mv_part), Y, ldy, snp, c.s, p->hk()));
         else
             HIP_OK(bemk::launch_product_packed_f32(
                 pl, static_cast<const float2*>(p->prec == BEM_MIXED ? p->A32 : p->A), p->lda, c.n, c.nr,
-                reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), Y, ldy, c.s, p->hk()));
+                reinterpret_cast<float2*>(c.at<double2>(c.W.mv_part)), Y, ldy, snp, c.s, p->hk()));
         return BEM_OK;
     }
     if (!c.v32()) {

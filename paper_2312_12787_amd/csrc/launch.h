@@ -111,11 +111,29 @@ struct ProductPlan {
     size_t xt_offset;  // in complex values of the accumulation type
 };
 ProductPlan product_plan(const MvShapes* shapes, int types, int n, int nr);
+// The normalisation of Krylov step j folded into its product (steps j >= 1
+// of a problem whose products read packed right-hand sides): the packed
+// inputs hold w of step j - 1 (written by the update kernel), and the split
+// reduction divides the product of each right-hand side by |w|, stores
+// v_j = w / |w| into the basis, |w| into hnorm and clears the stopping marks
+// of step j - 1.
+struct StepNorm {
+    const double* norm_part;  // [nr][nu] partial sums of |w|^2 of the update blocks
+    int nu;                   // update_blocks(n)
+    void* V;                  // v_j, column-major (ldv): complex64 if v32, else complex128
+    size_t ldv;
+    bool v32;
+    double* hnorm;
+    int* active;
+};
+int update_blocks(int n);
 hipError_t launch_product_packed_f64(const ProductPlan& pl, const double2* A, size_t lda, int n, int nr,
-                                     double2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook);
+                                     double2* part, double2* Y, size_t ldy, const StepNorm* sn, hipStream_t s,
+                                     const KernelHook* hook);
 // FP32 matrix and sums (complex64 basis), Y widened to FP64.
 hipError_t launch_product_packed_f32(const ProductPlan& pl, const float2* A, size_t lda, int n, int nr,
-                                     float2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook);
+                                     float2* part, double2* Y, size_t ldy, const StepNorm* sn, hipStream_t s,
+                                     const KernelHook* hook);
 // R = B - A X (FP64)
 hipError_t launch_residual_f64(const double2* A, size_t lda, int n, const double2* X, size_t ldx, int nrhs,
                               const double2* B, size_t ldb, double2* R, size_t ldr, double2* partial, hipStream_t s,

@@ -11,6 +11,7 @@
 #include <cstdlib>
 
 #include "internal.h"
+#include "krylov_dev.h"
 #include "launch.h"
 
 namespace bemk {
@@ -33,32 +34,8 @@ __device__ __forceinline__ double2 ld2(const float2* p)
 __device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
 __device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 
-// Move a double between lanes with a DPP pattern (two 32-bit moves); lanes
-// whose row is masked off or whose source is out of range receive 0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double v)
-{
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false),
-                            __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false));
-}
-
-// Sum over the 64 lanes of a wave, returned in every lane (GFX9 DPP: quad
-// swaps, half-row and row mirrors give each 16-lane row its sum; the row
-// broadcasts of lanes 15 and 31 then collect the four rows into row 3, and
-// lane 63 is read out).
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141, 0xf>(v);  // row_half_mirror
-    v += dpp_f64<0x140, 0xf>(v);  // row_mirror
-    v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
+using dev::STOPPING;
+using dev::wave_sum;
 
 // Sum NV values over the 256 threads of a block; result valid in thread 0.
 template <int NV>
@@ -340,11 +317,11 @@ __device__ __forceinline__ double block_sum4(double v, double* red, int slot)
 __host__ __device__ constexpr size_t arn_lds_elems(int m) { return 5 * ((size_t)m + 1) + 4 * 64 + 16; }
 
 // A column that stops at step j of a cycle (convergence, spent budget, end of
-// the Krylov space) is marked 2 in `active` while the update blocks of the same
-// launch may still read it (they update columns marked 1 or 2; the update of a
-// stopping column is never used), and the normalisation kernel that follows
-// clears the mark; at the last step of a cycle it is cleared at once.
-constexpr int STOPPING = 2;
+// the Krylov space) is marked STOPPING in `active` while the update blocks of
+// the same launch may still read it (they update columns marked 1 or
+// STOPPING; the update of a stopping column is never used), and the
+// normalisation that follows clears the mark; at the last step of a cycle it
+// is cleared at once.
 
 __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, const double2* __restrict__ partP,
                                         const double2* __restrict__ partQ, double2* __restrict__ Hraw,
@@ -541,7 +518,8 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
                                           int ns, const double2* __restrict__ partP,
                                           const double2* __restrict__ partQ, const double* __restrict__ hnorm,
                                           double2* __restrict__ W, size_t ldw, int n, double* __restrict__ norm_out,
-                                          const int* __restrict__ active, double2* __restrict__ lds)
+                                          const int* __restrict__ active, TV* __restrict__ xt, int xw,
+                                          double2* __restrict__ lds)
 {
     if (!active[r]) return;
     const size_t L = (size_t)m + 1;
@@ -601,6 +579,7 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
         w = make_double2((w.x - vc.x) * ig, (w.y - vc.y) * ig);
         st2(vj + q, v);
         W[(size_t)r * ldw + q] = w;
+        if (xt) st2(xt + (size_t)q * xw + r, w);  // the next product's input (its reduction divides by |w|)
         nn[0] = fma(w.x, w.x, w.y * w.y);
     }
     block_sum<1>(nn, red + 12);
@@ -631,16 +610,14 @@ __device__ __forceinline__ void dc_next(int r, int bx, const double2* __restrict
         return;
     }
     if (threadIdx.x < 64) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nu; b += 64) v += norm_part[r * nu + b];
-        v = wave_sum(v);
-        if (threadIdx.x == 0) bsh = sqrt(v);
+        const double beta = dev::step_beta(norm_part + (size_t)r * nu, nu);
+        if (threadIdx.x == 0) bsh = beta;
     }
     __syncthreads();
     const double beta = bsh;
     if (bx == 0 && threadIdx.x == 0) hnorm[r] = beta;
     if (q >= n) return;
-    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    const double inv = dev::inv_beta(beta);
     const double2 w = W[(size_t)r * ldw + q];
     const double2 v = make_double2(w.x * inv, w.y * inv);
     st2(V + (size_t)r * ldv + q, v);
@@ -844,7 +821,7 @@ __global__ __launch_bounds__(BS) void k_dc_update(const ArnSet<NP> S, int j, int
     }
     const int u = b - P.nr;
     dc_update<TV>(u / P.nu, u % P.nu, P.nu, static_cast<TV*>(P.V), P.ldv, P.nr, j, m, P.ns, P.partP, P.partQ,
-                  P.hnorm, P.W, P.ldw, P.n, P.norm_part, P.active, arn_lds);
+                  P.hnorm, P.W, P.ldw, P.n, P.norm_part, P.active, static_cast<TV*>(P.xt), P.xw, arn_lds);
 }
 
 template <class TV, int NP>
@@ -902,6 +879,8 @@ DotCfg dot_cfg()
     return c;
 }
 
+int update_blocks(int n) { return (n + BS - 1) / BS; }
+
 int arnoldi_blocks(int n) { return std::max((n + BS - 1) / BS, (n + dot_cfg().rows - 1) / dot_cfg().rows); }
 
 namespace {
@@ -924,13 +903,16 @@ hipError_t launch_arnoldi_kernels(const DotCfg& dc, const ArnSet<NP>& S, const i
 {
     const int jc = j + 1;
     const bool last = j == m;
+    // problems whose products read packed right-hand sides normalise v_j in
+    // the product of step j; at the last step, which has no product, here
+    if (last && nb[3] > 0) hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, j);
     if (last)
         launch_dc_dots<false, TV>(dc, S, nb[0], jc, s);
     else
         launch_dc_dots<true, TV>(dc, S, nb[0], jc, s);
     hipLaunchKernelGGL((k_dc_update<TV, NP>), dim3(nb[2]), dim3(BS), arn_lds_elems(m) * sizeof(double2), s, S, j, m,
                        last);
-    if (!last) hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
+    if (!last && nb[3] > 0) hipLaunchKernelGGL((k_dc_next<TV, NP>), dim3(nb[3]), dim3(BS), 0, s, S, jc);
     return hipGetLastError();
 }
 
@@ -971,10 +953,13 @@ hipError_t launch_arnoldi_t(const ArnoldiArgs* a, int np, int j, hipStream_t s)
         P.xw = A.xw;
         P.ns = (A.n + dc.rows - 1) / dc.rows;  // row chunks of the projection kernel
         P.rcp = (A.nr * P.ns + 7) / 8 * 8;
-        P.nu = (A.n + BS - 1) / BS;             // blocks of the update kernel
-        // projection, (unused), step + update, normalisation blocks
+        P.nu = update_blocks(A.n);              // blocks of the update kernel
+        // projection, (unused), step + update, normalisation blocks; the
+        // normalisation of a problem with packed product inputs runs only at
+        // the last step (before the projection)
+        const bool packed = A.xt != nullptr;
         const int counts[4] = {P.rcp * ((jc + dc.batch - 1) / dc.batch), 0, A.nr + (j == m ? 0 : P.nu * A.nr),
-                               P.nu * (A.xt ? A.xw : A.nr)};
+                               (j == m) == packed ? P.nu * A.nr : 0};
         for (int q = 0; q < 4; ++q) {
             P.b0[q] = nb[q];
             nb[q] += counts[q];

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "krylov_dev.h"
 #include "launch.h"
 
 namespace bemk {
@@ -617,11 +618,57 @@ hipError_t matvec_any(const TA* A, size_t lda, int n, const TX* X, size_t ldx, i
     return hipGetLastError();
 }
 
+__device__ __forceinline__ void st_basis(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st_basis(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+// The split reduction of a Krylov step's product whose inputs were w of the
+// previous step, not yet divided by |w|: Y = (sum of the split partial sums,
+// in split order) / |w| = A v_j, and before Y overwrites w (Y is the step's w
+// buffer): v_j = w / |w| into the basis for active columns, |w| into hnorm,
+// and the stopping marks of the previous step cleared (what the
+// normalisation kernel does otherwise).
+template <class ACC, class TV>
+__global__ void k_step_reduce(const ACC* __restrict__ part, int splits, int n, int nrhs, double2* __restrict__ Y,
+                              size_t ldy, const double* __restrict__ nrm, int nu, TV* __restrict__ V, size_t ldv,
+                              double* __restrict__ hnorm, int* __restrict__ active)
+{
+    __shared__ double inv_s;
+    const int r = blockIdx.y;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int act = active[r];
+    if (threadIdx.x < 64) {
+        const double beta = dev::step_beta(nrm + (size_t)r * nu, nu);
+        if (threadIdx.x == 0) {
+            inv_s = dev::inv_beta(beta);
+            if (blockIdx.x == 0 && act == 1) hnorm[r] = beta;
+        }
+    }
+    __syncthreads();
+    // every block of a marked column skips it, whether it reads the mark or the zero
+    if (blockIdx.x == 0 && threadIdx.x == 0 && act == dev::STOPPING) active[r] = 0;
+    if (row >= n) return;
+    using S = decltype(ACC{}.x);
+    S sr = S(0), si = S(0);
+    for (int sp = 0; sp < splits; ++sp) {
+        const ACC v = part[((size_t)sp * nrhs + r) * n + row];
+        sr += v.x;
+        si += v.y;
+    }
+    double2* y = Y + (size_t)r * ldy + row;
+    const double inv = inv_s;
+    if (act == 1) {
+        const double2 w = *y;
+        st_basis(V + (size_t)r * ldv + row, make_double2(w.x * inv, w.y * inv));
+    }
+    *y = make_double2((double)sr * inv, (double)si * inv);
+}
+
 // Products of the Krylov steps with 5-64 right-hand sides, packed by the
-// caller at part + xt_offset: the matrix-core kernel and the split reduction.
+// caller at part + xt_offset: the matrix-core kernel and the split reduction
+// (with sn: inputs not yet normalised, see k_step_reduce).
 template <class TA, class ACC>
 hipError_t product_packed(const ProductPlan& pl, const TA* A, size_t lda, int n, int nr, ACC* part, double2* Y,
-                          size_t ldy, hipStream_t s, const KernelHook* hook)
+                          size_t ldy, const StepNorm* sn, hipStream_t s, const KernelHook* hook)
 {
     using S = decltype(ACC{}.x);
     const int rows_per_block = 16 * pl.shape.rt * MV_WAVES;
@@ -630,8 +677,16 @@ hipError_t product_packed(const ProductPlan& pl, const TA* A, size_t lda, int n,
     launch_mfma_variant<TA, S, ACC>(pl.shape, pl.ng, dim3((n + rows_per_block - 1) / rows_per_block, pl.splits), s, A,
                                     lda, n, part + pl.xt_offset, nr, part, mcps);
     hook_call(hook, KIND_MATVEC, 1, s);
-    hipLaunchKernelGGL((k_matvec_reduce<ACC, double2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, part, pl.splits,
-                       n, nr, Y, ldy, nullptr, 0);
+    const dim3 grid((n + BS - 1) / BS, nr);
+    if (!sn)
+        hipLaunchKernelGGL((k_matvec_reduce<ACC, double2>), grid, dim3(BS), 0, s, part, pl.splits, n, nr, Y, ldy,
+                           nullptr, 0);
+    else if (sn->v32)
+        hipLaunchKernelGGL((k_step_reduce<ACC, float2>), grid, dim3(BS), 0, s, part, pl.splits, n, nr, Y, ldy,
+                           sn->norm_part, sn->nu, static_cast<float2*>(sn->V), sn->ldv, sn->hnorm, sn->active);
+    else
+        hipLaunchKernelGGL((k_step_reduce<ACC, double2>), grid, dim3(BS), 0, s, part, pl.splits, n, nr, Y, ldy,
+                           sn->norm_part, sn->nu, static_cast<double2*>(sn->V), sn->ldv, sn->hnorm, sn->active);
     return hipGetLastError();
 }
 
@@ -649,15 +704,17 @@ ProductPlan product_plan(const MvShapes* shapes, int types, int n, int nr)
 }
 
 hipError_t launch_product_packed_f64(const ProductPlan& pl, const double2* A, size_t lda, int n, int nr,
-                                     double2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook)
+                                     double2* part, double2* Y, size_t ldy, const StepNorm* sn, hipStream_t s,
+                                     const KernelHook* hook)
 {
-    return product_packed<double2, double2>(pl, A, lda, n, nr, part, Y, ldy, s, hook);
+    return product_packed<double2, double2>(pl, A, lda, n, nr, part, Y, ldy, sn, s, hook);
 }
 
 hipError_t launch_product_packed_f32(const ProductPlan& pl, const float2* A, size_t lda, int n, int nr,
-                                     float2* part, double2* Y, size_t ldy, hipStream_t s, const KernelHook* hook)
+                                     float2* part, double2* Y, size_t ldy, const StepNorm* sn, hipStream_t s,
+                                     const KernelHook* hook)
 {
-    return product_packed<float2, float2>(pl, A, lda, n, nr, part, Y, ldy, s, hook);
+    return product_packed<float2, float2>(pl, A, lda, n, nr, part, Y, ldy, sn, s, hook);
 }
 
 int matvec_splits_valu(int n)
