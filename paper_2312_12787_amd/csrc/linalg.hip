@@ -303,13 +303,23 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b)
 // the update (which form the same S, T, gamma and c themselves).
 constexpr int DC_STEP_BS = 256;  // threads of a step block
 
-// sum over the workgroup in a fixed order: each wave's DPP sum, then waves 0..3
-__device__ __forceinline__ double block_sum4(double v, double* red, int slot)
+// three sums over the workgroup with one barrier, each in a fixed order: the
+// wave's DPP sum, then waves 0..3
+__device__ __forceinline__ void block_sum4x3(double& a, double& b, double& c, double* red)
 {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[slot * 4 + (threadIdx.x >> 6)] = v;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[w] = a;
+        red[4 + w] = b;
+        red[8 + w] = c;
+    }
     __syncthreads();
-    return ((red[slot * 4] + red[slot * 4 + 1]) + red[slot * 4 + 2]) + red[slot * 4 + 3];
+    a = ((red[0] + red[1]) + red[2]) + red[3];
+    b = ((red[4] + red[5]) + red[6]) + red[7];
+    c = ((red[8] + red[9]) + red[10]) + red[11];
 }
 
 // LDS of the step and update blocks (double2 units): five arrays of m + 1
@@ -390,9 +400,7 @@ __device__ __forceinline__ void dc_step(int r, int nr, int j, int m, int ns, con
             sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
         }
     }
-    ss = block_sum4(ss, red, 0);
-    str = block_sum4(str, red, 1);
-    sti = block_sum4(sti, red, 2);
+    block_sum4x3(ss, str, sti, red);
     const double alpha = Sl[j].x;
     const double gamma = brk ? 0.0 : sqrt(fmax(alpha - ss, 0.0));
     int still = 1;
@@ -543,6 +551,14 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
         tl[i] = make_double2(qr, qi);
     }
     const double beta = j >= 1 ? hnorm[r] : 1.0;
+    // this thread's candidate rows, loaded while the coefficients are formed
+    const int q = bx * BS + threadIdx.x;
+    TV* vj = V + ((size_t)j * nr + r) * ldv;
+    double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
+    if (q < n) {
+        v = ld2(vj + q);
+        w = W[(size_t)r * ldw + q];
+    }
     __syncthreads();
     if (!(beta > 0.0)) return;  // the previous step ended the Krylov space
     double ss = 0.0, str = 0.0, sti = 0.0;
@@ -552,20 +568,14 @@ __device__ __forceinline__ void dc_update(int r, int bx, int nu, TV* __restrict_
         str = fma(a.x, t.x, fma(a.y, t.y, str));
         sti = fma(a.x, t.y, fma(-a.y, t.x, sti));
     }
-    ss = block_sum4(ss, red, 0);
-    str = block_sum4(str, red, 1);
-    sti = block_sum4(sti, red, 2);
+    block_sum4x3(ss, str, sti, red);
     const double gamma = sqrt(fmax(sl[j].x - ss, 0.0));
     if (!(gamma > 0.0)) return;
     const double ig = 1.0 / gamma;
     const double2 tau = tl[j];
     const double2 c = make_double2((tau.x - str) * ig, (tau.y - sti) * ig);
     double nn[1] = {0.0};
-    const int q = bx * BS + threadIdx.x;
     if (q < n) {
-        TV* vj = V + ((size_t)j * nr + r) * ldv;
-        double2 v = ld2(vj + q);
-        double2 w = W[(size_t)r * ldw + q];
         for (int i = 0; i < j; ++i) {
             const double2 b = ld2(V + ((size_t)i * nr + r) * ldv + q);
             const double2 a = sl[i], t = tl[i];

@@ -636,6 +636,19 @@ __global__ void k_step_reduce(const ACC* __restrict__ part, int splits, int n, i
     const int r = blockIdx.y;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     const int act = active[r];
+    // this thread's loads first (they do not depend on |w|), then |w|
+    using S = decltype(ACC{}.x);
+    S sr = S(0), si = S(0);
+    double2 w = make_double2(0.0, 0.0);
+    double2* y = Y + (size_t)r * ldy + row;
+    if (row < n) {
+        for (int sp = 0; sp < splits; ++sp) {
+            const ACC v = part[((size_t)sp * nrhs + r) * n + row];
+            sr += v.x;
+            si += v.y;
+        }
+        w = *y;
+    }
     if (threadIdx.x < 64) {
         const double beta = dev::step_beta(nrm + (size_t)r * nu, nu);
         if (threadIdx.x == 0) {
@@ -647,19 +660,8 @@ __global__ void k_step_reduce(const ACC* __restrict__ part, int splits, int n, i
     // every block of a marked column skips it, whether it reads the mark or the zero
     if (blockIdx.x == 0 && threadIdx.x == 0 && act == dev::STOPPING) active[r] = 0;
     if (row >= n) return;
-    using S = decltype(ACC{}.x);
-    S sr = S(0), si = S(0);
-    for (int sp = 0; sp < splits; ++sp) {
-        const ACC v = part[((size_t)sp * nrhs + r) * n + row];
-        sr += v.x;
-        si += v.y;
-    }
-    double2* y = Y + (size_t)r * ldy + row;
     const double inv = inv_s;
-    if (act == 1) {
-        const double2 w = *y;
-        st_basis(V + (size_t)r * ldv + row, make_double2(w.x * inv, w.y * inv));
-    }
+    if (act == 1) st_basis(V + (size_t)r * ldv + row, make_double2(w.x * inv, w.y * inv));
     *y = make_double2((double)sr * inv, (double)si * inv);
 }
 
