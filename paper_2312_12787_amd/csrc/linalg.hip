@@ -277,15 +277,28 @@ __device__ __forceinline__ void dc_dots(int bid, const TV* __restrict__ V, size_
             row(a, w, v, nb);
         }
     }
-    block_sum<NV>(acc, lds);
-    if (threadIdx.x == 0) {
+    // block sums in block_sum's order (each wave's DPP sum, then waves 0..3),
+    // finished by one thread per (real, imaginary) pair so that no thread
+    // holds all of them
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-        for (int b = 0; b < BATCH; ++b) {
-            if (b < nb) {
-                const size_t o = ((size_t)r * ns + chunk) * jc + i0 + b;
-                partP[o] = make_double2(acc[2 * b], acc[2 * b + 1]);
-                if (HASW) partQ[o] = make_double2(acc[2 * BATCH + 2 * b], acc[2 * BATCH + 2 * b + 1]);
-            }
+    for (int k = 0; k < NV; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[wave * NV + k] = acc[k];
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NV / 2) {
+        const int k = 2 * t;
+        const double re = lds[k] + lds[NV + k] + lds[2 * NV + k] + lds[3 * NV + k];
+        const double im = lds[k + 1] + lds[NV + k + 1] + lds[2 * NV + k + 1] + lds[3 * NV + k + 1];
+        const int b = t < BATCH ? t : t - BATCH;  // pairs BATCH.. are the wt projections
+        if (b < nb) {
+            const size_t o = ((size_t)r * ns + chunk) * jc + i0 + b;
+            if (t < BATCH)
+                partP[o] = make_double2(re, im);
+            else
+                partQ[o] = make_double2(re, im);
         }
     }
 }
