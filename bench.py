@@ -541,6 +541,28 @@ def served_record(args, P, torch, n_requests, open_loop=True):
     err = max(ff_err(r32[i], r64[i]) for i in range(len(reqs)))
     err32 = [ff_err(r32[i], ref[i]) for i in sample]
     err64 = [ff_err(r64[i], ref[i]) for i in sample]
+    f32 = None
+    if getattr(args, "serve_f32", False):
+        # the FP32-assembly server (BEM_F32: FP32 matrix, refinement residuals
+        # with it) on the same stream: capacity, footprint and its far-field
+        # error against the FP64 server and against FP64 to 1e-12
+        log("  FP32-assembly server ...")
+        Tf, rf, stf = closed_loop(P.F32, args.serve_tol)
+        ef = [ff_err(rf[i], r64[i]) for i in range(len(reqs))]
+        efr = [ff_err(rf[i], ref[i]) for i in sample]
+        f32 = {"solves_per_s": solves / Tf, "requests_per_s": len(reqs) / Tf,
+               "over_mixed": T32 / Tf, "arena_high_water_GiB": stf["arena_high_water"] / 2**30,
+               "far_field_rel_err_vs_fp64_server": {"max": max(ef), "p50": float(np.median(ef)),
+                                                    "p99": float(np.percentile(ef, 99)),
+                                                    "requests_above_1e-6": int(sum(e > 1e-6 for e in ef))},
+               "vs_fp64_1e-12_sample": {"max": max(efr), "p50": float(np.median(efr)),
+                                        "above_1e-6": int(sum(e > 1e-6 for e in efr))},
+               "failed_requests": [i for i in range(len(reqs)) if rf[i].status != 0],
+               "worst_requests": [{"request": i, "err": ef[i], "N": reqs[i]["spec"].n_elements,
+                                   "k0": float(np.real(reqs[i]["spec"].k[0])),
+                                   "k1": float(np.real(reqs[i]["spec"].k[1])),
+                                   "iters_max_mixed": int(r32[i].iters_max)}
+                                  for i in sorted(range(len(reqs)), key=lambda i: -ef[i])[:8]]}
     lat = []
     if open_loop:
         log("  open loop at the arrival times ...")
@@ -587,6 +609,8 @@ def served_record(args, P, torch, n_requests, open_loop=True):
         "gmres_iterations_max_per_request": {"p50": float(np.median([r32[i].iters_max for i in r32])),
                                              "max": int(max(r32[i].iters_max for i in r32))},
     }
+    if f32:
+        rec["f32_server"] = f32
     if lat:
         rec["latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                              "unit": "open loop at the stream's arrival times: completion - arrival, mixed server"}
@@ -617,6 +641,8 @@ def serve_mode(args, P, torch):
         "roofline": None,
     }
     out.update({k: rec[k] for k in ("capacity", "accuracy", "precision", "gmres_iterations_max_per_request")})
+    if "f32_server" in rec:
+        out["f32_server"] = rec["f32_server"]
     if "latency_ms" in rec:
         out["latency_ms"] = rec["latency_ms"]
     print(json.dumps(out), flush=True)
@@ -947,6 +973,8 @@ def main():
     ap.add_argument("--serve-restart", type=int, default=300,
                     help="serve: GMRES restart length (high-frequency requests need many steps)")
     ap.add_argument("--no-open-loop", action="store_true", help="serve: skip the real-time replay")
+    ap.add_argument("--serve-f32", action="store_true",
+                    help="serve: also run the FP32-assembly server (BEM_F32) on the stream and report its error")
     ap.add_argument("--fuse", type=int, default=1,
                     help="serve: requests a slot admits together and solves as one batch with fused Krylov launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
