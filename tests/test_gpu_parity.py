@@ -218,6 +218,35 @@ def test_kite4096_block_solve_residuals_against_oracle_rows():
     assert rr < 2e-9
 
 
+def test_kite4096_stagnating_solve_stays_accurate():
+    """Full size, asked for 1e-17 (below what FP64 reaches): the Krylov
+    steps run into the rounding floor, where a new vector lies almost inside
+    the basis and gamma = sqrt(alpha - |s|^2) loses its relative accuracy.
+    The solve must end within its budget with BEM_E_NOCONV, finite values,
+    a recomputed residual at the floor (well below 1e-10), and a solution at
+    least as good as the converged solve's on the oracle's sampled rows."""
+    P = _gpu()
+    spec = W.kite(4096, 20.0, 30.0)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    ang = W.equispaced_angles(16)
+    B = g.rhs(ang)
+    X, info = g.solve(B, restart=100, tol=1e-17, max_iter=400)
+    _say("stagnating kite4096: status", info.status, "iters", info.iters.tolist(), "rel", info.rel_residual.tolist())
+    assert info.status == 6 and not info.converged.all()
+    assert bool(torch.isfinite(torch.view_as_real(X)).all())
+    assert (info.iters <= 400).all() and info.rel_residual.max() < 1e-11
+    rows = np.array([3, 1000, 4095, 4096, 5000, 8191, 2222, 7777], dtype=np.int32)
+    po = O.Problem(spec)
+    Ar = po.assemble_rows(rows)
+    Bo = po.rhs(ang)
+    res = Bo[rows] - Ar @ X.cpu().numpy().T
+    rms_b = np.linalg.norm(Bo, axis=0) / np.sqrt(g.n)
+    rr = float(np.max(np.abs(res) / rms_b))
+    _say("stagnating solve: sampled residual / rms(b)", rr)
+    assert rr < 2e-9
+
+
 @pytest.mark.parametrize("tuned", [False, True], ids=["built-in shape", "tuned shape"])
 def test_kite4096_block_product_sampled_rows(tuned):
     """The benchmark's dominant kernel at full size: Y = A X for the 8192 x
