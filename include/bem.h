@@ -207,8 +207,13 @@ bem_status bem_matvec(const bem_problem *p, int nrhs, const void *X_dev, size_t 
 bem_status bem_matvec_noalloc(const bem_problem *p, int nrhs, const void *X_dev, size_t ldx, void *Y_dev,
                               size_t ldy, hipStream_t stream);
 
+/* Largest GMRES restart length: a cycle's Hessenberg column, rotations and
+ * projection sums of one right-hand side live in one workgroup's LDS
+ * (5 (m + 1) complex128 values plus 4.4 KB, at most 160 KB on gfx950).    */
+#define BEM_MAX_RESTART 1990
+
 typedef struct {
-    int restart;        /* GMRES restart length m (>= 1)                                  */
+    int restart;        /* GMRES restart length m, 1..BEM_MAX_RESTART                    */
     int max_iter;       /* cap on matrix-vector products per right-hand side            */
     double tol;         /* stop when ||b - A x|| <= tol ||b|| (true residual, FP64)      */
     double inner_tol;   /* BEM_F32 / BEM_MIXED only: relative tolerance of each inner solve;

@@ -226,7 +226,7 @@ WorkLayout make_work(int n, int nr, int m)
     W.upd_part = take((size_t)nr * W.anblk * sizeof(double));
     W.thr = take((size_t)nr * sizeof(double));
     W.iters = take((size_t)nr * sizeof(int));
-    W.y = take((size_t)nr * 1024 * sizeof(double2));
+    W.y = take((size_t)nr * (m + 1) * sizeof(double2));
     W.H = take((size_t)nr * (m + 1) * m * sizeof(double2));
     W.Hraw = take((size_t)nr * (m + 1) * m * sizeof(double2));
     W.cs = take((size_t)nr * m * sizeof(double2));
@@ -572,7 +572,8 @@ bem_status bem_sizes(const bem_problem* p, int prec, int nrhs, int restart, size
     if (prec != BEM_F64 && prec != BEM_F32 && prec != BEM_MIXED)
         return fail(BEM_E_ARG, "prec must be BEM_F64, BEM_F32 or BEM_MIXED");
     if (nrhs < 1) return fail(BEM_E_ARG, "nrhs must be >= 1");
-    if (restart < 1 || restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
+    if (restart < 1 || restart > BEM_MAX_RESTART)
+        return fail(BEM_E_ARG, "restart must be in [1, " + std::to_string(BEM_MAX_RESTART) + "]");
     const size_t n = 2 * (size_t)p->N;
     if (geom_bytes) *geom_bytes = p->L.total;
     if (matrix_bytes) *matrix_bytes = bemk::matrix_bytes_ld(prec, n, n);
@@ -1189,10 +1190,11 @@ bem_status gmres_cycle_end(GmItem& g)
     HIP_OK(bemk::launch_backsolve(nr, m, c.at<double2>(c.W.H), c.at<double2>(c.W.gvec), c.at<int>(c.W.kdim),
                                   c.at<double2>(c.W.y), c.s));
     if (c.v32())
-        HIP_OK(bemk::launch_xupdate(c.V32(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx,
+        HIP_OK(bemk::launch_xupdate(c.V32(0), ldv, nr, n, m, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx,
                                     c.s));
     else
-        HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx, c.s));
+        HIP_OK(bemk::launch_xupdate(c.V(0), ldv, nr, n, m, c.at<double2>(c.W.y), c.at<int>(c.W.kdim), g.X, g.ldx,
+                                    c.s));
     // FP64 accumulation also inside the refinement: with FP32 products the
     // rounding of the restart residual (about 1e-7 kappa ||b||) can exceed
     // the inner tolerance of an ill-conditioned problem, which then never
@@ -1356,7 +1358,8 @@ bem_status bem_solve_batch(int np, bem_problem* const* ps, const int* nrhs_v, co
     if (np < 1 || np > bemk::MAX_FUSED) return fail(BEM_E_ARG, "np must be in [1, 8]");
     if (!ps || !nrhs_v || !B_dev || !ldb_v || !opts || !X_dev || !ldx_v || !work_dev || !work_bytes || !info)
         return fail(BEM_E_ARG, "bad solve arguments");
-    if (opts->restart < 1 || opts->restart > 1000) return fail(BEM_E_ARG, "restart must be in [1, 1000]");
+    if (opts->restart < 1 || opts->restart > BEM_MAX_RESTART)
+        return fail(BEM_E_ARG, "restart must be in [1, " + std::to_string(BEM_MAX_RESTART) + "]");
     if (!(opts->tol > 0.0) || opts->max_iter < 1) return fail(BEM_E_ARG, "tol must be > 0 and max_iter >= 1");
     if (opts->graph_steps < 0 || opts->graph_steps > bemk::GRAPH_MAX_STEPS)
         return fail(BEM_E_ARG, "graph_steps must be in [0, " + std::to_string(bemk::GRAPH_MAX_STEPS) + "]");

@@ -191,9 +191,10 @@ hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const
                               hipStream_t s);
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
                             hipStream_t s);
-hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+// y: [nr][m + 1] (the back-solve's output)
+hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, int m, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s);
-hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, int m, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s);
 hipError_t launch_axpby_res(const double2* B, size_t ldb, const double2* AX, size_t ldax, int n, int nr,
                             double2* R, size_t ldr, hipStream_t s);

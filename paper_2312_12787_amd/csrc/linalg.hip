@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "bem.h"
 #include "internal.h"
 #include "krylov_dev.h"
 #include "launch.h"
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
                                                        const double2* __restrict__ gvec,
                                                        const int* __restrict__ kdim, double2* __restrict__ y)
 {
-    __shared__ double2 g[1024];
+    extern __shared__ double2 g[];  // m entries
     __shared__ double2 yi_s;
     const int r = blockIdx.x;
     const int k = kdim[r];
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(64) void k_backsolve_wave(int nr, int m, const doub
             const double2 yi = den > 0.0 ? make_double2((v.x * d.x + v.y * d.y) / den, (v.y * d.x - v.x * d.y) / den)
                                          : make_double2(0.0, 0.0);
             yi_s = yi;
-            y[(size_t)r * 1024 + i] = yi;
+            y[(size_t)r * (m + 1) + i] = yi;
         }
         __syncthreads();
         const double2 yi = yi_s;
@@ -338,6 +339,8 @@ __device__ __forceinline__ void block_sum4x3(double& a, double& b, double& c, do
 // LDS of the step and update blocks (double2 units): five arrays of m + 1
 // entries, the wave partials zp[4][64], then reduction slots and a flag.
 __host__ __device__ constexpr size_t arn_lds_elems(int m) { return 5 * ((size_t)m + 1) + 4 * 64 + 16; }
+static_assert(arn_lds_elems(BEM_MAX_RESTART) * sizeof(double2) <= 160 * 1024,
+              "a step block of the longest restart fits the 160 KiB of LDS a gfx950 workgroup can hold");
 
 // A column that stops at step j of a cycle (convergence, spent budget, end of
 // the Krylov space) is marked STOPPING in `active` while the update blocks of
@@ -674,7 +677,7 @@ __global__ void k_start_cycle(const double2* __restrict__ R, size_t ldr, int n, 
 
 
 template <class TV>
-__global__ void k_xupdate(const TV* __restrict__ V, size_t ldv, int nr, int n, const double2* __restrict__ y,
+__global__ void k_xupdate(const TV* __restrict__ V, size_t ldv, int nr, int n, int m, const double2* __restrict__ y,
                           const int* __restrict__ kdim, double2* __restrict__ X, size_t ldx)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -683,7 +686,7 @@ __global__ void k_xupdate(const TV* __restrict__ V, size_t ldv, int nr, int n, c
     const int k = kdim[r];
     if (k == 0) return;
     double2 x = X[(size_t)r * ldx + q];
-    const double2* yr = y + (size_t)r * 1024;
+    const double2* yr = y + (size_t)r * (m + 1);
     for (int i = 0; i < k; ++i) {
         const double2 c = yr[i];
         const double2 v = ld2(V + ((size_t)i * nr + r) * ldv + q);
@@ -1041,22 +1044,23 @@ hipError_t launch_start_cycle(const double2* R, size_t ldr, int n, int nr, const
 hipError_t launch_backsolve(int nr, int m, const double2* H, const double2* gvec, const int* kdim, double2* y,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_backsolve_wave, dim3(nr), dim3(64), 0, s, nr, m, H, gvec, kdim, y);
+    hipLaunchKernelGGL(k_backsolve_wave, dim3(nr), dim3(64), (size_t)m * sizeof(double2), s, nr, m, H, gvec, kdim,
+                       y);
     return hipGetLastError();
 }
 
-hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+hipError_t launch_xupdate(const double2* V, size_t ldv, int nr, int n, int m, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_xupdate<double2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, y, kdim, X,
+    hipLaunchKernelGGL((k_xupdate<double2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, m, y, kdim, X,
                        ldx);
     return hipGetLastError();
 }
 
-hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, const double2* y, const int* kdim,
+hipError_t launch_xupdate(const float2* V, size_t ldv, int nr, int n, int m, const double2* y, const int* kdim,
                           double2* X, size_t ldx, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_xupdate<float2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, y, kdim, X,
+    hipLaunchKernelGGL((k_xupdate<float2>), dim3((n + BS - 1) / BS, nr), dim3(BS), 0, s, V, ldv, nr, n, m, y, kdim, X,
                        ldx);
     return hipGetLastError();
 }

@@ -22,8 +22,8 @@ Single material: conventional (eq. (naive_bie)), Calderon beta = 1
 materials: conventional (eq. (3dom_conv_bie)), original (eq.
 (3dom_calderon_bie0)) and modified (eq. (3dom_calderon_bie)).  GMRES from
 x0 = 0 to a relative residual of 1e-8, incident angle 0, without restart up to
-1000 Krylov vectors (the library's largest restart length; a longer run
-restarts), at most 5000 steps (more: reported as None), FP64.
+1990 Krylov vectors (the library's largest restart length, BEM_MAX_RESTART; a
+longer run restarts), at most 5000 steps (more: reported as None), FP64.
 
 Usage: python sweeps.py [--exp NAME ...] [--quick]   (one JSON line per experiment)
 """
@@ -49,7 +49,7 @@ def iterations(spec, tol=1e-8, max_iter=5000):
     g = P.Problem(spec)
     g.assemble(P.F64)
     B = g.rhs([0.0])
-    X, info = g.solve(B, restart=min(g.n, 1000), tol=tol, max_iter=max_iter)
+    X, info = g.solve(B, restart=min(g.n, P.MAX_RESTART), tol=tol, max_iter=max_iter)
     return int(info.iters[0]), bool(info.converged[0])
 
 

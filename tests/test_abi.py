@@ -113,8 +113,12 @@ def test_sizes_and_order():
     assert _problem(spec).N == 22
     with pytest.raises(P.BemError, match="BEM_E_ARG"):
         g.sizes(P.F64, 0, 20)
+    # restart lengths up to BEM_MAX_RESTART (the step block's LDS holds a cycle)
+    assert P.MAX_RESTART == int(re.search(r"#define BEM_MAX_RESTART (\d+)",
+                                          open(os.path.join(ROOT, "include", "bem.h")).read()).group(1))
+    assert g.sizes(P.F64, 1, P.MAX_RESTART)[2] > g.sizes(P.F64, 1, 1000)[2]
     with pytest.raises(P.BemError, match="BEM_E_ARG"):
-        g.sizes(P.F64, 1, 1001)
+        g.sizes(P.F64, 1, P.MAX_RESTART + 1)
 
 
 def test_call_order_errors_before_any_device_work():

@@ -247,6 +247,30 @@ def test_kite4096_stagnating_solve_stays_accurate():
     assert rr < 2e-9
 
 
+def test_long_unrestarted_cycle_matches_oracle_rows():
+    """GMRES without restart beyond 1000 Krylov vectors (restart
+    BEM_MAX_RESTART: the step block's LDS near its limit) on the paper's
+    junction example in the conventional Burton-Miller form (disk split by a
+    diameter, 800 elements, omega = 1, eps = 1, 2, 3; Sec. 7.2), which
+    restarted at 1000 vectors takes 1988 steps: one cycle of more than 1000
+    steps reaches 1e-8, and the residual on the oracle's own matrix agrees."""
+    P = _gpu()
+    spec = W.split_disk(800, [1.0, np.sqrt(2.0), np.sqrt(3.0)], form=W.CONVENTIONAL)
+    g = P.Problem(spec)
+    g.assemble(P.F64)
+    B = g.rhs([0.0])
+    X, info = g.solve(B, restart=P.MAX_RESTART, tol=1e-8, max_iter=5000)
+    _say("split disk, conventional, unrestarted: iters", info.iters.tolist(), "restarts", info.restarts.tolist(),
+         "rel", info.rel_residual.tolist())
+    assert info.converged.all() and int(info.restarts[0]) == 0 and 1000 < int(info.iters[0]) < P.MAX_RESTART
+    po = O.Problem(spec)
+    Ao = po.assemble()
+    bo = po.rhs([0.0])[:, 0]
+    res = np.linalg.norm(bo - Ao @ X[0].cpu().numpy()) / np.linalg.norm(bo)
+    _say("residual on the oracle's matrix", res)
+    assert res < 2e-8
+
+
 @pytest.mark.parametrize("tuned", [False, True], ids=["built-in shape", "tuned shape"])
 def test_kite4096_block_product_sampled_rows(tuned):
     """The benchmark's dominant kernel at full size: Y = A X for the 8192 x

@@ -10,7 +10,7 @@ the qualitative claims the paper draws from its figures.
   and both stay flat in N; the conventional one grows (Sec. 7.2).
 * Disk split by a diameter (two triple points): modified < original <
   conventional (Sec. 7.2).
-GMRES without restart up to 1000 vectors, tolerance 1e-8, angle 0 (Sec. 7);
+GMRES without restart up to 1990 vectors, tolerance 1e-8, angle 0 (Sec. 7);
 a solve that has not converged after 5000 steps counts as unbounded.
 """
 import math
