@@ -331,7 +331,8 @@ bem_status bem_profile_read(bem_problem *p, bem_profile *out, int reset);
  * column splits, complex-product form -- with the problem's assembled matrix
  * and nrhs right-hand sides (the FP64 matrix for BEM_F64; the FP32 matrix,
  * or the FP32 copy of BEM_MIXED, with FP64 vectors otherwise), `reps` timed
- * products each after one untimed, and installs the fastest for its shape
+ * products each after one untimed (the four fastest twice more, each keeping
+ * its best time), and installs the fastest for its shape
  * class: (matrix and accumulation precision, right-hand-side groups of 16 up
  * to 64 or the vector kernel's up to 4, ceil(log2 n)) in the process's table.
  * A problem resolves the shapes of all its products when bem_assemble runs

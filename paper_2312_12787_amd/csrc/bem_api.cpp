@@ -805,24 +805,40 @@ bem_status bem_tune(const bem_problem* p, int nrhs, const void* X_dev, size_t ld
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    double best = 1e300, def = 0.0;
-    bemk::MvShape bestc = cand.front();
-    for (size_t c = 0; c < cand.size() && err == hipSuccess; ++c) {
-        bemk::force_shape(&cand[c]);
-        err = product();
-        if (err == hipSuccess) err = hipEventRecord(e0, stream);
-        for (int r = 0; r < reps && err == hipSuccess; ++r) err = product();
-        if (err == hipSuccess) err = hipEventRecord(e1, stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
+    // average of `reps` products after one untimed, per candidate
+    auto timed = [&](const bemk::MvShape& sh, double& avg) -> hipError_t {
+        bemk::force_shape(&sh);
+        hipError_t e = product();
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = product();
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        const double avg = (double)ms / reps;
-        if (c == 0) def = avg;  // the built-in shape is the first candidate
-        if (err == hipSuccess && avg < best) {
-            best = avg;
-            bestc = cand[c];
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        avg = (double)ms / reps;
+        return e;
+    };
+    std::vector<double> t(cand.size(), 1e300);
+    for (size_t c = 0; c < cand.size() && err == hipSuccess; ++c) err = timed(cand[c], t[c]);
+    const double def = t[0];  // the built-in shape is the first candidate
+    // the fastest few again, twice each in turn, keeping each one's best
+    // time: candidates within timing noise of each other are then ranked on
+    // more than one short sample
+    std::vector<size_t> order(cand.size());
+    for (size_t c = 0; c < order.size(); ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return t[a] < t[b]; });
+    const size_t top = std::min<size_t>(4, order.size());
+    for (int pass = 0; pass < 2 && err == hipSuccess; ++pass)
+        for (size_t k = 0; k < top && err == hipSuccess; ++k) {
+            double again = 0.0;
+            err = timed(cand[order[k]], again);
+            t[order[k]] = std::min(t[order[k]], again);
         }
-    }
+    size_t bi = 0;
+    for (size_t c = 1; c < cand.size(); ++c)
+        if (t[c] < t[bi]) bi = c;
+    const double best = t[bi];
+    const bemk::MvShape bestc = cand[bi];
     bemk::force_shape(nullptr);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
