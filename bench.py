@@ -890,8 +890,9 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
                               f"over A)", "bound": "mfma", "achieved": mv_tfs, "peak": FP32_MFMA_PEAK_TFS,
                     "unit": "TFLOP/s", "frac": mv_tfs / FP32_MFMA_PEAK_TFS,
                     "mfma_busy_frac": mv_tfs / FP32_MFMA_PEAK_TFS * (0.75 if g3 else 1.0),
-                    "note": "achieved counts 8 flops per complex multiply-add; the 3-product form runs 6 of them "
-                            "on the matrix cores (mfma_busy_frac)" if g3 else "4-product form",
+                    "note": "achieved counts 8 flops per complex multiply-add (the algorithmic count, so frac "
+                            "can reach 1.33); the 3-product form runs 6 of them on the matrix cores, and "
+                            "mfma_busy_frac is the matrix cores' share of their peak" if g3 else "4-product form",
                     "traffic": traffic_record(wl.name)}
     else:
         roofline = {"kernel": f"k_matvec_mfma (FP64 MFMA split-K block product, {nr} right-hand sides)"

@@ -244,7 +244,8 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
     // loads per step) walk the columns software-pipelined: the loads of the
     // next 4U columns are issued before the products of the current ones, so
     // a wave keeps its reads in flight while its matrix-core work runs.  The
-    // wider shapes are matrix-core bound and would spill the second buffer.
+    // wider shapes, matrix-core bound, would spill a second buffer; they
+    // rotate their slots instead (below).
     constexpr bool PIPE = NG == 1 && RT * U <= 16;
     auto load = [&](TA (&a)[U][RT], V2 (&x)[U][NG], int cc) {
 #pragma unroll
@@ -275,31 +276,47 @@ __global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, si
     };
     int c = c0;
     if constexpr (!PIPE) {
-        for (; c + 4 * U <= c1; c += 4 * U) {
+        // rotating slots: slot u of the next 4U columns is loaded as soon as
+        // slot u of the current ones has gone into the matrix cores, so a
+        // wave keeps loads in flight without a second buffer; the scheduling
+        // barriers keep that order (the compiler otherwise moves the loads
+        // next to their uses and waits for all of them).  Measured on gfx950,
+        // kite of 16384 elements, 64 right-hand sides: FP32 product 3.82 ->
+        // 3.50 ms, three waves per SIMD instead of two
+        if (c + 4 * U <= c1) {
             TA a[U][RT];
             V2 x[U][NG];
+            load(a, x, c);
+            for (;;) {
+                const int cn = c + 4 * U;
+                const bool more = cn + 4 * U <= c1;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int col = c + 4 * u + lk;
+                for (int u = 0; u < U; ++u) {
+                    T ar[RT], ai[RT], xr[NG], xi[NG];
 #pragma unroll
-                for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
+                    for (int t = 0; t < RT; ++t) {
+                        ar[t] = rok[t] ? (T)a[u][t].x : T(0);
+                        ai[t] = rok[t] ? (T)a[u][t].y : T(0);
+                    }
 #pragma unroll
-                for (int t = 0; t < RT; ++t) a[u][t] = ld_stream(ap[t] + (size_t)col * lda);
-            }
+                    for (int g = 0; g < NG; ++g) {
+                        xr[g] = x[u][g].x;
+                        xi[g] = x[u][g].y;
+                    }
+                    step(ar, ai, xr, xi);
+                    __builtin_amdgcn_sched_barrier(0);
+                    // unconditional (the last pass reloads its own columns):
+                    // a load under a branch makes the compiler wait for every
+                    // load in flight before the next slot
+                    const int col = (more ? cn : c) + 4 * u + lk;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                T ar[RT], ai[RT], xr[NG], xi[NG];
+                    for (int g = 0; g < NG; ++g) x[u][g] = XT[(size_t)col * XW + 16 * g + lr];
 #pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    ar[t] = rok[t] ? (T)a[u][t].x : T(0);
-                    ai[t] = rok[t] ? (T)a[u][t].y : T(0);
+                    for (int t = 0; t < RT; ++t) a[u][t] = ld_stream(ap[t] + (size_t)col * lda);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    xr[g] = x[u][g].x;
-                    xi[g] = x[u][g].y;
-                }
-                step(ar, ai, xr, xi);
+                c = cn;
+                if (!more) break;
             }
         }
     } else if (c + 4 * U <= c1) {
