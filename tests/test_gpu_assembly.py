@@ -9,7 +9,8 @@ launch wrote would show; each is compared with the oracle's matrix
 a MIXED assembly is the FP64 matrix rounded to FP32, bit for bit.  Cases:
 every element near (small k), almost every element far (large k), a
 non-convex curve (the kite's concave side comes back within the radius),
-graded junction meshes with elements down to h/16 (three sectors), and the
+Gauss rules of 8, 10 and 5 points (the kernels built for 8 and 10 points and
+the general one), graded junction meshes with elements down to h/16 (three sectors), and the
 disk split by a diameter.
 """
 import numpy as np
@@ -26,6 +27,7 @@ CASES = [
     ("disk300_k50-80_mostly_far", lambda: W.disk(300, 50.0, 80.0 + 1.0j)),
     ("kite700_k20-30", lambda: W.kite(700, 20.0, 30.0)),
     ("kite500_k12-18+0.5i_q10", lambda: W.kite(500, 12.0, 18.0 + 0.5j, quad=10)),
+    ("kite300_k8-12+0.3i_q5", lambda: W.kite(300, 8.0, 12.0 + 0.3j, quad=5)),
     ("sectors_graded_h1/40", lambda: W.sectors([10.0, 12.0, 18.0, 9.0 + 0.5j], h=1.0 / 40)),
     ("split_disk400", lambda: W.split_disk(400, [6.0, 6.0 * np.sqrt(2.0), 6.0 * np.sqrt(3.0)])),
 ]
