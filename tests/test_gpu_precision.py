@@ -129,6 +129,44 @@ def test_precision_path_full_size_kite16384(k1):
     assert (np.abs(res) / scale).max() < 1e-9
 
 
+def test_precision_product_full_size_kite16384_sampled_rows():
+    """The precision workload's dominant kernel at full size and in the launch
+    shape the benchmark times (autotuned for 64 right-hand sides): Y = A32 X
+    for the 32768 x 32768 FP32 kite matrix.  On eight sampled rows (first /
+    last / ragged row tiles of both equation blocks):
+    * the GPU's FP32 entries against the oracle's FP64 rows, within 1e-6 of
+      the largest entry (the assembly test's FP32 bar, here at full size);
+    * Y against the same FP32 rows times X in FP64, which isolates the
+      product: each row is a sum of n products accumulated in FP32, whose
+      rounding errors of either sign add up to about sqrt(n) u |A_i| |X|
+      (u = 2^-24); the bar is four times that, for the three-product form's
+      extra sums."""
+    P = _gpu()
+    P.tune_reset()
+    try:
+        spec = W.kite(16384, 20.0, 30.0)
+        g = P.Problem(spec)
+        A32 = g.assemble(P.F32)
+        rng = np.random.default_rng(5)
+        X = (rng.standard_normal((g.n, 64)) + 1j * rng.standard_normal((g.n, 64))).astype(np.complex64)
+        Xt = torch.as_tensor(X.T.copy(), device="cuda")
+        print("tuned", g.tune(64, reps=2, X=Xt.to(torch.complex128)), flush=True)
+        A32 = g.assemble(P.F32, out=A32)  # a problem takes the launch shapes in force at its assembly
+        Y = g.matvec(Xt).cpu().numpy().T
+        rows = np.array([0, 255, 256, 16383, 16384, 20000, 32511, 32767], dtype=np.int32)
+        Ag = A32[:, torch.as_tensor(rows, device=A32.device).long()].T.cpu().numpy().astype(np.complex128)
+        Ao = O.Problem(spec).assemble_rows(rows)
+        e_entries = np.abs(Ag - Ao).max() / np.abs(Ao).max()
+        X64 = X.astype(np.complex128)
+        scale = np.abs(Ag) @ np.abs(X64)            # |A_i| |X| per sampled row and right-hand side
+        e_prod = (np.abs(Y[rows] - Ag @ X64) / scale).max()
+        bar = 4.0 * np.sqrt(g.n) * 2.0 ** -24
+        print("kite16384 FP32: entries vs oracle", e_entries, "product / (|A||X|)", e_prod, "bar", bar, flush=True)
+        assert e_entries < 1e-6 and e_prod < bar
+    finally:
+        P.tune_reset()
+
+
 def test_mixed_matrix_is_the_fp64_matrix_and_its_rounding():
     """BEM_MIXED writes the FP64 matrix (bit-identical to BEM_F64) and its
     entries rounded to FP32 (bit-identical to rounding the FP64 matrix) in one
