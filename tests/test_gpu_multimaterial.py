@@ -91,6 +91,40 @@ def test_sectors_full_size_solve_residual_on_oracle_rows():
     assert rr < 2e-9
 
 
+def test_sectors_full_size_product_sampled_rows():
+    """The multi-material workload's dominant kernel at full size, in the
+    launch shape the benchmark times (autotuned for one right-hand side): the
+    vector product y = A x over the 14970 x 14970 complex128 matrix.  On
+    eight sampled rows (both ends of each interface's row range, junction
+    neighbourhoods): the GPU's entries against the oracle's rows within 1e-14
+    of the largest entry (only rounding separates two evaluations of the same
+    definition), and y against the same GPU rows times x, within four times
+    sqrt(n) u |A_i| |x| (u = 2^-53), the size of n rounding errors of either
+    sign in an FP64 sum."""
+    P = _gpu()
+    P.tune_reset()
+    try:
+        spec = W.sectors(K)
+        g = P.Problem(spec)
+        A_t = g.assemble(P.F64)
+        rng = np.random.default_rng(17)
+        x = rng.standard_normal((g.n, 1)) + 1j * rng.standard_normal((g.n, 1))
+        xt = torch.as_tensor(x.T.copy(), device="cuda")
+        print("tuned", g.tune(1, reps=2, X=xt), flush=True)
+        A_t = g.assemble(P.F64, out=A_t)  # a problem takes the launch shapes in force at its assembly
+        y = g.matvec(xt).cpu().numpy().T
+        rows = np.array([0, 1700, 5000, 7484, 7485, 9000, 12000, 14969], dtype=np.int32)
+        Ag = A_t[:, torch.as_tensor(rows, device=A_t.device).long()].T.cpu().numpy()
+        Ao = O.Problem(spec).assemble_rows(rows)
+        e_entries = np.abs(Ag - Ao).max() / np.abs(Ao).max()
+        e_prod = (np.abs(y[rows] - Ag @ x) / (np.abs(Ag) @ np.abs(x))).max()
+        bar = 4.0 * np.sqrt(g.n) * 2.0 ** -53
+        print("sectors product: entries vs oracle", e_entries, "product / (|A||x|)", e_prod, "bar", bar, flush=True)
+        assert e_entries < 1e-14 and e_prod < bar
+    finally:
+        P.tune_reset()
+
+
 def test_sectors_far_field_error_by_refinement():
     """The multi-material workload's far-field error: the full-size solution
     (h = 1/800, 7485 graded elements) against one on the mesh refined to
