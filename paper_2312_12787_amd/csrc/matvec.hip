@@ -195,8 +195,21 @@ struct Mfma<float> {
 // P3 = (Ar + Ai)(Xr + Xi); Yr = P1 - P2, Yi = P3 - P1 - P2) instead of four;
 // NG: groups of 16 right-hand sides taken in the same pass over A (X packed
 // XT[c * 16 NG + r]), so that one read of A serves up to 64 right-hand sides.
+// The wide shapes, which are matrix-core bound, carry an occupancy target:
+// left alone the compiler puts their accumulators in AGPRs beside the load
+// slots and runs one or two waves per SIMD; with the target they fit in the
+// VGPRs without spilling (FP32 sums with 64 right-hand sides: three waves,
+// 3.49 -> 3.45 ms per kite16384 product; FP64 sums over two to four groups,
+// where RT * NG <= 4 keeps them spill-free: two waves, the kite16384 FP64
+// path 73.7 -> 84.4 solves/s).  The single-group shapes keep the compiler's
+// own allocation (the HBM-bound 16-RHS product pipelines its loads instead).
+constexpr int mfma_min_waves(int tbytes, int rt, int ng)
+{
+    return (tbytes == 4 && ng >= 4) ? 3 : (tbytes == 8 && ng >= 2 && rt * ng <= 4) ? 2 : 1;
+}
+
 template <class TA, class T, int RT, int U, bool G3, int NG>
-__global__ __launch_bounds__(BS) void k_matvec_mfma(const TA* __restrict__ A, size_t lda, int n,
+__global__ __launch_bounds__(BS, mfma_min_waves(sizeof(T), RT, NG)) void k_matvec_mfma(const TA* __restrict__ A, size_t lda, int n,
                                                     const typename Mfma<T>::v2* __restrict__ XT, int nrhs,
                                                     typename Mfma<T>::v2* __restrict__ part, int cps)
 {
