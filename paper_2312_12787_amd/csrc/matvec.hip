@@ -295,7 +295,7 @@ __global__ __launch_bounds__(BS, mfma_min_waves(sizeof(T), RT, NG)) void k_matve
         // barriers keep that order (the compiler otherwise moves the loads
         // next to their uses and waits for all of them).  Measured on gfx950,
         // kite of 16384 elements, 64 right-hand sides: FP32 product 3.82 ->
-        // 3.50 ms, three waves per SIMD instead of two
+        // 3.50 ms at the same register count (two waves per SIMD)
         if (c + 4 * U <= c1) {
             TA a[U][RT];
             V2 x[U][NG];
