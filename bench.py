@@ -824,6 +824,32 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
         if errs:
             raise errs[0]
 
+    def run_steps(k, record):
+        """k steps.  With --case-pipeline the concurrent cases each run their
+        k steps back to back on their own stream and host thread, without a
+        barrier between steps, so that one case's assembly can run beside the
+        other case's solve; otherwise both cases start every step together."""
+        if not (mode["concurrent"] and args.case_pipeline):
+            for _ in range(k):
+                step(record)
+            return
+        import threading
+        errs = []
+
+        def body(ci):
+            try:
+                for _ in range(k):
+                    run_case(ci, record, time.perf_counter())
+            except BaseException as e:  # re-raised on the main thread
+                errs.append(e)
+        th = [threading.Thread(target=body, args=(ci,)) for ci in range(len(probs))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if errs:
+            raise errs[0]
+
     for _ in range(warmup):
         step(False)
     tuning = None
@@ -841,8 +867,7 @@ def run_workload(args, wl, P, torch, steps, warmup, tune=True, graph_steps=0):
     torch.cuda.synchronize()
     w0 = time.monotonic_ns()  # the clock of rocprofv3's timestamps: lets a trace pick out the timed launches
     t0 = time.perf_counter()
-    for _ in range(steps):
-        step(True)
+    run_steps(steps, True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     windows = {"timed": [w0, time.monotonic_ns()]}
@@ -984,6 +1009,9 @@ def main():
     ap.add_argument("--sequential-cases", action="store_true",
                     help="run a workload's cases one after another on one stream (default: concurrently, one "
                          "stream and host thread per case)")
+    ap.add_argument("--case-pipeline", action="store_true",
+                    help="concurrent cases run their timed steps back to back, each on its own, instead of "
+                         "starting every step together")
     ap.add_argument("--serve-prefix", type=int, default=200,
                     help="requests of the stream in the default run's served record")
     ap.add_argument("--graph-steps", type=int, default=0,
