@@ -10,7 +10,9 @@ residual of 1e-10, far field at 360 directions; everything in FP64.
 One step = both cases, each: derive the geometry tables on the device,
 assemble the matrix, build the 16 right-hand sides, solve, evaluate the far
 field; the two cases run concurrently, each on its own stream driven by its
-own host thread (--sequential-cases: one after the other).  The inputs (node
+own host thread, and start every step together (--sequential-cases: one
+after the other; --case-pipeline: each case runs its steps back to back
+without that barrier).  The inputs (node
 coordinates) are uploaded once before the timed region.  value = solved
 right-hand sides per second over the K timed steps.
 
